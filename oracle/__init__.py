@@ -56,6 +56,7 @@ class Stats(ct.Structure):
                 ("level_vertices", ct.c_int64 * MAXP),
                 ("level_entries", ct.c_int64 * MAXP),
                 ("communities", ct.c_int64 * MAXP),
+                ("refined_vertices", ct.c_int64 * MAXP),
                 ("affected", ct.c_int64),
                 ("changed", ct.c_int64),
                 ("moves_pass0", ct.c_int64)]
@@ -67,6 +68,7 @@ class Stats(ct.Structure):
                 "level_vertices": list(self.level_vertices[:p]),
                 "level_entries": list(self.level_entries[:p]),
                 "communities": list(self.communities[:p]),
+                "refined_vertices": list(self.refined_vertices[:p]),
                 "affected": self.affected, "changed": self.changed,
                 "moves_pass0": self.moves_pass0}
 
@@ -100,6 +102,10 @@ def _load():
         lib.or_update.argtypes = [i32, i64, P, P, P, i64, P, P, P, i64, P, P, P, P, P, P, P, P, P, P, P, P]
         lib.or_best_move.argtypes = [i64, P, P, P, P, P, P, dbl, i32, P]
         lib.or_best_move.restype = i32
+        lib.or_move_phase.argtypes = [i64, P, P, P, P, P, P, P, P, P, i32, dbl, dbl, i32, i32, P, P]
+        lib.or_move_phase.restype = i32
+        lib.or_subset_renumber.argtypes = [i64, P, P, P]
+        lib.or_subset_renumber.restype = None
         _lib = lib
     return _lib
 
@@ -288,3 +294,27 @@ def best_move(g: Graph, C, K, Sig, M2: float, i: int):
     c = lib.or_best_move(g.n, _p(g.off), _p(g.idx), _p(g.w), _p(C), _p(K), _p(Sig), float(M2),
                          int(i), _p(gout))
     return int(c), float(gout[0])
+
+
+def move_phase(g: Graph, C, K, Sig, M2: float, dC, U, rng, track: bool, tau: float = 0.01,
+               max_iter: int = 20, sync: bool = False):
+    """One local-moving phase (Alg. leidenMove); returns (iterations, C, Sig, dC, U, moves,
+    total gain in units of 2m^2)."""
+    lib = _load()
+    C = _c(C, np.int32).copy(); Sig = _c(Sig, np.float64).copy()
+    dC = _c(dC, np.uint8).copy(); U = _c(U, np.uint8).copy()
+    K = _c(K, np.float64); rng = _c(rng, np.uint8)
+    nm = np.zeros(1, np.int64)
+    gain = np.zeros(1, np.float64)
+    l = lib.or_move_phase(g.n, _p(g.off), _p(g.idx), _p(g.w), _p(C), _p(K), _p(Sig), _p(dC), _p(U),
+                          _p(rng), 1 if track else 0, float(M2), float(tau), int(max_iter),
+                          1 if sync else 0, _p(nm), _p(gain))
+    return int(l), C, Sig, dC, U, int(nm[0]), float(gain[0])
+
+
+def subset_renumber(C, Sig, dC):
+    """Alg. leidenSubsetRenumber (representative = smallest member id)."""
+    lib = _load()
+    C = _c(C, np.int32).copy(); Sig = _c(Sig, np.float64).copy(); dC = _c(dC, np.uint8).copy()
+    lib.or_subset_renumber(len(C), _p(C), _p(Sig), _p(dC))
+    return C, Sig, dC

@@ -58,6 +58,7 @@ typedef struct {
   int64_t level_vertices[OR_MAXP];
   int64_t level_entries[OR_MAXP];
   int64_t communities[OR_MAXP];
+  int64_t refined_vertices[OR_MAXP]; /* vertices whose bound is flagged changed at refinement */
   int64_t affected;      /* |{i : deltaV[i]}| at the start */
   int64_t changed;       /* |{c : deltaC'[c]}| after the first local-moving phase */
   int64_t moves_pass0;   /* vertex moves in the first local-moving phase */
@@ -172,7 +173,8 @@ static void lgraph_free(lgraph *g) {
 /* ------------------------------------------------------------------------ */
 static int32_t move_async(const lgraph *G, int32_t *C, const double *K, double *Sig,
                           uint8_t *dC, uint8_t *U, const uint8_t *rng, int track,
-                          double M2, double Tp, int32_t max_iter, dtab *H, int64_t *nmoves) {
+                          double M2, double Tp, int32_t max_iter, dtab *H, int64_t *nmoves,
+                          double *gtot) {
   int32_t l = 0;
   for (int32_t it = 0; it < max_iter; it++) {
     double gsum = 0.0;
@@ -194,6 +196,7 @@ static int32_t move_async(const lgraph *G, int32_t *C, const double *K, double *
       Sig[c] += K[i];
       C[i] = c;
       gsum += g;
+      *gtot += g;
       (*nmoves)++;
       for (int64_t e = G->off[i]; e < G->off[i + 1]; e++)
         if (G->idx[e] != (int32_t)i) U[G->idx[e]] = 1;
@@ -216,7 +219,8 @@ static int32_t move_async(const lgraph *G, int32_t *C, const double *K, double *
 /* moves in the fixed tile order above.                                      */
 static int32_t move_sync(const lgraph *G, int32_t *C, const double *K, double *Sig,
                          uint8_t *dC, uint8_t *U, const uint8_t *rng, int track,
-                         double M2, double Tp, int32_t max_iter, dtab *H, int64_t *nmoves) {
+                         double M2, double Tp, int32_t max_iter, dtab *H, int64_t *nmoves,
+                         double *gtot) {
   int64_t n = G->n;
   int64_t m = n ? n : 1;
   int32_t *Cs = (int32_t *)malloc((size_t)m * sizeof(int32_t));
@@ -278,6 +282,7 @@ static int32_t move_sync(const lgraph *G, int32_t *C, const double *K, double *S
       if (track) { dC[d] = 1; dC[c] = 1; }
     }
     double gsum = tiled_sum(gi, n);
+    *gtot += gsum;
     l = it + 1;
     if (gsum <= Tp) break;
   }
@@ -516,11 +521,12 @@ int or_core(int64_t n, const int64_t *off, const int32_t *idx, const float *w,
     const uint8_t *rng = (pass == 0) ? in_range : ones;
     double Tp = tau * M2 * M2 / 2.0;
     int64_t nm = 0;
+    double gt = 0.0;
     int32_t li;
     if (p->sync_mode)
-      li = move_sync(&G, C, Kl, Sl, dC, U, rng, track && pass == 0, M2, Tp, p->max_iter, &H, &nm);
+      li = move_sync(&G, C, Kl, Sl, dC, U, rng, track && pass == 0, M2, Tp, p->max_iter, &H, &nm, &gt);
     else
-      li = move_async(&G, C, Kl, Sl, dC, U, rng, track && pass == 0, M2, Tp, p->max_iter, &H, &nm);
+      li = move_async(&G, C, Kl, Sl, dC, U, rng, track && pass == 0, M2, Tp, p->max_iter, &H, &nm, &gt);
     if (pass == 0) {
       st->moves_pass0 = nm;
       for (int64_t c = 0; c < nl; c++) st->changed += dC[c] ? 1 : 0;
@@ -530,6 +536,7 @@ int or_core(int64_t n, const int64_t *off, const int32_t *idx, const float *w,
     st->level_entries[pass] = G.nnz;
     subset_renumber(nl, C, Sl, dC, tmpi, tmpd, tmpb);
     memcpy(CB, C, (size_t)nl * sizeof(int32_t));
+    for (int64_t i = 0; i < nl; i++) st->refined_vertices[pass] += dC[CB[i]] ? 1 : 0;
     break_changed(nl, C, Kl, Sl, dC);
     if (p->sync_mode)
       st->refine_rounds[pass] = refine_sync(&G, CB, C, Kl, Sl, dC, M2, p->max_iter, &H);
@@ -881,4 +888,32 @@ int32_t or_best_move(int64_t n, const int64_t *off, const int32_t *idx, const fl
   int32_t c = best_community(&H, C[i], M2, K[i], Sig, NULL, -1, g_out);
   dtab_free(&H);
   return c;
+}
+
+/* One local-moving phase (Alg. "leidenMove") on a given graph and state,     */
+/* exposed so its bookkeeping can be pinned directly.  Returns the number of */
+/* iterations; *gain_out receives the total gain of the moves in units of     */
+/* 2m^2 (the sum of the per-move scores).                                     */
+int32_t or_move_phase(int64_t n, const int64_t *off, const int32_t *idx, const float *w,
+                      int32_t *C, const double *K, double *Sig, uint8_t *dC, uint8_t *U,
+                      const uint8_t *rng, int32_t track, double M2, double tau, int32_t max_iter,
+                      int32_t sync_mode, int64_t *nmoves, double *gain_out) {
+  lgraph G = {n, off[n], (int64_t *)off, (int32_t *)idx, (float *)w, 0};
+  dtab H;
+  if (dtab_init(&H, n) != OR_OK) return -1;
+  double Tp = tau * M2 * M2 / 2.0;
+  *gain_out = 0.0;
+  int32_t l = sync_mode ? move_sync(&G, C, K, Sig, dC, U, rng, track, M2, Tp, max_iter, &H, nmoves, gain_out)
+                        : move_async(&G, C, K, Sig, dC, U, rng, track, M2, Tp, max_iter, &H, nmoves, gain_out);
+  dtab_free(&H);
+  return l;
+}
+
+/* Alg. "leidenSubsetRenumber" exposed for a direct pin. */
+void or_subset_renumber(int64_t n, int32_t *C, double *Sig, uint8_t *dC) {
+  int32_t *rep = (int32_t *)malloc((size_t)(n ? n : 1) * sizeof(int32_t));
+  double *S2 = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
+  uint8_t *d2 = (uint8_t *)malloc((size_t)(n ? n : 1));
+  subset_renumber(n, C, Sig, dC, rep, S2, d2);
+  free(rep); free(S2); free(d2);
 }

@@ -462,3 +462,138 @@ def test_refine_variants_valid(variant):
     check_state_invariants(st2.g, st2)
     if variant == 2:
         assert stats["passes"] >= 1
+
+
+# --------------------------------------------------------------------------
+# Phase-level pins
+# --------------------------------------------------------------------------
+def _rand_state(g, rng, k):
+    C = rng.integers(0, k, g.n).astype(np.int32)
+    K = np.array([g.w[g.off[i]:g.off[i + 1]].astype(np.float64).sum() for i in range(g.n)])
+    Sig = np.zeros(g.n); np.add.at(Sig, C, K)
+    return C, K, Sig, float(K.sum())
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_move_phase_async_exact_gain_and_bookkeeping(seed):
+    """Alg. leidenMove, serial asynchronous: each move's score is exact, so the
+    total equals half the exact change of 4m^2 Q; Sigma stays the scatter of K
+    by C; with one sweep every mover flags exactly its source and target."""
+    rng = np.random.default_rng(seed)
+    g = as_og(gen.gnp(40, 0.12, seed=300 + seed, weights="int"))
+    C, K, Sig, M2 = _rand_state(g, rng, 12)
+    ones = np.ones(g.n, np.uint8)
+    for max_iter in (1, 20):
+        l, C2, Sig2, dC, U, nm, gain = oracle.move_phase(g, C, K, Sig, M2, np.zeros(g.n, np.uint8),
+                                                         ones, ones, True, max_iter=max_iter)
+        assert Fraction(gain) * 2 == q4_exact(g, C2) - q4_exact(g, C)
+        S = np.zeros(g.n); np.add.at(S, C2, K)
+        assert np.array_equal(S, Sig2)
+        if max_iter == 1:
+            moved = np.flatnonzero(C2 != C)
+            expect = set(C[moved]) | set(C2[moved])
+            assert set(np.flatnonzero(dC)) == expect
+            assert nm == len(moved)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_move_phase_sync_rules(seed):
+    """Synchronous mode: no accepted swap between neighbours, Sigma bookkeeping
+    exact, the next frontier contains every neighbour of a mover, and with one
+    iteration every mover flags exactly its source and target."""
+    rng = np.random.default_rng(50 + seed)
+    g = as_og(gen.gnp(40, 0.15, seed=400 + seed, weights="int"))
+    C, K, Sig, M2 = _rand_state(g, rng, 10)
+    ones = np.ones(g.n, np.uint8)
+    l, C2, Sig2, dC, U, nm, gain = oracle.move_phase(g, C, K, Sig, M2, np.zeros(g.n, np.uint8),
+                                                     ones, ones, True, max_iter=1, sync=True)
+    moved = np.flatnonzero(C2 != C)
+    assert nm == len(moved) > 0
+    S = np.zeros(g.n); np.add.at(S, C2, K)
+    assert np.array_equal(S, Sig2)
+    assert set(np.flatnonzero(dC)) == set(C[moved]) | set(C2[moved])
+    for i in moved:
+        for j in g.idx[g.off[i]:g.off[i + 1]]:
+            if j != i:
+                assert U[j] == 1
+                if j in moved:
+                    assert not (C2[i] == C[j] and C2[j] == C[i])
+    # every accepted move has a positive score from the snapshot
+    for i in moved:
+        c, gval = oracle.best_move(g, C, K, Sig, M2, int(i))
+        assert c == C2[i] and gval > 0
+
+
+def test_subset_renumber_min_member():
+    """Alg. leidenSubsetRenumber with the smallest member as representative."""
+    rng = np.random.default_rng(3)
+    n = 50
+    C = rng.integers(0, 50, n).astype(np.int32)
+    Sig = rng.random(n)
+    dC = (rng.random(n) < 0.3).astype(np.uint8)
+    C2, S2, d2 = oracle.subset_renumber(C, Sig, dC)
+    for c in np.unique(C):
+        mem = np.flatnonzero(C == c)
+        r = mem.min()
+        assert np.all(C2[mem] == r)
+        assert S2[r] == Sig[c] and d2[r] == dC[c]
+    reps = set(C2)
+    for x in range(n):
+        if x not in reps:
+            assert S2[x] == 0.0 and d2[x] == 0
+
+
+def test_ds_marks_neighbours_outside_the_community():
+    """Alg. deltaScreening: an intra deletion marks the source's neighbours too.
+    In two K5 joined by bridge 4-5, deleting 3-4 marks {0..4} and 5."""
+    g = as_og(gen.clique_ring(2, 5))
+    st, _ = oracle.static(g)
+    empty = np.array([], np.int32)
+    for u, v in ((3, 4), (4, 3)):   # the batch lists each edge once, in either orientation
+        b = oracle.Batch(np.array([u]), np.array([v]), empty, empty, np.array([], np.float32))
+        gt, _ = oracle.apply_batch(g, b)
+        dV, _, _ = oracle.mark("ds", gt, b, st.C, st.K, st.Sig, st.M2)
+        assert sorted(np.flatnonzero(dV)) == [0, 1, 2, 3, 4, 5]
+        dV, _, _ = oracle.mark("df", gt, b, st.C, st.K, st.Sig, st.M2)
+        assert sorted(np.flatnonzero(dV)) == [3, 4]
+
+
+def test_pass_loop_rules():
+    """Alg. leiden: the first pass never stops on convergence; later passes refine
+    every community; the last dendrogram lookup uses the refined labels."""
+    g = as_og(gen.clique_ring(4, 5))
+    st, _ = oracle.static(g)
+    e = np.array([], np.int32)
+    _, dV, dC, stats = oracle.update(st, oracle.Batch(e, e, e, e, np.array([], np.float32)), "df")
+    assert stats["passes"] == 2 and stats["move_iters"] == [1, 1]
+    assert stats["refined_vertices"] == [0, stats["level_vertices"][1]]
+    # huge tolerance: every local-moving phase stops after one iteration; the
+    # cliques only appear through the refined labels of the last pass
+    for sync in (False, True):
+        st, stats = oracle.static(g, oracle.make_params(sync=sync, tau0=10.0))
+        assert stats["passes"] == 2 and stats["communities"][0] > 4
+        assert same_partition(st.C, np.repeat(np.arange(4), 5))
+    g2 = as_og(gen.planted_partition(512, 8, 0.15, 0.01, seed=2))
+    st, stats = oracle.static(g2)
+    assert stats["refined_vertices"] == stats["level_vertices"]
+
+
+def test_sync_blocks_only_exact_reverse_moves():
+    """Hand-built case: i (in D = {i, x}) proposes D -> E (E = {y}); its
+    neighbour j (F = {j}) proposes F -> D with a larger gain.  Only an exact
+    reverse move blocks a proposal, so both moves are accepted in one
+    synchronous iteration (only i and j are in the frontier)."""
+    i, x, y, j = 0, 1, 2, 3
+    g = as_og(gen.from_edges(4, [i, i, i, j], [x, y, j, x], [1.0, 3.0, 1.0, 8.0]))
+    C = np.array([0, 0, 2, 3], np.int32)          # D = {0, 1} labelled 0, E = {2}, F = {3}
+    K = np.array([g.w[g.off[k]:g.off[k + 1]].astype(np.float64).sum() for k in range(4)])
+    Sig = np.zeros(4); np.add.at(Sig, C, K)
+    M2 = float(K.sum())
+    ci, gi = oracle.best_move(g, C, K, Sig, M2, i)
+    cj, gj = oracle.best_move(g, C, K, Sig, M2, j)
+    assert (ci, cj) == (2, 0) and gj > gi > 0
+    ones = np.ones(4, np.uint8)
+    front = np.array([1, 0, 0, 1], np.uint8)    # only i and j are unprocessed
+    l, C2, Sig2, dC, U, nm, gain = oracle.move_phase(g, C, K, Sig, M2, np.zeros(4, np.uint8),
+                                                     front, ones, False, max_iter=1, sync=True)
+    assert C2[i] == 2 and C2[j] == 0 and nm == 2
