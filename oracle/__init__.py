@@ -46,7 +46,7 @@ def build(force: bool = True) -> str:
 class Params(ct.Structure):
     _fields_ = [("tau0", ct.c_double), ("tol_drop", ct.c_double), ("agg_tol", ct.c_double),
                 ("max_iter", ct.c_int32), ("max_passes", ct.c_int32),
-                ("sync_mode", ct.c_int32), ("refine_variant", ct.c_int32)]
+                ("sync_mode", ct.c_int32), ("refine_variant", ct.c_int32), ("nslices", ct.c_int32)]
 
 
 class Stats(ct.Structure):
@@ -75,9 +75,11 @@ class Stats(ct.Structure):
 
 def make_params(sync: bool = False, tau0: float = 0.01, tol_drop: float = 10.0,
                 agg_tol: float = 1.0, max_iter: int = 20, max_passes: int = 10,
-                refine_variant: int = 0) -> Params:
-    """Defaults from Sec. 4.6 (tau0 = 0.01, drop 10, 20 iterations); passes 10."""
-    return Params(tau0, tol_drop, agg_tol, max_iter, max_passes, 1 if sync else 0, refine_variant)
+                refine_variant: int = 0, nslices: int = 16) -> Params:
+    """Defaults from Sec. 4.6 (tau0 = 0.01, drop 10, 20 iterations); passes 10;
+    synchronous mode with 16 slices per sweep."""
+    return Params(tau0, tol_drop, agg_tol, max_iter, max_passes, 1 if sync else 0, refine_variant,
+                  nslices)
 
 
 _lib = None
@@ -297,7 +299,7 @@ def best_move(g: Graph, C, K, Sig, M2: float, i: int):
 
 
 def move_phase(g: Graph, C, K, Sig, M2: float, dC, U, rng, track: bool, tau: float = 0.01,
-               max_iter: int = 20, sync: bool = False):
+               max_iter: int = 20, sync: bool = False, nslices: int = 16):
     """One local-moving phase (Alg. leidenMove); returns (iterations, C, Sig, dC, U, moves,
     total gain in units of 2m^2)."""
     lib = _load()
@@ -308,7 +310,7 @@ def move_phase(g: Graph, C, K, Sig, M2: float, dC, U, rng, track: bool, tau: flo
     gain = np.zeros(1, np.float64)
     l = lib.or_move_phase(g.n, _p(g.off), _p(g.idx), _p(g.w), _p(C), _p(K), _p(Sig), _p(dC), _p(U),
                           _p(rng), 1 if track else 0, float(M2), float(tau), int(max_iter),
-                          1 if sync else 0, _p(nm), _p(gain))
+                          int(nslices) if sync else 0, _p(nm), _p(gain))
     return int(l), C, Sig, dC, U, int(nm[0]), float(gain[0])
 
 

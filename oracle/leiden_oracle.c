@@ -47,8 +47,9 @@ typedef struct {
   double agg_tol;         /* aggregation tolerance; 1.0 = never skip (Sec. 4.6)  */
   int32_t max_iter;       /* local-moving iterations per pass, 20 (Sec. 4.6)     */
   int32_t max_passes;     /* passes; not stated in the paper, 10                 */
-  int32_t sync_mode;      /* 0: serial asynchronous, 1: synchronous (test mode)  */
+  int32_t sync_mode;      /* 0: serial asynchronous, 1: synchronous (sliced)     */
   int32_t refine_variant; /* 0 subset refine, 1 full refine, 2 no continued passes (Sec. 4.1-4.3) */
+  int32_t nslices;        /* synchronous mode: slices per sweep (>= 1) */
 } or_params;
 
 typedef struct {
@@ -208,85 +209,98 @@ static int32_t move_async(const lgraph *G, int32_t *C, const double *K, double *
   return l;
 }
 
-/* Synchronous local-moving (deterministic mode; not in the paper, whose    */
-/* asynchronous order a GPU cannot reproduce).  Every unprocessed in-range   */
-/* vertex proposes its best move from a snapshot of C and Sigma.  A proposal  */
-/* d -> c is blocked when a neighbour proposes the exact reverse move c -> d  */
-/* and has priority (larger gain; equal gains: smaller vertex id), which     */
-/* removes the swap oscillation of simultaneous moves.  Accepted moves are   */
-/* applied at once.  The next frontier is the neighbours of the movers plus  */
-/* the blocked proposers.  The iteration's gain is the sum over accepted     */
-/* moves in the fixed tile order above.                                      */
+/* Slice of a vertex in the synchronous mode: MurmurHash3's 32-bit finaliser */
+/* (fmix32, Appleby) of the id, modulo the number of slices.                 */
+static int32_t slice_of(int64_t i, int32_t S) {
+  uint32_t h = (uint32_t)i;
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return (int32_t)(h % (uint32_t)S);
+}
+
+/* Synchronous local-moving (deterministic mode; not in the paper, whose     */
+/* serial asynchronous order a GPU cannot reproduce).  An iteration sweeps   */
+/* the S slices in order.  In a slice, every unprocessed in-range vertex of   */
+/* the slice is marked processed and proposes its best move from the current */
+/* state; a proposal d -> c is blocked when a neighbour of the same slice     */
+/* proposes the exact reverse move c -> d with priority (larger gain; equal   */
+/* gains: smaller id).  Accepted moves are applied at once and mark their    */
+/* neighbours unprocessed (a later slice sees them in the same iteration);   */
+/* blocked proposers stay unprocessed.  The iteration's gain is the sum of   */
+/* the accepted gains in the fixed tile order above.                          */
 static int32_t move_sync(const lgraph *G, int32_t *C, const double *K, double *Sig,
                          uint8_t *dC, uint8_t *U, const uint8_t *rng, int track,
-                         double M2, double Tp, int32_t max_iter, dtab *H, int64_t *nmoves,
-                         double *gtot) {
+                         double M2, double Tp, int32_t max_iter, int32_t S, dtab *H,
+                         int64_t *nmoves, double *gtot) {
   int64_t n = G->n;
   int64_t m = n ? n : 1;
-  int32_t *Cs = (int32_t *)malloc((size_t)m * sizeof(int32_t));
-  double *Ss = (double *)malloc((size_t)m * sizeof(double));
   int32_t *prop = (int32_t *)malloc((size_t)m * sizeof(int32_t));
+  int32_t *from = (int32_t *)malloc((size_t)m * sizeof(int32_t));
+  int32_t *sl = (int32_t *)malloc((size_t)m * sizeof(int32_t));
   double *gp = (double *)malloc((size_t)m * sizeof(double));
   double *gi = (double *)malloc((size_t)m * sizeof(double));
-  uint8_t *act = (uint8_t *)malloc((size_t)m);
   uint8_t *acc = (uint8_t *)malloc((size_t)m);
   int32_t l = 0;
+  for (int64_t i = 0; i < n; i++) sl[i] = slice_of(i, S);
   for (int32_t it = 0; it < max_iter; it++) {
-    memcpy(Cs, C, (size_t)n * sizeof(int32_t));
-    memcpy(Ss, Sig, (size_t)n * sizeof(double));
-    memcpy(act, U, (size_t)n);
-    memset(U, 0, (size_t)n);
-    /* proposals from the snapshot */
-    for (int64_t i = 0; i < n; i++) {
-      prop[i] = -1;
-      gp[i] = 0.0;
-      if (!act[i] || !rng[i]) continue;
-      int32_t d = Cs[i];
-      dtab_clear(H);
-      for (int64_t e = G->off[i]; e < G->off[i + 1]; e++) {
-        int32_t j = G->idx[e];
-        if (j == (int32_t)i) continue;
-        dtab_add(H, Cs[j], (double)G->w[e]);
+    for (int64_t i = 0; i < n; i++) gi[i] = 0.0;
+    for (int32_t s = 0; s < S; s++) {
+      /* proposals of the slice, from the current state */
+      for (int64_t i = 0; i < n; i++) {
+        prop[i] = -1;
+        if (sl[i] != s || !U[i]) continue;
+        U[i] = 0;
+        if (!rng[i]) continue;
+        int32_t d = C[i];
+        dtab_clear(H);
+        for (int64_t e = G->off[i]; e < G->off[i + 1]; e++) {
+          int32_t j = G->idx[e];
+          if (j == (int32_t)i) continue;
+          dtab_add(H, C[j], (double)G->w[e]);
+        }
+        double g;
+        int32_t c = best_community(H, d, M2, K[i], Sig, NULL, -1, &g);
+        if (c < 0) continue;
+        prop[i] = c;
+        from[i] = d;
+        gp[i] = g;
       }
-      double g;
-      int32_t c = best_community(H, d, M2, K[i], Ss, NULL, -1, &g);
-      if (c < 0) continue;
-      prop[i] = c;
-      gp[i] = g;
-    }
-    /* swap resolution among adjacent proposers */
-    for (int64_t i = 0; i < n; i++) {
-      acc[i] = 0;
-      gi[i] = 0.0;
-      if (prop[i] < 0) continue;
-      int win = 1;
-      for (int64_t e = G->off[i]; e < G->off[i + 1] && win; e++) {
-        int32_t j = G->idx[e];
-        if (j == (int32_t)i || prop[j] < 0) continue;
-        if (prop[j] != Cs[i] || Cs[j] != prop[i]) continue;
-        if (gp[j] > gp[i] || (gp[j] == gp[i] && j < (int32_t)i)) win = 0;
+      /* swap resolution among proposing neighbours of the slice */
+      for (int64_t i = 0; i < n; i++) {
+        acc[i] = 0;
+        if (prop[i] < 0) continue;
+        int win = 1;
+        for (int64_t e = G->off[i]; e < G->off[i + 1] && win; e++) {
+          int32_t j = G->idx[e];
+          if (j == (int32_t)i || prop[j] < 0) continue;
+          if (prop[j] != from[i] || from[j] != prop[i]) continue;
+          if (gp[j] > gp[i] || (gp[j] == gp[i] && j < (int32_t)i)) win = 0;
+        }
+        acc[i] = (uint8_t)win;
       }
-      if (win) { acc[i] = 1; gi[i] = gp[i]; }
-      else U[i] = 1; /* blocked proposers stay in the frontier */
-    }
-    for (int64_t i = 0; i < n; i++) {
-      if (!acc[i]) continue;
-      int32_t c = prop[i];
-      int32_t d = Cs[i];
-      C[i] = c;
-      Sig[d] -= K[i];
-      Sig[c] += K[i];
-      (*nmoves)++;
-      for (int64_t e = G->off[i]; e < G->off[i + 1]; e++)
-        if (G->idx[e] != (int32_t)i) U[G->idx[e]] = 1;
-      if (track) { dC[d] = 1; dC[c] = 1; }
+      for (int64_t i = 0; i < n; i++) {
+        if (prop[i] < 0) continue;
+        if (!acc[i]) { U[i] = 1; continue; }
+        int32_t c = prop[i], d = from[i];
+        C[i] = c;
+        Sig[d] -= K[i];
+        Sig[c] += K[i];
+        gi[i] = gp[i];
+        (*nmoves)++;
+        for (int64_t e = G->off[i]; e < G->off[i + 1]; e++)
+          if (G->idx[e] != (int32_t)i) U[G->idx[e]] = 1;
+        if (track) { dC[d] = 1; dC[c] = 1; }
+      }
     }
     double gsum = tiled_sum(gi, n);
     *gtot += gsum;
     l = it + 1;
     if (gsum <= Tp) break;
   }
-  free(Cs); free(Ss); free(prop); free(gp); free(gi); free(act); free(acc);
+  free(prop); free(from); free(sl); free(gp); free(gi); free(acc);
   return l;
 }
 
@@ -354,54 +368,58 @@ static int32_t refine_async(const lgraph *G, const int32_t *CB, int32_t *C, cons
   return 1;
 }
 
-/* Synchronous refinement (deterministic test mode; not in the paper).  Each */
-/* round: every isolated representative vertex of a changed bound proposes a */
-/* target from a snapshot (singleton targets only towards smaller ids); a     */
-/* proposal is accepted when the target's representative is not itself       */
-/* proposing; rounds stop when nothing is accepted.                           */
+/* Synchronous refinement (deterministic mode; not in the paper).  One sweep */
+/* over the S slices in order, like the paper's single sweep.  In a slice,    */
+/* every isolated vertex of a changed bound proposes its best target inside   */
+/* the bound from the current state; a proposal is accepted when the target's */
+/* representative is not proposing in the slice, or when the two propose to  */
+/* each other and the proposer has priority (larger gain; equal gains:        */
+/* smaller id).  Accepted merges are applied at once.                         */
 static int32_t refine_sync(const lgraph *G, const int32_t *CB, int32_t *C, const double *K,
-                           double *Sig, const uint8_t *dC, double M2, int32_t max_rounds, dtab *H) {
+                           double *Sig, const uint8_t *dC, double M2, int32_t S, dtab *H) {
   int64_t n = G->n;
-  int32_t *Cs = (int32_t *)malloc((size_t)(n ? n : 1) * sizeof(int32_t));
-  double *Ss = (double *)malloc((size_t)(n ? n : 1) * sizeof(double));
-  int32_t *sz = (int32_t *)calloc((size_t)(n ? n : 1), sizeof(int32_t));
-  int32_t *prop = (int32_t *)malloc((size_t)(n ? n : 1) * sizeof(int32_t));
-  int32_t rounds = 0;
+  int64_t m = n ? n : 1;
+  int32_t *sz = (int32_t *)calloc((size_t)m, sizeof(int32_t));
+  int32_t *prop = (int32_t *)malloc((size_t)m * sizeof(int32_t));
+  double *gp = (double *)malloc((size_t)m * sizeof(double));
+  uint8_t *acc = (uint8_t *)malloc((size_t)m);
   for (int64_t i = 0; i < n; i++) sz[C[i]]++;
-  for (int32_t r = 0; r < max_rounds; r++) {
-    memcpy(Cs, C, (size_t)n * sizeof(int32_t));
-    memcpy(Ss, Sig, (size_t)n * sizeof(double));
+  for (int32_t s = 0; s < S; s++) {
     for (int64_t i = 0; i < n; i++) {
       prop[i] = -1;
+      if (slice_of(i, S) != s) continue;
       if (!dC[CB[i]]) continue;
-      if (Cs[i] != (int32_t)i || sz[i] != 1) continue;
+      if (C[i] != (int32_t)i || sz[i] != 1) continue;
       dtab_clear(H);
       for (int64_t e = G->off[i]; e < G->off[i + 1]; e++) {
         int32_t j = G->idx[e];
         if (j == (int32_t)i) continue;
         if (CB[j] != CB[i]) continue;
-        dtab_add(H, Cs[j], (double)G->w[e]);
+        dtab_add(H, C[j], (double)G->w[e]);
       }
       double g;
-      prop[i] = best_community(H, (int32_t)i, M2, K[i], Ss, sz, (int32_t)i, &g);
+      prop[i] = best_community(H, (int32_t)i, M2, K[i], Sig, NULL, -1, &g);
+      gp[i] = g;
     }
-    int64_t acc = 0;
     for (int64_t i = 0; i < n; i++) {
       int32_t c = prop[i];
-      if (c < 0 || prop[c] >= 0) continue;
+      acc[i] = 0;
+      if (c < 0) continue;
+      if (prop[c] < 0) acc[i] = 1;
+      else if (prop[c] == (int32_t)i && (gp[i] > gp[c] || (gp[i] == gp[c] && (int32_t)i < c))) acc[i] = 1;
+    }
+    for (int64_t i = 0; i < n; i++) {
+      if (!acc[i]) continue;
+      int32_t c = prop[i];
       C[i] = c;
       Sig[i] -= K[i];
       Sig[c] += K[i];
-      acc++;
+      sz[i]--;
+      sz[c]++;
     }
-    rounds = r + 1;
-    if (acc == 0) break;
-    /* sizes after the round */
-    memset(sz, 0, (size_t)n * sizeof(int32_t));
-    for (int64_t i = 0; i < n; i++) sz[C[i]]++;
   }
-  free(Cs); free(Ss); free(sz); free(prop);
-  return rounds;
+  free(sz); free(prop); free(gp); free(acc);
+  return 1;
 }
 
 /* "Renumber communities" of Alg. "leiden": dense labels in ascending order  */
@@ -515,6 +533,7 @@ int or_core(int64_t n, const int64_t *off, const int32_t *idx, const float *w,
   for (int64_t i = 0; i < n; i++) st->affected += dV[i] ? 1 : 0;
   if (p->refine_variant == 1) { memset(dC, 1, (size_t)n); track = 0; }
   double tau = p->tau0;
+  const int32_t S = p->nslices > 0 ? p->nslices : 1;
   int32_t pass;
   for (pass = 0; pass < p->max_passes; pass++) {
     int64_t nl = G.n;
@@ -524,7 +543,7 @@ int or_core(int64_t n, const int64_t *off, const int32_t *idx, const float *w,
     double gt = 0.0;
     int32_t li;
     if (p->sync_mode)
-      li = move_sync(&G, C, Kl, Sl, dC, U, rng, track && pass == 0, M2, Tp, p->max_iter, &H, &nm, &gt);
+      li = move_sync(&G, C, Kl, Sl, dC, U, rng, track && pass == 0, M2, Tp, p->max_iter, S, &H, &nm, &gt);
     else
       li = move_async(&G, C, Kl, Sl, dC, U, rng, track && pass == 0, M2, Tp, p->max_iter, &H, &nm, &gt);
     if (pass == 0) {
@@ -539,7 +558,7 @@ int or_core(int64_t n, const int64_t *off, const int32_t *idx, const float *w,
     for (int64_t i = 0; i < nl; i++) st->refined_vertices[pass] += dC[CB[i]] ? 1 : 0;
     break_changed(nl, C, Kl, Sl, dC);
     if (p->sync_mode)
-      st->refine_rounds[pass] = refine_sync(&G, CB, C, Kl, Sl, dC, M2, p->max_iter, &H);
+      st->refine_rounds[pass] = refine_sync(&G, CB, C, Kl, Sl, dC, M2, S, &H);
     else
       st->refine_rounds[pass] = refine_async(&G, CB, C, Kl, Sl, dC, M2, &H);
     st->passes = pass + 1;
@@ -903,7 +922,7 @@ int32_t or_move_phase(int64_t n, const int64_t *off, const int32_t *idx, const f
   if (dtab_init(&H, n) != OR_OK) return -1;
   double Tp = tau * M2 * M2 / 2.0;
   *gain_out = 0.0;
-  int32_t l = sync_mode ? move_sync(&G, C, K, Sig, dC, U, rng, track, M2, Tp, max_iter, &H, nmoves, gain_out)
+  int32_t l = sync_mode ? move_sync(&G, C, K, Sig, dC, U, rng, track, M2, Tp, max_iter, sync_mode, &H, nmoves, gain_out)
                         : move_async(&G, C, K, Sig, dC, U, rng, track, M2, Tp, max_iter, &H, nmoves, gain_out);
   dtab_free(&H);
   return l;

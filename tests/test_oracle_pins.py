@@ -506,7 +506,7 @@ def test_move_phase_sync_rules(seed):
     C, K, Sig, M2 = _rand_state(g, rng, 10)
     ones = np.ones(g.n, np.uint8)
     l, C2, Sig2, dC, U, nm, gain = oracle.move_phase(g, C, K, Sig, M2, np.zeros(g.n, np.uint8),
-                                                     ones, ones, True, max_iter=1, sync=True)
+                                                     ones, ones, True, max_iter=1, sync=True, nslices=1)
     moved = np.flatnonzero(C2 != C)
     assert nm == len(moved) > 0
     S = np.zeros(g.n); np.add.at(S, C2, K)
@@ -522,6 +522,29 @@ def test_move_phase_sync_rules(seed):
     for i in moved:
         c, gval = oracle.best_move(g, C, K, Sig, M2, int(i))
         assert c == C2[i] and gval > 0
+
+
+@pytest.mark.parametrize("S", [2, 16])
+def test_move_phase_sliced_sync_bookkeeping(S):
+    """Sliced synchronous sweeps: Sigma bookkeeping stays exact, every mover
+    flags its source and target, and with zero tolerance the phase ends with
+    an empty frontier before the iteration cap."""
+    rng = np.random.default_rng(7)
+    g = as_og(gen.gnp(80, 0.08, seed=77, weights="int"))
+    C, K, Sig, M2 = _rand_state(g, rng, 20)
+    ones = np.ones(g.n, np.uint8)
+    l, C2, Sig2, dC, U, nm, gain = oracle.move_phase(g, C, K, Sig, M2, np.zeros(g.n, np.uint8),
+                                                     ones, ones, True, max_iter=1, sync=True, nslices=S)
+    moved = np.flatnonzero(C2 != C)
+    S_ = np.zeros(g.n); np.add.at(S_, C2, K)
+    assert np.array_equal(S_, Sig2)
+    assert set(C[moved]) | set(C2[moved]) <= set(np.flatnonzero(dC))
+    l, C3, Sig3, dC3, U3, nm3, gain3 = oracle.move_phase(g, C, K, Sig, M2, np.zeros(g.n, np.uint8),
+                                                         ones, ones, True, tau=0.0, max_iter=200, sync=True,
+                                                         nslices=S)
+    assert U3.sum() == 0 and l < 200
+    S3 = np.zeros(g.n); np.add.at(S3, C3, K)
+    assert np.array_equal(S3, Sig3)
 
 
 def test_subset_renumber_min_member():
@@ -570,7 +593,7 @@ def test_pass_loop_rules():
     # huge tolerance: every local-moving phase stops after one iteration; the
     # cliques only appear through the refined labels of the last pass
     for sync in (False, True):
-        st, stats = oracle.static(g, oracle.make_params(sync=sync, tau0=10.0))
+        st, stats = oracle.static(g, oracle.make_params(sync=sync, tau0=10.0, nslices=2))
         assert stats["passes"] == 2 and stats["communities"][0] > 4
         assert same_partition(st.C, np.repeat(np.arange(4), 5))
     g2 = as_og(gen.planted_partition(512, 8, 0.15, 0.01, seed=2))
@@ -595,5 +618,17 @@ def test_sync_blocks_only_exact_reverse_moves():
     ones = np.ones(4, np.uint8)
     front = np.array([1, 0, 0, 1], np.uint8)    # only i and j are unprocessed
     l, C2, Sig2, dC, U, nm, gain = oracle.move_phase(g, C, K, Sig, M2, np.zeros(4, np.uint8),
-                                                     front, ones, False, max_iter=1, sync=True)
+                                                     front, ones, False, max_iter=1, sync=True, nslices=1)
     assert C2[i] == 2 and C2[j] == 0 and nm == 2
+
+
+def test_zero_gain_move_is_not_taken():
+    """Eq. 2 gain exactly zero (checked in exact arithmetic): no move, since only
+    a strictly better community is taken (Sec. A.3, "a superior community")."""
+    g = as_og(gen.gnp(6, 0.5, seed=0, weights="unit"))
+    C = np.array([2, 1, 1, 0, 0, 0], np.int32)
+    K = np.diff(g.off).astype(np.float64)
+    Sig = np.zeros(6); np.add.at(Sig, C, K)
+    C2 = C.copy(); C2[3] = 2
+    assert q4_exact(g, C2) == q4_exact(g, C)      # the only candidate has zero gain
+    assert oracle.best_move(g, C, K, Sig, float(K.sum()), 3)[0] == -1
