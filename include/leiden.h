@@ -1,0 +1,198 @@
+/*
+ * leiden.h - C ABI of the MI355X (gfx950) dynamic Leiden library.
+ *
+ * Community detection on an evolving undirected graph with the Leiden method
+ * and its three dynamic front-ends, Naive-dynamic (ND), Delta-screening (DS)
+ * and Dynamic Frontier (DF), as defined in Sahu, "A Starting Point for Dynamic
+ * Community Detection with Leiden Algorithm" (arXiv 2405.11658):
+ *   - problem statement and update call: Sec. 3.5 and Sec. 4.5 (the update
+ *     takes G^t, the batch Delta^-, Delta^+, C^{t-1}, K^{t-1}, Sigma^{t-1} and
+ *     returns C^t, K^t, Sigma^t);
+ *   - modularity: Eq. 1; move score: Eq. 2;
+ *   - pass loop: Alg. "leiden"; phases: Alg. "leidenMove", "leidenRefine",
+ *     "leidenAggregate", "leidenSubsetRenumber"; weights: Alg. "updateWeights";
+ *   - front-ends: Alg. "naiveDynamic", "deltaScreening", "dynamicFrontier".
+ *
+ * Conventions.  Graphs are CSR: int64 offsets [n+1], int32 neighbour ids,
+ * float32 weights (> 0).  An undirected graph stores both directions of every
+ * edge; a self-loop (i,i,w) is stored once and counts w once.  Weight totals
+ * (K, Sigma, 2m) and modularity are float64 (Sec. 5.1.2).
+ *
+ * Memory.  Unless a parameter says "host", every pointer is a device pointer
+ * (hipMalloc'd memory of the current device).  The caller owns all input and
+ * output buffers; they must stay valid until the work enqueued on `stream`
+ * completes.  A handle owns its graph, state and scratch; leiden_destroy frees
+ * them.  `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *
+ * Ordering.  Calls are stream-ordered; calls that return host values (q_out,
+ * stats, counts) synchronise the stream before returning.
+ *
+ * Errors.  Every entry point returns a leiden_status; no exception crosses the
+ * ABI.  On LEIDEN_EINVAL the handle is unchanged (inputs are validated before
+ * any mutation).  leiden_last_error() gives a message for the last failure on
+ * a handle.
+ *
+ * Concurrency.  A handle is used by one host thread at a time; distinct
+ * handles are independent.
+ */
+#ifndef LEIDEN_H
+#define LEIDEN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LEIDEN_OK = 0,
+  LEIDEN_EINVAL = 1, /* bad argument, id out of range, non-positive weight,
+                        malformed batch (see leiden_batch) */
+  LEIDEN_ENOMEM = 2, /* device allocation failed */
+  LEIDEN_ESTATE = 3, /* update before leiden_static / leiden_set_state */
+  LEIDEN_EHIP = 4    /* HIP runtime error */
+} leiden_status;
+
+/* Dynamic front-ends (Sec. 3.5.1-3.5.3, Appendix A.1-A.2, Sec. 4.5). */
+typedef enum { LEIDEN_ND = 1, LEIDEN_DS = 2, LEIDEN_DF = 3 } leiden_mode;
+
+/* Parameters (Sec. 4.6 and 5.1.2).  leiden_default_params fills the paper's
+ * values: tau0 = 0.01, tol_drop = 10, max_iter = 20; max_passes = 10 (not
+ * stated in the paper); agg_tol = 1.0 (aggregation never skipped, Sec. 4.6).
+ * Local moving and refinement sweep the vertices in nslices hash-ordered
+ * slices (default 16); the slices run in order, the vertices of a slice
+ * synchronously (the GPU form of the paper's asynchronous sweep).
+ * sync_mode = 1 sums the per-iteration gain in a fixed order so results are
+ * bit-identical to the CPU oracle's synchronous mode; 0 uses atomics (the
+ * move/refine decisions are the same).  refine_variant: 0 Subset Refine
+ * (Sec. 4.3, default), 1 Full Refine (Sec. 4.2), 2 no continued passes
+ * (Sec. 4.1). */
+typedef struct {
+  double tau0;
+  double tol_drop;
+  double agg_tol;
+  int32_t max_iter;
+  int32_t max_passes;
+  int32_t sync_mode;
+  int32_t refine_variant;
+  int32_t nslices; /* 1 .. 1024 */
+} leiden_params;
+
+#define LEIDEN_MAX_PASSES 64
+
+/* Per-call statistics (host struct). */
+typedef struct {
+  int32_t passes;
+  int32_t move_iters[LEIDEN_MAX_PASSES];
+  int32_t refine_rounds[LEIDEN_MAX_PASSES];
+  int64_t level_vertices[LEIDEN_MAX_PASSES];
+  int64_t level_entries[LEIDEN_MAX_PASSES];
+  int64_t communities[LEIDEN_MAX_PASSES];
+  int64_t refined_vertices[LEIDEN_MAX_PASSES];
+  int64_t affected;     /* vertices initially marked affected */
+  int64_t changed;      /* communities flagged changed after the first local-moving phase */
+  int64_t moves_pass0;  /* moves in the first local-moving phase */
+  double ms_total;      /* device time of the call (HIP events on `stream`) */
+  double ms_apply;      /* batch validation + graph update (not in the paper's timing) */
+  double ms_mark;       /* marking, changedCommunities, updateWeights */
+  double ms_move;
+  double ms_refine;
+  double ms_aggregate;
+  double ms_other;      /* renumber, lookup, final relabel, Sigma recompute, modularity */
+} leiden_stats;
+
+/* Batch update (Sec. 3.5, Sec. 5.1.4).  Device arrays; each undirected edge
+ * is listed once, in either orientation; the library applies both
+ * directions.  A deleted edge must exist in G^{t-1} (its weight is taken
+ * from the graph); an inserted edge must not; no self-loops, no repeated
+ * edge, ids in [0, n), inserted weights finite and > 0.  Anything else is
+ * LEIDEN_EINVAL and leaves the handle unchanged. */
+typedef struct {
+  int64_t n_del;
+  const int32_t *del_u;
+  const int32_t *del_v;
+  int64_t n_ins;
+  const int32_t *ins_u;
+  const int32_t *ins_v;
+  const float *ins_w;
+} leiden_batch;
+
+/* Optional trace of an update (device arrays of n bytes, each nullable):
+ * affected = deltaV after marking (isAffected), in_range = inAffectedRange,
+ * changed = changed-community flags from changedCommunities (keyed by the
+ * previous community id). */
+typedef struct {
+  uint8_t *affected;
+  uint8_t *in_range;
+  uint8_t *changed;
+} leiden_trace;
+
+typedef struct leiden_handle leiden_handle;
+
+void leiden_default_params(leiden_params *p /* host */);
+
+/* Create a handle holding a copy of the graph (rows are sorted by the
+ * library; duplicate entries in a row are LEIDEN_EINVAL).  params may be NULL
+ * for the defaults.  *out (host) receives the handle. */
+leiden_status leiden_create(int64_t n, int64_t nnz, const int64_t *offsets, const int32_t *indices,
+                            const float *weights, const leiden_params *params, void *stream,
+                            leiden_handle **out);
+
+leiden_status leiden_destroy(leiden_handle *h);
+
+leiden_status leiden_set_params(leiden_handle *h, const leiden_params *params /* host */);
+
+/* Static Leiden (Alg. "leiden" from singletons, everything affected and
+ * changed).  membership_out: n int32, dense labels in [0, |Gamma|) ascending
+ * by final label; nullable.  q_out (host, nullable): Eq. 1 of the result.
+ * stats (host, nullable).  Stores C, K, Sigma, 2m in the handle. */
+leiden_status leiden_static(leiden_handle *h, int32_t *membership_out, double *q_out,
+                            leiden_stats *stats, void *stream);
+
+/* Dynamic update: apply the batch to the handle's graph (G^t), then run the
+ * ND / DS / DF front-end and the pass loop from the stored membership.
+ * Outputs as for leiden_static; trace nullable.  Requires a prior
+ * leiden_static or leiden_set_state (else LEIDEN_ESTATE). */
+leiden_status leiden_update(leiden_handle *h, const leiden_batch *batch, int32_t mode,
+                            int32_t *membership_out, double *q_out, leiden_stats *stats,
+                            const leiden_trace *trace, void *stream);
+
+/* Eq. 1 in FP64 for any CSR graph and membership (labels in [0, n));
+ * q_out (host) is 0 when the graph has no edges.  Stateless. */
+leiden_status leiden_modularity(int64_t n, const int64_t *offsets, const int32_t *indices,
+                                const float *weights, const int32_t *membership, double *q_out,
+                                void *stream);
+
+/* Alg. "leidenAggregate" for a given membership with dense labels in
+ * [0, ncomm): super-vertex CSR with, for each pair of communities, the FP64
+ * sum of the weights rounded to float32.  out_offsets: ncomm+1 int64;
+ * out_indices / out_weights: capacity nnz.  Rows are compacted; the order of
+ * entries inside a row is unspecified.  *nnz_out (host) receives the number
+ * of entries.  Stateless. */
+leiden_status leiden_aggregate(int64_t n, const int64_t *offsets, const int32_t *indices,
+                               const float *weights, const int32_t *membership, int64_t ncomm,
+                               int64_t *out_offsets, int32_t *out_indices, float *out_weights,
+                               int64_t *nnz_out, void *stream);
+
+/* State access.  get_graph copies the current CSR (capacity n+1 / nnz; *nnz
+ * host, may be queried first with NULL arrays).  get_state copies C (n
+ * int32), K and Sigma (n float64 each) and 2m (host); any pointer nullable.
+ * set_state installs a membership (labels in [0, n)) and recomputes K,
+ * Sigma and 2m from the graph. */
+leiden_status leiden_get_graph(leiden_handle *h, int64_t *offsets, int32_t *indices, float *weights,
+                               int64_t *nnz /* host */, void *stream);
+leiden_status leiden_get_state(leiden_handle *h, int32_t *membership, double *K, double *Sigma,
+                               double *m2 /* host */, void *stream);
+leiden_status leiden_set_state(leiden_handle *h, const int32_t *membership, void *stream);
+
+int64_t leiden_num_vertices(const leiden_handle *h);
+int64_t leiden_num_entries(const leiden_handle *h);
+
+const char *leiden_strerror(int32_t status);
+const char *leiden_last_error(const leiden_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LEIDEN_H */

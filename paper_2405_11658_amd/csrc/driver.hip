@@ -1,0 +1,1068 @@
+// Host driver and C ABI of the dynamic Leiden library (see include/leiden.h).
+//
+// The pass loop follows Alg. "leiden": local-moving (k_move.hip), subset
+// renumbering, breaking of changed communities and refinement (k_refine.hip),
+// then - unless a later pass converged in one iteration - dense renumbering,
+// dendrogram lookup and aggregation (k_aggregate.hip) into the next level.
+// Front-ends (Alg. "naiveDynamic", "deltaScreening", "dynamicFrontier") and
+// "updateWeights" run on the device (k_batch.hip).  Data-dependent loop
+// control reads one scalar per iteration back to the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "kernels.hpp"
+#include "leiden.h"
+
+using namespace lk;
+
+namespace {
+
+struct DBuf {
+  void *p = nullptr;
+  size_t cap = 0;
+};
+
+enum Slot {
+  // level arrays (size n of level 0)
+  L_C, L_K, L_S, L_S2, L_dC, L_dC2, L_U, L_rng, L_CB, L_Ctop, L_prop, L_from, L_gp, L_gi, L_Sz,
+  L_rep, L_lists, L_region, L_tiles, L_flags, L_map, L_scnt, L_vbs, L_soff, L_sfill,
+  // level graphs (ping-pong)
+  G0_off, G0_idx, G0_w, G0_crow, G1_off, G1_idx, G1_w, G1_crow,
+  // aggregation
+  A_cnt, A_coff, A_mem, A_mdeg, A_mpos, A_mcrow, A_toff, A_hidx, A_hw, A_rowlen, A_pkey, A_pval,
+  A_pcnt_item, A_pcnt, A_tcap, A_tstart, A_tkeys, A_tvals,
+  // hubs
+  H_keys, H_vals,
+  // primitives
+  T_tmp,
+  // batch
+  B_keys, B_vals, B_skeys, B_svals, B_ew, B_bstart, B_bcnt, B_dcnt, B_icnt, B_isdel, B_delpre,
+  B_newdeg,
+  // marking
+  M_dE, M_dCm, M_k2, M_k2s, M_v2, M_v2s, M_list,
+  // modularity
+  Q_S, Q_crow,
+  NSLOT
+};
+
+struct DevScal {
+  int32_t bucket_n[8];
+  unsigned long long maxdeg;
+  double gain;
+  unsigned long long moves;
+  int32_t accepted;
+  int32_t err;
+  unsigned long long refined;
+  double acc[4];
+  double m2delta;
+  double tiles_total;
+  int32_t list_count;
+  int32_t pad;
+  unsigned long long nz;
+};
+
+struct Workspace {
+  DBuf ws[NSLOT];
+  DBuf scal;
+  void *hpin = nullptr;
+  std::string err;
+  std::vector<hipEvent_t> events;
+  ~Workspace() {
+    for (auto &b : ws)
+      if (b.p) (void)hipFree(b.p);
+    if (scal.p) (void)hipFree(scal.p);
+    if (hpin) (void)hipHostFree(hpin);
+    for (auto e : events) (void)hipEventDestroy(e);
+  }
+};
+
+}  // namespace
+
+struct leiden_handle {
+  int64_t n = 0;
+  int64_t nnz = 0;
+  leiden_params prm;
+  DBuf g_off, g_idx, g_w, g_crow;
+  DBuf t_off, t_idx, t_w;
+  DBuf C, K, Sig;
+  double M2 = 0.0;
+  bool has_state = false;
+  Workspace w;
+  ~leiden_handle() {
+    for (DBuf *b : {&g_off, &g_idx, &g_w, &g_crow, &t_off, &t_idx, &t_w, &C, &K, &Sig})
+      if (b->p) (void)hipFree(b->p);
+  }
+};
+
+namespace {
+
+struct Fail {
+  leiden_status st;
+};
+
+constexpr size_t kPinBytes = 65536;
+constexpr int kMaxSlices = 1024;
+
+// Call context: workspace + stream; helpers throw Fail, caught at the ABI.
+struct Ctx {
+  Workspace *w;
+  hipStream_t s;
+
+  void check(hipError_t e, const char *what) {
+    if (e != hipSuccess) {
+      w->err = std::string(what) + ": " + hipGetErrorString(e);
+      throw Fail{e == hipErrorOutOfMemory ? LEIDEN_ENOMEM : LEIDEN_EHIP};
+    }
+  }
+  void launched(const char *what) { check(hipGetLastError(), what); }
+  void invalid(const std::string &msg) {
+    w->err = msg;
+    throw Fail{LEIDEN_EINVAL};
+  }
+
+  void ensure(DBuf &b, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (b.cap >= bytes) return;
+    if (b.p) {
+      check(hipStreamSynchronize(s), "hipStreamSynchronize");
+      check(hipFree(b.p), "hipFree");
+      b.p = nullptr;
+      b.cap = 0;
+    }
+    size_t want = std::max(bytes, (size_t)(b.cap + b.cap / 4));
+    want = (want + 255) & ~(size_t)255;
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      b.p = nullptr;
+      w->err = "device allocation of " + std::to_string(want) + " bytes failed";
+      throw Fail{LEIDEN_ENOMEM};
+    }
+    b.cap = want;
+  }
+  template <class T>
+  T *get(Slot k, int64_t count) {
+    ensure(w->ws[k], (size_t)std::max<int64_t>(count, 1) * sizeof(T));
+    return (T *)w->ws[k].p;
+  }
+  DevScal *scal() {
+    if (!w->scal.p) {
+      ensure(w->scal, sizeof(DevScal));
+      check(hipMemsetAsync(w->scal.p, 0, sizeof(DevScal), s), "memset");
+    }
+    return (DevScal *)w->scal.p;
+  }
+  void *pin() {
+    if (!w->hpin) check(hipHostMalloc(&w->hpin, kPinBytes, hipHostMallocDefault), "hipHostMalloc");
+    return w->hpin;
+  }
+  template <class T>
+  void zero(T *p, int64_t count) {
+    if (count > 0) check(hipMemsetAsync(p, 0, (size_t)count * sizeof(T), s), "hipMemsetAsync");
+  }
+  template <class T>
+  T read(const T *dev) {
+    T *hp = (T *)pin();
+    check(hipMemcpyAsync(hp, dev, sizeof(T), hipMemcpyDeviceToHost, s), "hipMemcpyAsync D2H");
+    check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    return *hp;
+  }
+  template <class T>
+  void copy(T *dst, const T *src, int64_t count) {
+    if (count > 0)
+      check(hipMemcpyAsync(dst, src, (size_t)count * sizeof(T), hipMemcpyDeviceToDevice, s), "hipMemcpyAsync D2D");
+  }
+  void *tmp(size_t bytes) { return get<unsigned char>(T_tmp, (int64_t)bytes); }
+};
+
+// Phase timing with events on the call's stream.
+enum Cat { CAT_APPLY, CAT_MARK, CAT_MOVE, CAT_REFINE, CAT_AGG, CAT_OTHER, NCAT };
+struct Timer {
+  Ctx &x;
+  bool on;
+  std::vector<std::pair<hipEvent_t, int>> marks;
+  size_t used = 0;
+  Timer(Ctx &c, bool enabled) : x(c), on(enabled) {}
+  void mark(int cat) {  // the interval ending here is attributed to `cat`
+    if (!on) return;
+    if (used == x.w->events.size()) {
+      hipEvent_t e;
+      x.check(hipEventCreate(&e), "hipEventCreate");
+      x.w->events.push_back(e);
+    }
+    hipEvent_t e = x.w->events[used++];
+    x.check(hipEventRecord(e, x.s), "hipEventRecord");
+    marks.push_back({e, cat});
+  }
+  void finish(leiden_stats *st) {
+    if (!on || !st || marks.size() < 2) return;
+    x.check(hipEventSynchronize(marks.back().first), "hipEventSynchronize");
+    double t[NCAT] = {0};
+    for (size_t k = 1; k < marks.size(); ++k) {
+      float ms = 0.f;
+      x.check(hipEventElapsedTime(&ms, marks[k - 1].first, marks[k].first), "hipEventElapsedTime");
+      t[marks[k].second] += ms;
+    }
+    float tot = 0.f;
+    x.check(hipEventElapsedTime(&tot, marks.front().first, marks.back().first), "hipEventElapsedTime");
+    st->ms_total = tot;
+    st->ms_apply = t[CAT_APPLY];
+    st->ms_mark = t[CAT_MARK];
+    st->ms_move = t[CAT_MOVE];
+    st->ms_refine = t[CAT_REFINE];
+    st->ms_aggregate = t[CAT_AGG];
+    st->ms_other = t[CAT_OTHER];
+  }
+};
+
+struct Level {
+  int64_t n, nnz;
+  const int64_t *off;
+  const int32_t *idx;
+  const float *w;
+  const int32_t *crow;
+};
+
+int64_t pow2_at_least(int64_t x) {
+  int64_t c = 2;
+  while (c < x) c <<= 1;
+  return c;
+}
+
+// Eq. 1 for a level graph and membership (labels < n).
+double modularity_dev(Ctx &x, const Level &g, const int32_t *C) {
+  DevScal *sc = x.scal();
+  double *S = x.get<double>(Q_S, g.n);
+  x.zero(S, g.n);
+  x.zero(sc->acc, 4);
+  modularity_edges(g.off, g.idx, g.w, g.crow, g.n, g.nnz, C, sc->acc, S, x.s);
+  modularity_comm(S, g.n, sc->acc, x.s);
+  x.launched("modularity");
+  double acc[4];
+  x.check(hipMemcpyAsync(x.pin(), sc->acc, sizeof(acc), hipMemcpyDeviceToHost, x.s), "D2H");
+  x.check(hipStreamSynchronize(x.s), "sync");
+  memcpy(acc, x.pin(), sizeof(acc));
+  const double M2 = acc[1];
+  if (!(M2 > 0.0)) return 0.0;
+  modularity_comm_sq(S, g.n, M2, sc->acc, x.s);
+  x.launched("modularity_sq");
+  const double sq = x.read(&sc->acc[2]);
+  return acc[0] / M2 - sq;
+}
+
+// Per-level slice and degree-bucket layout: host copy of the region starts
+// (index s*kNB+b), the device copy, and the vertex-by-slice grouping.
+struct Layout {
+  int S;
+  std::vector<int64_t> region;  // S*kNB+1
+  std::vector<int64_t> soff;    // S+1
+  int64_t nhub;
+};
+
+Layout level_layout(Ctx &x, const Level &g, int S, int32_t *region_dev, int32_t *counts_tmp, int32_t *scnt,
+                    int32_t *soff_dev, int32_t *sfill, int32_t *vbyslice) {
+  Layout L;
+  L.S = S;
+  const int nb = S * kNB;
+  x.zero(counts_tmp, nb);
+  x.zero(scnt, S);
+  slice_hist(g.off, g.n, S, counts_tmp, scnt, x.s);
+  x.launched("slice_hist");
+  int32_t *hp = (int32_t *)x.pin();
+  x.check(hipMemcpyAsync(hp, counts_tmp, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, x.s), "D2H");
+  x.check(hipMemcpyAsync(hp + nb, scnt, sizeof(int32_t) * S, hipMemcpyDeviceToHost, x.s), "D2H");
+  x.check(hipStreamSynchronize(x.s), "sync");
+  L.region.assign(nb + 1, 0);
+  L.soff.assign(S + 1, 0);
+  for (int k = 0; k < nb; ++k) L.region[k + 1] = L.region[k] + hp[k];
+  for (int k = 0; k < S; ++k) L.soff[k + 1] = L.soff[k] + hp[nb + k];
+  L.nhub = 0;
+  for (int s = 0; s < S; ++s) L.nhub += hp[s * kNB + kNB - 1];
+  int32_t *up = hp + nb + S;
+  for (int k = 0; k <= nb; ++k) up[k] = (int32_t)L.region[k];
+  for (int k = 0; k <= S; ++k) up[nb + 1 + k] = (int32_t)L.soff[k];
+  x.check(hipMemcpyAsync(region_dev, up, sizeof(int32_t) * (nb + 1), hipMemcpyHostToDevice, x.s), "H2D");
+  x.check(hipMemcpyAsync(soff_dev, up + nb + 1, sizeof(int32_t) * (S + 1), hipMemcpyHostToDevice, x.s), "H2D");
+  x.zero(sfill, S);
+  slice_scatter(g.n, S, soff_dev, sfill, vbyslice, x.s);
+  x.launched("slice_scatter");
+  x.check(hipStreamSynchronize(x.s), "sync");  // the pinned staging area is reused
+  return L;
+}
+
+int64_t max_degree(Ctx &x, const Level &g) {
+  DevScal *sc = x.scal();
+  x.zero(sc->bucket_n, 8);
+  x.zero(&sc->maxdeg, 1);
+  bucket_hist(g.off, g.n, sc->bucket_n, &sc->maxdeg, x.s);
+  x.launched("bucket_hist");
+  return (int64_t)x.read(&sc->maxdeg);
+}
+
+struct Hub {
+  int *keys = nullptr;
+  double *vals = nullptr;
+  int64_t cap = 0;
+  int blocks = 0;
+};
+
+Hub hub_tables(Ctx &x, int64_t nhub, int64_t maxdeg) {
+  Hub h;
+  if (nhub <= 0) return h;
+  h.cap = pow2_at_least(2 * maxdeg);
+  const int64_t budget = (int64_t)8 << 30;  // bytes for hub tables
+  int64_t blocks = std::min<int64_t>(nhub, 256);
+  blocks = std::max<int64_t>(1, std::min<int64_t>(blocks, budget / (h.cap * 12)));
+  h.blocks = (int)blocks;
+  h.keys = x.get<int>(H_keys, h.cap * blocks);
+  h.vals = x.get<double>(H_vals, h.cap * blocks);
+  return h;
+}
+
+// exclusive scans through the shared temp buffer
+void scan_i32(Ctx &x, const int32_t *in, int32_t *out, int64_t n) {
+  size_t tb = scan_excl_i32(nullptr, 0, in, out, n, x.s);
+  scan_excl_i32(x.tmp(tb), tb, in, out, n, x.s);
+  x.launched("scan_i32");
+}
+void scan_i64(Ctx &x, const int64_t *in, int64_t *out, int64_t n) {
+  size_t tb = scan_excl_i64(nullptr, 0, in, out, n, x.s);
+  scan_excl_i64(x.tmp(tb), tb, in, out, n, x.s);
+  x.launched("scan_i64");
+}
+void scan_i32_i64(Ctx &x, const int32_t *in, int64_t *out, int64_t n) {
+  size_t tb = scan_excl_i32_to_i64(nullptr, 0, in, out, n, x.s);
+  scan_excl_i32_to_i64(x.tmp(tb), tb, in, out, n, x.s);
+  x.launched("scan_i32_i64");
+}
+
+// Dense relabel of C[0..n) (labels < bound) in ascending order; returns count.
+int64_t renumber_dense(Ctx &x, int32_t *C, int64_t n, int64_t bound) {
+  int32_t *flags = x.get<int32_t>(L_flags, bound + 1);
+  int32_t *map = x.get<int32_t>(L_map, bound + 1);
+  x.zero(flags, bound + 1);
+  mark_used(C, n, flags, x.s);
+  scan_i32(x, flags, map, bound + 1);
+  gather_map(C, map, n, x.s);
+  x.launched("renumber");
+  return (int64_t)x.read(&map[bound]);
+}
+
+// Alg. "leidenAggregate": level g with dense labels C (< ncomm) -> out level.
+Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, int outbuf, double *Kout) {
+  AggArgs a;
+  memset(&a, 0, sizeof(a));
+  a.n = g.n;
+  a.nnz = g.nnz;
+  a.ncomm = ncomm;
+  a.off = g.off;
+  a.idx = g.idx;
+  a.w = g.w;
+  a.C = C;
+  const int64_t nch = ceil_div(std::max<int64_t>(g.nnz, 1), kChunk);
+  a.cnt = x.get<int32_t>(A_cnt, ncomm + 1);
+  a.coff = x.get<int32_t>(A_coff, ncomm + 1);
+  a.mem = x.get<int32_t>(A_mem, g.n);
+  a.mdeg = x.get<int64_t>(A_mdeg, g.n + 1);
+  a.mpos = x.get<int64_t>(A_mpos, g.n + 1);
+  a.mcrow = x.get<int32_t>(A_mcrow, nch + 2);
+  a.toff = x.get<int64_t>(A_toff, ncomm + 1);
+  a.hidx = x.get<int32_t>(A_hidx, g.nnz);
+  a.hw = x.get<float>(A_hw, g.nnz);
+  a.rowlen = x.get<int32_t>(A_rowlen, ncomm + 1);
+  a.pkey = x.get<unsigned long long>(A_pkey, g.nnz);
+  a.pval = x.get<double>(A_pval, g.nnz);
+  a.pcnt_item = x.get<int32_t>(A_pcnt_item, nch + 1);
+  a.pcnt = x.get<int32_t>(A_pcnt, ncomm + 1);
+  a.tcap = x.get<int64_t>(A_tcap, ncomm + 1);
+  a.tstart = x.get<int64_t>(A_tstart, ncomm + 1);
+  const Slot so = outbuf ? G1_off : G0_off, si = outbuf ? G1_idx : G0_idx, sw = outbuf ? G1_w : G0_w,
+             sc = outbuf ? G1_crow : G0_crow;
+  a.out_off = x.get<int64_t>(so, ncomm + 1);
+  a.out_K = Kout;
+
+  x.zero(a.cnt, ncomm + 1);
+  agg_count(a, x.s);
+  scan_i32(x, a.cnt, a.coff, ncomm + 1);
+  const int64_t M = x.read(&a.coff[ncomm]);
+  x.zero(a.cnt, ncomm + 1);
+  agg_scatter(a, x.s);
+  agg_mdeg(a, M, x.s);
+  x.launched("agg_scatter");
+  scan_i64(x, a.mdeg, a.mpos, M + 1);
+  chunk_start_rows(a.mpos, M, g.nnz, a.mcrow, x.s);
+  agg_toff(a, x.s);
+  x.zero(a.rowlen, ncomm + 1);
+  x.zero(a.pcnt, ncomm + 1);
+  agg_items(a, M, x.s);
+  agg_caps(a, x.s);
+  x.launched("agg_items");
+  scan_i64(x, a.tcap, a.tstart, ncomm + 1);
+  const int64_t tc = x.read(&a.tstart[ncomm]);
+  if (tc > 0) {
+    int *tk = x.get<int>(A_tkeys, tc);
+    double *tv = x.get<double>(A_tvals, tc);
+    fill_i32(tk, -1, tc, x.s);
+    x.zero(tv, tc);
+    agg_part_insert(a, tk, tv, x.s);
+    agg_part_emit(a, tk, tv, tc, x.s);
+    x.launched("agg_parts");
+  }
+  scan_i32_i64(x, a.rowlen, a.out_off, ncomm + 1);
+  const int64_t nnz2 = x.read(&a.out_off[ncomm]);
+  const int64_t nch2 = ceil_div(std::max<int64_t>(nnz2, 1), kChunk);
+  a.out_idx = x.get<int32_t>(si, nnz2);
+  a.out_w = x.get<float>(sw, nnz2);
+  a.out_crow = x.get<int32_t>(sc, nch2 + 2);
+  chunk_start_rows(a.out_off, ncomm, nnz2, a.out_crow, x.s);
+  if (Kout) x.zero(Kout, ncomm);
+  agg_compact(a, nnz2, x.s);
+  x.launched("agg_compact");
+  Level o{ncomm, nnz2, a.out_off, a.out_idx, a.out_w, a.out_crow};
+  return o;
+}
+
+// The pass loop of Alg. "leiden".  On entry the level arrays hold the
+// previous membership (L_C), K (L_K), Sigma (L_S), changed flags (L_dC),
+// affected flags (L_U) and range flags (L_rng) for the level-0 graph g0.
+// On exit `out` (n) holds dense labels.
+void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool track, int32_t *out,
+              leiden_stats *st, Timer &tm) {
+  const int64_t n = g0.n;
+  DevScal *sc = x.scal();
+  int32_t *C = x.get<int32_t>(L_C, n);
+  double *K = x.get<double>(L_K, n);
+  double *S = x.get<double>(L_S, n);
+  double *S2 = x.get<double>(L_S2, n);
+  uint8_t *dC = x.get<uint8_t>(L_dC, n);
+  uint8_t *dC2 = x.get<uint8_t>(L_dC2, n);
+  uint8_t *U = x.get<uint8_t>(L_U, n);
+  uint8_t *rng = x.get<uint8_t>(L_rng, n);
+  int32_t *CB = x.get<int32_t>(L_CB, n);
+  int32_t *Ctop = x.get<int32_t>(L_Ctop, n);
+  int32_t *prop = x.get<int32_t>(L_prop, n);
+  int32_t *from = x.get<int32_t>(L_from, n);
+  double *gp = x.get<double>(L_gp, n);
+  double *gi = p.sync_mode ? x.get<double>(L_gi, n) : nullptr;
+  int32_t *Sz = x.get<int32_t>(L_Sz, n);
+  int32_t *rep = x.get<int32_t>(L_rep, n + 1);
+  const int NS = std::max(1, std::min(p.nslices, kMaxSlices));
+  int32_t *lists = x.get<int32_t>(L_lists, n);
+  int32_t *region = x.get<int32_t>(L_region, NS * kNB + 1);
+  int32_t *counts = x.get<int32_t>(L_scnt, NS * kNB + NS);
+  int32_t *scnt = counts + NS * kNB;
+  int32_t *vbs = x.get<int32_t>(L_vbs, n);
+  int32_t *soff = x.get<int32_t>(L_soff, NS + 1);
+  int32_t *sfill = x.get<int32_t>(L_sfill, NS);
+  double *tiles = x.get<double>(L_tiles, n / 256 + 2);
+
+  if (p.refine_variant == 1) {
+    fill_u8(dC, 1, n, x.s);
+    track = false;
+  }
+  if (st) {
+    x.zero(&sc->nz, 1);
+    count_nonzero_u8(U, n, &sc->nz, x.s);
+    x.launched("count");
+    st->affected = (int64_t)x.read(&sc->nz);
+  }
+  iota_i32(Ctop, n, x.s);
+  fill_i32(prop, -1, n, x.s);
+  x.launched("core init");
+  tm.mark(CAT_OTHER);
+
+  Level g = g0;
+  int curbuf = -1;  // -1: the level-0 graph
+  double tau = p.tau0;
+  int pass = 0;
+  for (pass = 0; pass < p.max_passes; ++pass) {
+    const int64_t nl = g.n;
+    const Layout B = level_layout(x, g, NS, region, counts, scnt, soff, sfill, vbs);
+    const Hub hub = hub_tables(x, B.nhub, B.nhub > 0 ? max_degree(x, g) : 0);
+    if (pass > 0) fill_u8(rng, 1, nl, x.s);
+    const double Tp = tau * M2 * M2 / 2.0;
+
+    MoveArgs ma;
+    memset(&ma, 0, sizeof(ma));
+    ma.n = nl; ma.off = g.off; ma.idx = g.idx; ma.w = g.w;
+    ma.C = C; ma.K = K; ma.Sig = S; ma.dC = dC; ma.U = U; ma.rng = rng; ma.M2 = M2;
+    ma.track = (track && pass == 0) ? 1 : 0;
+    ma.prop = prop; ma.from = from; ma.gp = gp; ma.gi = gi;
+    ma.lists = lists; ma.region = region; ma.counts = counts; ma.nsl = NS; ma.vbyslice = vbs;
+    ma.gain = gi ? nullptr : &sc->gain; ma.moves = &sc->moves;
+    ma.hub_keys = hub.keys; ma.hub_vals = hub.vals; ma.hub_cap = hub.cap; ma.hub_blocks = hub.blocks;
+    int li = 0;
+    int64_t moves_total = 0;
+    tm.mark(CAT_OTHER);
+    for (int it = 0; it < p.max_iter; ++it) {
+      x.zero(counts, NS * kNB);
+      x.zero(&sc->gain, 1);
+      x.zero(&sc->moves, 1);
+      if (gi) x.zero(gi, nl);
+      for (int sl = 0; sl < NS; ++sl) {
+        ma.s = sl;
+        ma.vbeg = B.soff[sl];
+        ma.vend = B.soff[sl + 1];
+        move_frontier(ma, x.s);
+        move_propose(ma, B.region.data(), x.s);
+        move_apply(ma, B.region.data(), x.s);
+      }
+      if (gi) tiled_sum(gi, nl, tiles, &sc->gain, x.s);
+      x.launched("move iteration");
+      struct {
+        double gain;
+        unsigned long long moves;
+      } r;
+      x.check(hipMemcpyAsync(x.pin(), &sc->gain, sizeof(r), hipMemcpyDeviceToHost, x.s), "D2H");
+      x.check(hipStreamSynchronize(x.s), "sync");
+      memcpy(&r, x.pin(), sizeof(r));
+      moves_total += (int64_t)r.moves;
+      li = it + 1;
+      if (r.gain <= Tp) break;
+    }
+    tm.mark(CAT_MOVE);
+    if (st && pass < LEIDEN_MAX_PASSES) {
+      st->move_iters[pass] = li;
+      st->level_vertices[pass] = nl;
+      st->level_entries[pass] = g.nnz;
+      if (pass == 0) {
+        st->moves_pass0 = moves_total;
+        x.zero(&sc->nz, 1);
+        count_nonzero_u8(dC, nl, &sc->nz, x.s);
+        x.launched("count");
+        st->changed = (int64_t)x.read(&sc->nz);
+      }
+    }
+    // subset renumber, bounds, break, refine
+    subset_renumber(nl, C, rep, S, S2, dC, dC2, x.s);
+    std::swap(S, S2);
+    std::swap(dC, dC2);
+    x.launched("subset_renumber");
+    RefineArgs ra;
+    memset(&ra, 0, sizeof(ra));
+    ra.n = nl; ra.off = g.off; ra.idx = g.idx; ra.w = g.w;
+    ra.C = C; ra.CB = CB; ra.K = K; ra.Sig = S; ra.dC = dC; ra.S = Sz; ra.M2 = M2;
+    ra.prop = prop; ra.gp = gp; ra.lists = lists; ra.region = region; ra.counts = counts; ra.nsl = NS;
+    ra.refined = &sc->refined;
+    ra.hub_keys = hub.keys; ra.hub_vals = hub.vals; ra.hub_cap = hub.cap; ra.hub_blocks = hub.blocks;
+    x.zero(counts, NS * kNB);
+    x.zero(&sc->refined, 1);
+    refine_break(ra, x.s);
+    x.launched("break");
+    for (int sl = 0; sl < NS; ++sl) {
+      ra.s = sl;
+      refine_propose(ra, B.region.data(), x.s);
+      refine_accept(ra, B.region.data(), x.s);
+    }
+    x.launched("refine sweep");
+    const int rounds = 1;
+    tm.mark(CAT_REFINE);
+    if (st && pass < LEIDEN_MAX_PASSES) {
+      st->refine_rounds[pass] = rounds;
+      st->refined_vertices[pass] = (int64_t)x.read(&sc->refined);
+      st->passes = pass + 1;
+    }
+    if ((pass > 0 || p.refine_variant == 2) && li <= 1) {
+      if (st && pass < LEIDEN_MAX_PASSES) {
+        // communities of this level, for the statistics only
+        int32_t *tmpC = x.get<int32_t>(L_CB, nl);
+        x.copy(tmpC, C, nl);
+        st->communities[pass] = renumber_dense(x, tmpC, nl, nl);
+      }
+      tm.mark(CAT_OTHER);
+      break;
+    }
+    const int64_t ncomm = renumber_dense(x, C, nl, nl);
+    if (st && pass < LEIDEN_MAX_PASSES) st->communities[pass] = ncomm;
+    if (p.agg_tol < 1.0 && (double)ncomm / (double)nl > p.agg_tol) {
+      tm.mark(CAT_OTHER);
+      break;
+    }
+    gather_map(Ctop, C, n, x.s);  // dendrogram lookup
+    x.launched("lookup");
+    tm.mark(CAT_OTHER);
+    const int outbuf = (curbuf == 0) ? 1 : 0;
+    g = aggregate_level(x, g, C, ncomm, outbuf, K);
+    curbuf = outbuf;
+    tm.mark(CAT_AGG);
+    x.copy(S, K, ncomm);
+    fill_u8(U, 1, ncomm, x.s);
+    iota_i32(C, ncomm, x.s);
+    fill_u8(dC, 1, ncomm, x.s);
+    x.launched("pass reset");
+    tau = tau / p.tol_drop;
+  }
+  if (st && pass >= p.max_passes) st->passes = p.max_passes;
+  gather_map(Ctop, C, n, x.s);
+  renumber_dense(x, Ctop, n, n);
+  x.copy(out, Ctop, n);
+  x.launched("final lookup");
+  tm.mark(CAT_OTHER);
+}
+
+}  // namespace
+
+namespace {
+leiden_status run_guarded(Workspace &w, const std::function<void()> &f) {
+  try {
+    f();
+    return LEIDEN_OK;
+  } catch (const Fail &e) {
+    return e.st;
+  } catch (const std::bad_alloc &) {
+    w.err = "host allocation failed";
+    return LEIDEN_ENOMEM;
+  } catch (...) {
+    w.err = "unexpected error";
+    return LEIDEN_EHIP;
+  }
+}
+
+// Sort rows of a CSR in place (keys = neighbour ids, values = weights).
+void sort_rows(Ctx &x, int64_t n, int64_t nnz, int64_t *off, int32_t *idx, float *w, int32_t *idx2, float *w2) {
+  if (nnz == 0) return;
+  size_t tb = seg_sort_i32_f32(nullptr, 0, idx, idx2, w, w2, nnz, n, off, x.s);
+  seg_sort_i32_f32(x.tmp(tb), tb, idx, idx2, w, w2, nnz, n, off, x.s);
+  x.launched("segmented sort");
+  x.copy(idx, idx2, nnz);
+  x.copy(w, w2, nnz);
+}
+
+Level handle_level(leiden_handle *h) {
+  return Level{h->n, h->nnz, (const int64_t *)h->g_off.p, (const int32_t *)h->g_idx.p,
+               (const float *)h->g_w.p, (const int32_t *)h->g_crow.p};
+}
+
+void refresh_crow(Ctx &x, leiden_handle *h) {
+  const int64_t nch = ceil_div(std::max<int64_t>(h->nnz, 1), kChunk);
+  x.ensure(h->g_crow, (size_t)(nch + 2) * sizeof(int32_t));
+  chunk_start_rows((const int64_t *)h->g_off.p, h->n, h->nnz, (int32_t *)h->g_crow.p, x.s);
+  x.launched("chunk_start_rows");
+}
+
+bool valid_params(const leiden_params *p) {
+  return p && p->tau0 >= 0 && p->tol_drop > 0 && p->agg_tol > 0 && p->max_iter >= 1 &&
+         p->max_passes >= 1 && p->max_passes <= LEIDEN_MAX_PASSES && (p->sync_mode == 0 || p->sync_mode == 1) &&
+         p->refine_variant >= 0 && p->refine_variant <= 2 && p->nslices >= 1 && p->nslices <= kMaxSlices;
+}
+
+}  // namespace
+
+// ============================ C ABI =========================================
+extern "C" {
+
+void leiden_default_params(leiden_params *p) {
+  if (!p) return;
+  p->tau0 = 0.01;
+  p->tol_drop = 10.0;
+  p->agg_tol = 1.0;
+  p->max_iter = 20;
+  p->max_passes = 10;
+  p->sync_mode = 0;
+  p->refine_variant = 0;
+  p->nslices = 16;
+}
+
+const char *leiden_strerror(int32_t status) {
+  switch (status) {
+    case LEIDEN_OK: return "ok";
+    case LEIDEN_EINVAL: return "invalid argument";
+    case LEIDEN_ENOMEM: return "out of device memory";
+    case LEIDEN_ESTATE: return "no community state (run leiden_static or leiden_set_state first)";
+    case LEIDEN_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char *leiden_last_error(const leiden_handle *h) { return h ? h->w.err.c_str() : ""; }
+int64_t leiden_num_vertices(const leiden_handle *h) { return h ? h->n : -1; }
+int64_t leiden_num_entries(const leiden_handle *h) { return h ? h->nnz : -1; }
+
+leiden_status leiden_create(int64_t n, int64_t nnz, const int64_t *offsets, const int32_t *indices,
+                            const float *weights, const leiden_params *params, void *stream,
+                            leiden_handle **out) {
+  if (!out || n < 0 || nnz < 0 || n > INT32_MAX - 1 || !offsets || (nnz > 0 && (!indices || !weights)))
+    return LEIDEN_EINVAL;
+  if (params && !valid_params(params)) return LEIDEN_EINVAL;
+  *out = nullptr;
+  leiden_handle *h = new (std::nothrow) leiden_handle();
+  if (!h) return LEIDEN_ENOMEM;
+  h->n = n;
+  h->nnz = nnz;
+  if (params) h->prm = *params;
+  else leiden_default_params(&h->prm);
+  Ctx x{&h->w, (hipStream_t)stream};
+  leiden_status st = run_guarded(h->w, [&] {
+    x.ensure(h->g_off, (size_t)(n + 1) * sizeof(int64_t));
+    x.ensure(h->g_idx, (size_t)std::max<int64_t>(nnz, 1) * sizeof(int32_t));
+    x.ensure(h->g_w, (size_t)std::max<int64_t>(nnz, 1) * sizeof(float));
+    x.copy((int64_t *)h->g_off.p, offsets, n + 1);
+    x.copy((int32_t *)h->g_idx.p, indices, nnz);
+    x.copy((float *)h->g_w.p, weights, nnz);
+    DevScal *sc = x.scal();
+    x.zero(&sc->err, 1);
+    check_offsets((const int64_t *)h->g_off.p, n, nnz, &sc->err, x.s);
+    x.launched("check_offsets");
+    if (x.read(&sc->err)) x.invalid("offsets are not a valid CSR of nnz entries");
+    x.ensure(h->t_idx, (size_t)std::max<int64_t>(nnz, 1) * sizeof(int32_t));
+    x.ensure(h->t_w, (size_t)std::max<int64_t>(nnz, 1) * sizeof(float));
+    sort_rows(x, n, nnz, (int64_t *)h->g_off.p, (int32_t *)h->g_idx.p, (float *)h->g_w.p,
+              (int32_t *)h->t_idx.p, (float *)h->t_w.p);
+    refresh_crow(x, h);
+    check_rows_chunked((const int64_t *)h->g_off.p, (const int32_t *)h->g_idx.p, (const float *)h->g_w.p, n,
+                       nnz, (const int32_t *)h->g_crow.p, &sc->err, x.s);
+    x.launched("check_rows");
+    if (x.read(&sc->err))
+      x.invalid("graph has an id out of range, a non-positive or non-finite weight, or a repeated entry");
+  });
+  if (st != LEIDEN_OK) {
+    delete h;
+    return st;
+  }
+  *out = h;
+  return LEIDEN_OK;
+}
+
+leiden_status leiden_destroy(leiden_handle *h) {
+  if (!h) return LEIDEN_EINVAL;
+  (void)hipDeviceSynchronize();
+  delete h;
+  return LEIDEN_OK;
+}
+
+leiden_status leiden_set_params(leiden_handle *h, const leiden_params *params) {
+  if (!h || !valid_params(params)) return LEIDEN_EINVAL;
+  h->prm = *params;
+  return LEIDEN_OK;
+}
+
+leiden_status leiden_static(leiden_handle *h, int32_t *membership_out, double *q_out, leiden_stats *stats,
+                            void *stream) {
+  if (!h) return LEIDEN_EINVAL;
+  if (stats) memset(stats, 0, sizeof(*stats));
+  Ctx x{&h->w, (hipStream_t)stream};
+  return run_guarded(h->w, [&] {
+    Timer tm(x, stats != nullptr);
+    tm.mark(CAT_OTHER);
+    const int64_t n = h->n;
+    x.ensure(h->C, (size_t)std::max<int64_t>(n, 1) * sizeof(int32_t));
+    x.ensure(h->K, (size_t)std::max<int64_t>(n, 1) * sizeof(double));
+    x.ensure(h->Sig, (size_t)std::max<int64_t>(n, 1) * sizeof(double));
+    int32_t *C = (int32_t *)h->C.p;
+    double *K = (double *)h->K.p;
+    double *Sig = (double *)h->Sig.p;
+    const Level g = handle_level(h);
+    DevScal *sc = x.scal();
+    x.zero(K, n);
+    row_sums(g.off, g.w, n, g.nnz, g.crow, K, x.s);
+    x.zero(sc->acc, 4);
+    modularity_comm(K, n, sc->acc, x.s);
+    x.launched("static init");
+    const double M2 = x.read(&sc->acc[1]);
+    if (n > 0) {
+      iota_i32(x.get<int32_t>(L_C, n), n, x.s);
+      x.copy(x.get<double>(L_K, n), K, n);
+      x.copy(x.get<double>(L_S, n), K, n);
+      fill_u8(x.get<uint8_t>(L_dC, n), 1, n, x.s);
+      fill_u8(x.get<uint8_t>(L_U, n), 1, n, x.s);
+      fill_u8(x.get<uint8_t>(L_rng, n), 1, n, x.s);
+      x.launched("static init");
+      run_core(x, h->prm, g, M2, false, C, stats, tm);
+      x.zero(Sig, n);
+      scatter_add(K, C, n, Sig, x.s);
+      x.launched("sigma");
+    }
+    h->M2 = M2;
+    h->has_state = true;
+    if (membership_out) x.copy(membership_out, (const int32_t *)C, n);
+    if (q_out) *q_out = (n > 0) ? modularity_dev(x, g, C) : 0.0;
+    tm.mark(CAT_OTHER);
+    tm.finish(stats);
+    x.check(hipStreamSynchronize(x.s), "sync");
+  });
+}
+
+leiden_status leiden_update(leiden_handle *h, const leiden_batch *batch, int32_t mode, int32_t *membership_out,
+                            double *q_out, leiden_stats *stats, const leiden_trace *trace, void *stream) {
+  if (!h || !batch) return LEIDEN_EINVAL;
+  if (mode != LEIDEN_ND && mode != LEIDEN_DS && mode != LEIDEN_DF) return LEIDEN_EINVAL;
+  if (batch->n_del < 0 || batch->n_ins < 0) return LEIDEN_EINVAL;
+  if (batch->n_del > 0 && (!batch->del_u || !batch->del_v)) return LEIDEN_EINVAL;
+  if (batch->n_ins > 0 && (!batch->ins_u || !batch->ins_v || !batch->ins_w)) return LEIDEN_EINVAL;
+  if (!h->has_state) {
+    h->w.err = "update before leiden_static or leiden_set_state";
+    return LEIDEN_ESTATE;
+  }
+  if (stats) memset(stats, 0, sizeof(*stats));
+  Ctx x{&h->w, (hipStream_t)stream};
+  return run_guarded(h->w, [&] {
+    Timer tm(x, stats != nullptr);
+    tm.mark(CAT_OTHER);
+    const int64_t n = h->n;
+    DevScal *sc = x.scal();
+    // ---- validate and apply the batch (G^{t-1} -> G^t) ----
+    BatchArgs b;
+    memset(&b, 0, sizeof(b));
+    b.n = n;
+    b.nnz = h->nnz;
+    b.off = (const int64_t *)h->g_off.p;
+    b.idx = (const int32_t *)h->g_idx.p;
+    b.w = (const float *)h->g_w.p;
+    b.nd = batch->n_del;
+    b.ni = batch->n_ins;
+    b.du = batch->del_u; b.dv = batch->del_v;
+    b.iu = batch->ins_u; b.iv = batch->ins_v; b.iw = batch->ins_w;
+    b.E = 2 * (b.nd + b.ni);
+    const int64_t E = b.E;
+    b.keys = x.get<unsigned long long>(B_keys, E);
+    b.vals = x.get<int32_t>(B_vals, E);
+    b.skeys = x.get<unsigned long long>(B_skeys, E);
+    b.svals = x.get<int32_t>(B_svals, E);
+    b.ew = x.get<float>(B_ew, E);
+    b.err = &sc->err;
+    b.bstart = x.get<int64_t>(B_bstart, n);
+    b.bcnt = x.get<int32_t>(B_bcnt, n);
+    b.dcnt = x.get<int32_t>(B_dcnt, n);
+    b.icnt = x.get<int32_t>(B_icnt, n);
+    b.isdel = x.get<int32_t>(B_isdel, E + 1);
+    b.delpre = x.get<int32_t>(B_delpre, E + 1);
+    b.newdeg = x.get<int64_t>(B_newdeg, n + 1);
+    b.crow = (const int32_t *)h->g_crow.p;
+    x.zero(&sc->err, 1);
+    x.zero(b.bcnt, n);
+    x.zero(b.dcnt, n);
+    x.zero(b.icnt, n);
+    batch_build(b, x.s);
+    x.launched("batch_build");
+    if (E > 0) {
+      size_t tb = sort_pairs_u64_i32(nullptr, 0, b.keys, b.skeys, b.vals, b.svals, E, x.s);
+      sort_pairs_u64_i32(x.tmp(tb), tb, b.keys, b.skeys, b.vals, b.svals, E, x.s);
+      x.launched("batch sort");
+    }
+    batch_dups_rows(b, x.s);
+    x.launched("batch_dups");
+    const int32_t err = x.read(&sc->err);
+    if (err) {
+      std::string why;
+      if (err & 1) why += " id out of range;";
+      if (err & 2) why += " self-loop;";
+      if (err & 4) why += " repeated edge;";
+      if (err & 8) why += " deletion of a missing edge;";
+      if (err & 16) why += " insertion of an existing edge;";
+      if (err & 32) why += " non-positive or non-finite weight;";
+      x.invalid("invalid batch:" + why);
+    }
+    x.ensure(h->t_off, (size_t)(n + 1) * sizeof(int64_t));
+    b.newoff = (int64_t *)h->t_off.p;
+    batch_newdeg(b, x.s);
+    scan_i64(x, b.newdeg, b.newoff, n + 1);
+    scan_i32(x, b.isdel, b.delpre, E + 1);
+    const int64_t nnz_new = x.read(&b.newoff[n]);
+    x.ensure(h->t_idx, (size_t)std::max<int64_t>(nnz_new, 1) * sizeof(int32_t));
+    x.ensure(h->t_w, (size_t)std::max<int64_t>(nnz_new, 1) * sizeof(float));
+    b.nidx = (int32_t *)h->t_idx.p;
+    b.nw = (float *)h->t_w.p;
+    batch_apply(b, x.s);
+    x.launched("batch_apply");
+    std::swap(h->g_off, h->t_off);
+    std::swap(h->g_idx, h->t_idx);
+    std::swap(h->g_w, h->t_w);
+    h->nnz = nnz_new;
+    refresh_crow(x, h);
+    tm.mark(CAT_APPLY);
+
+    // ---- marking, changedCommunities, updateWeights ----
+    const Level g = handle_level(h);
+    uint8_t *dV = x.get<uint8_t>(L_U, n);
+    uint8_t *rng = x.get<uint8_t>(L_rng, n);
+    uint8_t *dC = x.get<uint8_t>(L_dC, n);
+    x.zero(dV, n);
+    x.zero(rng, n);
+    x.zero(dC, n);
+    MarkArgs m;
+    memset(&m, 0, sizeof(m));
+    m.n = n;
+    m.off = g.off;
+    m.idx = g.idx;
+    m.E = E;
+    m.nd2 = 2 * b.nd;
+    m.skeys = b.skeys;
+    m.svals = b.svals;
+    m.ew = b.ew;
+    m.C = (const int32_t *)h->C.p;
+    m.K = (const double *)h->K.p;
+    m.Sig = (const double *)h->Sig.p;
+    m.M2 = h->M2;
+    m.dV = dV;
+    m.rng = rng;
+    m.dC = dC;
+    if (mode == LEIDEN_ND) {
+      fill_u8(dV, 1, n, x.s);
+      fill_u8(rng, 1, n, x.s);
+      mark_changed(m, x.s);
+    } else if (mode == LEIDEN_DF) {
+      mark_df(m, x.s);
+      fill_u8(rng, 1, n, x.s);
+    } else {
+      m.dE = x.get<uint8_t>(M_dE, n);
+      m.dCm = x.get<uint8_t>(M_dCm, n);
+      m.k2 = x.get<unsigned long long>(M_k2, E);
+      m.k2s = x.get<unsigned long long>(M_k2s, E);
+      m.v2 = x.get<double>(M_v2, E);
+      m.v2s = x.get<double>(M_v2s, E);
+      m.list = x.get<int32_t>(M_list, n);
+      m.count = &sc->list_count;
+      x.zero(m.dE, n);
+      x.zero(m.dCm, n);
+      x.zero(m.count, 1);
+      mark_ds_del(m, x.s);
+      mark_ds_keys(m, x.s);
+      if (E > 0) {
+        size_t tb = sort_pairs_u64_f64(nullptr, 0, m.k2, m.k2s, m.v2, m.v2s, E, x.s);
+        sort_pairs_u64_f64(x.tmp(tb), tb, m.k2, m.k2s, m.v2, m.v2s, E, x.s);
+      }
+      mark_ds_best(m, x.s);
+      mark_ds_expand(m, x.s);
+    }
+    x.launched("marking");
+    if (trace) {
+      if (trace->affected) x.copy(trace->affected, (const uint8_t *)dV, n);
+      if (trace->in_range) x.copy(trace->in_range, (const uint8_t *)rng, n);
+      if (trace->changed) x.copy(trace->changed, (const uint8_t *)dC, n);
+    }
+    x.zero(&sc->m2delta, 1);
+    update_weights(m, (double *)h->K.p, (double *)h->Sig.p, &sc->m2delta, x.s);
+    x.launched("update_weights");
+    h->M2 += x.read(&sc->m2delta);
+    tm.mark(CAT_MARK);
+
+    // ---- the pass loop from the previous membership ----
+    if (n > 0) {
+      x.copy(x.get<int32_t>(L_C, n), (const int32_t *)h->C.p, n);
+      x.copy(x.get<double>(L_K, n), (const double *)h->K.p, n);
+      x.copy(x.get<double>(L_S, n), (const double *)h->Sig.p, n);
+      run_core(x, h->prm, g, h->M2, true, (int32_t *)h->C.p, stats, tm);
+      x.zero((double *)h->Sig.p, n);
+      scatter_add((const double *)h->K.p, (const int32_t *)h->C.p, n, (double *)h->Sig.p, x.s);
+      x.launched("sigma");
+    }
+    if (membership_out) x.copy(membership_out, (const int32_t *)h->C.p, n);
+    if (q_out) *q_out = (n > 0) ? modularity_dev(x, g, (const int32_t *)h->C.p) : 0.0;
+    tm.mark(CAT_OTHER);
+    tm.finish(stats);
+    x.check(hipStreamSynchronize(x.s), "sync");
+  });
+}
+
+leiden_status leiden_modularity(int64_t n, const int64_t *offsets, const int32_t *indices, const float *weights,
+                                const int32_t *membership, double *q_out, void *stream) {
+  if (n < 0 || !q_out || (n > 0 && (!offsets || !membership))) return LEIDEN_EINVAL;
+  Workspace w;
+  Ctx x{&w, (hipStream_t)stream};
+  return run_guarded(w, [&] {
+    if (n == 0) { *q_out = 0.0; return; }
+    const int64_t nnz = x.read(offsets + n);
+    if (nnz > 0 && (!indices || !weights)) x.invalid("null edge arrays");
+    DevScal *sc = x.scal();
+    x.zero(&sc->err, 1);
+    check_labels(membership, n, n, &sc->err, x.s);
+    x.launched("check_labels");
+    if (x.read(&sc->err)) x.invalid("membership label out of range");
+    int32_t *crow = x.get<int32_t>(Q_crow, ceil_div(std::max<int64_t>(nnz, 1), kChunk) + 2);
+    chunk_start_rows(offsets, n, nnz, crow, x.s);
+    Level g{n, nnz, offsets, indices, weights, crow};
+    *q_out = modularity_dev(x, g, membership);
+  });
+}
+
+leiden_status leiden_aggregate(int64_t n, const int64_t *offsets, const int32_t *indices, const float *weights,
+                               const int32_t *membership, int64_t ncomm, int64_t *out_offsets,
+                               int32_t *out_indices, float *out_weights, int64_t *nnz_out, void *stream) {
+  if (n < 0 || ncomm < 0 || !nnz_out || !out_offsets || (n > 0 && (!offsets || !membership))) return LEIDEN_EINVAL;
+  Workspace w;
+  Ctx x{&w, (hipStream_t)stream};
+  return run_guarded(w, [&] {
+    const int64_t nnz = (n > 0) ? x.read(offsets + n) : 0;
+    DevScal *sc = x.scal();
+    x.zero(&sc->err, 1);
+    check_labels(membership, n, ncomm, &sc->err, x.s);
+    x.launched("check_labels");
+    if (x.read(&sc->err)) x.invalid("membership label outside [0, ncomm)");
+    int32_t *crow = x.get<int32_t>(Q_crow, ceil_div(std::max<int64_t>(nnz, 1), kChunk) + 2);
+    chunk_start_rows(offsets, n, nnz, crow, x.s);
+    Level g{n, nnz, offsets, indices, weights, crow};
+    const Level o = aggregate_level(x, g, membership, ncomm, 0, nullptr);
+    x.copy(out_offsets, o.off, ncomm + 1);
+    if (o.nnz > 0) {
+      if (!out_indices || !out_weights) x.invalid("null output arrays");
+      x.copy(out_indices, o.idx, o.nnz);
+      x.copy(out_weights, o.w, o.nnz);
+    }
+    *nnz_out = o.nnz;
+    x.check(hipStreamSynchronize(x.s), "sync");
+  });
+}
+
+leiden_status leiden_get_graph(leiden_handle *h, int64_t *offsets, int32_t *indices, float *weights,
+                               int64_t *nnz, void *stream) {
+  if (!h) return LEIDEN_EINVAL;
+  Ctx x{&h->w, (hipStream_t)stream};
+  return run_guarded(h->w, [&] {
+    if (nnz) *nnz = h->nnz;
+    if (offsets) x.copy(offsets, (const int64_t *)h->g_off.p, h->n + 1);
+    if (indices) x.copy(indices, (const int32_t *)h->g_idx.p, h->nnz);
+    if (weights) x.copy(weights, (const float *)h->g_w.p, h->nnz);
+    x.check(hipStreamSynchronize(x.s), "sync");
+  });
+}
+
+leiden_status leiden_get_state(leiden_handle *h, int32_t *membership, double *K, double *Sigma, double *m2,
+                               void *stream) {
+  if (!h) return LEIDEN_EINVAL;
+  if (!h->has_state) return LEIDEN_ESTATE;
+  Ctx x{&h->w, (hipStream_t)stream};
+  return run_guarded(h->w, [&] {
+    if (membership) x.copy(membership, (const int32_t *)h->C.p, h->n);
+    if (K) x.copy(K, (const double *)h->K.p, h->n);
+    if (Sigma) x.copy(Sigma, (const double *)h->Sig.p, h->n);
+    if (m2) *m2 = h->M2;
+    x.check(hipStreamSynchronize(x.s), "sync");
+  });
+}
+
+leiden_status leiden_set_state(leiden_handle *h, const int32_t *membership, void *stream) {
+  if (!h || (h->n > 0 && !membership)) return LEIDEN_EINVAL;
+  Ctx x{&h->w, (hipStream_t)stream};
+  return run_guarded(h->w, [&] {
+    const int64_t n = h->n;
+    DevScal *sc = x.scal();
+    x.zero(&sc->err, 1);
+    check_labels(membership, n, n, &sc->err, x.s);
+    x.launched("check_labels");
+    if (x.read(&sc->err)) x.invalid("membership label out of range");
+    x.ensure(h->C, (size_t)std::max<int64_t>(n, 1) * sizeof(int32_t));
+    x.ensure(h->K, (size_t)std::max<int64_t>(n, 1) * sizeof(double));
+    x.ensure(h->Sig, (size_t)std::max<int64_t>(n, 1) * sizeof(double));
+    const Level g = handle_level(h);
+    x.copy((int32_t *)h->C.p, membership, n);
+    x.zero((double *)h->K.p, n);
+    row_sums(g.off, g.w, n, g.nnz, g.crow, (double *)h->K.p, x.s);
+    x.zero((double *)h->Sig.p, n);
+    scatter_add((const double *)h->K.p, (const int32_t *)h->C.p, n, (double *)h->Sig.p, x.s);
+    x.zero(sc->acc, 4);
+    modularity_comm((const double *)h->K.p, n, sc->acc, x.s);
+    x.launched("set_state");
+    h->M2 = x.read(&sc->acc[1]);
+    h->has_state = true;
+  });
+}
+
+}  // extern "C"

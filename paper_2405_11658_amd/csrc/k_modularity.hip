@@ -1,0 +1,74 @@
+// Modularity, Eq. 1: Q = sum_c [sigma_c / 2m - (Sigma_c / 2m)^2], with sigma_c the
+// weight of stored entries inside c and Sigma_c the total weight of c.  One
+// chunked pass over the CSR accumulates the internal weight and the per-row
+// sums scattered to communities (FP64); a second pass over communities sums
+// Sigma_c and (Sigma_c / 2m)^2.
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace lk {
+
+__global__ __launch_bounds__(256) void k_mod_edges(const int64_t *off, const int32_t *idx, const float *w,
+                                                   const int32_t *crow, int64_t nnz, const int32_t *C,
+                                                   double *acc, double *S) {
+  __shared__ int rowof[kChunk];
+  __shared__ double ksum[kChunk];
+  __shared__ int sh[16];
+  __shared__ double sd[16];
+  const int64_t q0 = (int64_t)blockIdx.x * kChunk;
+  const int len = (int)min((int64_t)kChunk, nnz - q0);
+  chunk_rows<kChunk>(off, q0, len, crow[blockIdx.x], crow[blockIdx.x + 1], rowof, sh);
+  for (int t = threadIdx.x; t < kChunk; t += blockDim.x) ksum[t] = 0.0;
+  __syncthreads();
+  double sig = 0.0;
+  for (int t = threadIdx.x; t < len; t += blockDim.x) {
+    const int r = rowof[t];
+    const int64_t q = q0 + t;
+    const double x = (double)w[q];
+    if (C[idx[q]] == C[r]) sig += x;
+    int64_t s0 = off[r] - q0;
+    if (s0 < 0) s0 = 0;
+    atomicAdd(&ksum[s0], x);
+  }
+  sig = block_sum(sig, sd);
+  if (threadIdx.x == 0 && sig != 0.0) unsafeAtomicAdd(&acc[0], sig);
+  for (int t0 = 0; t0 < kChunk; t0 += blockDim.x) {
+    const int t = t0 + threadIdx.x;
+    const bool st = t < len && (t == 0 || rowof[t] != rowof[t - 1]);
+    const int c = st ? C[rowof[t]] : 0;
+    wave_peel_add_f64(S, c, st ? ksum[t] : 0.0, st);
+  }
+}
+
+void modularity_edges(const int64_t *off, const int32_t *idx, const float *w, const int32_t *crow,
+                      int64_t n, int64_t nnz, const int32_t *C, double *acc, double *S, hipStream_t s) {
+  (void)n;
+  if (nnz > 0) hipLaunchKernelGGL(k_mod_edges, (int)ceil_div(nnz, kChunk), 256, 0, s, off, idx, w, crow, nnz, C, acc, S);
+}
+
+__global__ __launch_bounds__(256) void k_mod_comm(const double *S, int64_t n, double *acc) {
+  __shared__ double sd[16];
+  double t = 0.0;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) t += S[c];
+  t = block_sum(t, sd);
+  if (threadIdx.x == 0 && t != 0.0) unsafeAtomicAdd(&acc[1], t);
+}
+void modularity_comm(const double *S, int64_t n, double *acc, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_mod_comm, flat_grid(n, 256, 1024), 256, 0, s, S, n, acc);
+}
+
+__global__ __launch_bounds__(256) void k_mod_comm_sq(const double *S, int64_t n, double M2, double *acc) {
+  __shared__ double sd[16];
+  double t = 0.0;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+    const double a = S[c] / M2;
+    t += a * a;
+  }
+  t = block_sum(t, sd);
+  if (threadIdx.x == 0 && t != 0.0) unsafeAtomicAdd(&acc[2], t);
+}
+void modularity_comm_sq(const double *S, int64_t n, double M2, double *acc, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_mod_comm_sq, flat_grid(n, 256, 1024), 256, 0, s, S, n, M2, acc);
+}
+
+}  // namespace lk

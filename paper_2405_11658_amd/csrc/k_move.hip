@@ -1,0 +1,448 @@
+// Local-moving phase (Alg. "leidenMove" with "scanCommunities", self=false),
+// executed on the GPU as sweeps over S vertex slices (hash of the id); the
+// slices of an iteration run in order, each synchronously:
+//   frontier  - unprocessed in-range vertices of the slice are marked
+//               processed (vertex pruning) and bucketed by degree;
+//   propose   - each frontier vertex builds its neighbour-community weight
+//               table and picks the community of best Eq. 2 gain (strictly
+//               positive, ties to the smaller id);
+//   apply     - a proposal d -> c is dropped when a neighbour of the same
+//               slice proposes the exact reverse move c -> d with priority
+//               (larger gain, then smaller id); accepted moves update C,
+//               Sigma (atomics), flag
+//               source and target communities as changed (dynamic runs) and
+//               mark the mover's neighbours unprocessed; dropped proposers stay
+//               unprocessed.
+// Degree buckets pick the table: registers of a 4/8/32-lane group (all-pairs
+// combine), an LDS table per wavefront or workgroup, or a global-memory table
+// per workgroup for hubs.
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace lk {
+
+__device__ __forceinline__ int bucket_of_d(int64_t deg) {
+  return deg <= 4 ? 0 : deg <= 8 ? 1 : deg <= 32 ? 2 : deg <= 256 ? 3 : deg <= 2048 ? 4 : 5;
+}
+
+__global__ __launch_bounds__(256) void k_slice_hist(const int64_t *off, int64_t n, int S, int32_t *counts,
+                                                    int32_t *slice_cnt) {
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = i0 + threadIdx.x;
+    int64_t deg = 0;
+    int sl = 0;
+    if (i < n) {
+      deg = off[i + 1] - off[i];
+      sl = slice_of(i, S);
+    }
+    wave_peel_inc(slice_cnt, sl, i < n);
+    wave_peel_inc(counts, sl * kNB + (deg > 0 ? bucket_of_d(deg) : 0), deg > 0);
+  }
+}
+void slice_hist(const int64_t *off, int64_t n, int S, int32_t *counts, int32_t *slice_cnt, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_slice_hist, flat_grid(n), 256, 0, s, off, n, S, counts, slice_cnt);
+}
+
+__global__ __launch_bounds__(256) void k_slice_scatter(int64_t n, int S, const int32_t *slice_off,
+                                                       int32_t *slice_fill, int32_t *vbyslice) {
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = i0 + threadIdx.x;
+    const int sl = i < n ? slice_of(i, S) : 0;
+    const int pos = wave_peel_inc(slice_fill, sl, i < n);
+    if (i < n) vbyslice[slice_off[sl] + pos] = (int32_t)i;
+  }
+}
+void slice_scatter(int64_t n, int S, const int32_t *slice_off, int32_t *slice_fill, int32_t *vbyslice,
+                   hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_slice_scatter, flat_grid(n), 256, 0, s, n, S, slice_off, slice_fill, vbyslice);
+}
+
+// Frontier of slice s: its unprocessed vertices become processed; in-range
+// ones with edges are bucketed by degree.  Proposals of the slice are reset.
+__global__ __launch_bounds__(256) void k_frontier(MoveArgs a) {
+  int32_t *counts = a.counts + a.s * kNB;
+  const int32_t *region = a.region + a.s * kNB;
+  for (int64_t t0 = a.vbeg + (int64_t)blockIdx.x * blockDim.x; t0 < a.vend; t0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = t0 + threadIdx.x;
+    int b = -1;
+    int i = 0;
+    if (t < a.vend) {
+      i = a.vbyslice[t];
+      a.prop[i] = -1;
+      if (a.U[i]) {
+        a.U[i] = 0;
+        if (a.rng[i]) {
+          const int64_t deg = a.off[i + 1] - a.off[i];
+          if (deg > 0) b = bucket_of_d(deg);
+        }
+      }
+    }
+    const int pos = wave_peel_inc(counts, b < 0 ? 0 : b, b >= 0);
+    if (b >= 0) a.lists[region[b] + pos] = i;
+  }
+}
+
+// ---- propose: small-degree groups (deg <= G), all-pairs combine in registers
+template <int G>
+__global__ __launch_bounds__(256) void k_propose_small(MoveArgs a, int b) {
+  const int count = a.counts[a.s * kNB + b];
+  const int32_t *list = a.lists + a.region[a.s * kNB + b];
+  const int gl = threadIdx.x & (G - 1);
+  // the loop runs in step for the whole wavefront (collectives stay uniform)
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwave = (int64_t)gridDim.x * blockDim.x / kWave;
+  const int gin = lane() / G;
+  for (int64_t v0 = wave * (kWave / G); v0 < count; v0 += nwave * (kWave / G)) {
+    const int64_t v = v0 + gin;
+    const bool valid = v < count;
+    const int i = valid ? list[v] : 0;
+    int deg = 0, d = 0;
+    int64_t e0 = 0;
+    if (valid) {
+      e0 = a.off[i];
+      deg = (int)(a.off[i + 1] - e0);
+      d = a.C[i];
+    }
+    int key = -1;
+    float wt = 0.0f;
+    if (gl < deg) {
+      const int j = a.idx[e0 + gl];
+      if (j != i) { key = a.C[j]; wt = a.w[e0 + gl]; }
+    }
+    double sum = 0.0;
+    bool first = true;
+#pragma unroll
+    for (int s = 0; s < G; ++s) {
+      const int ks = __shfl(key, s, G);
+      const float ws = __shfl(wt, s, G);
+      if (ks == key) {
+        sum += (double)ws;
+        if (s < gl) first = false;
+      }
+    }
+    const double bown = group_sum<G>((key == d && first) ? sum : 0.0);
+    double g = 0.0;
+    int c = kNoComm;
+    if (key >= 0 && key != d && first) {
+      const double x = move_score(a.M2, sum, bown, a.K[i], a.Sig[key], a.Sig[d]);
+      if (x > 0.0) { g = x; c = key; }
+    }
+    group_argmax<G>(g, c);
+    if (valid && gl == 0) {
+      a.from[i] = d;
+      a.prop[i] = (c == kNoComm) ? -1 : c;
+      a.gp[i] = g;
+    }
+  }
+}
+
+template <bool GLOBAL>
+__device__ __forceinline__ int ld_key(const int *p) {
+  if (GLOBAL) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return *p;
+}
+template <bool GLOBAL>
+__device__ __forceinline__ double ld_val(const double *p) {
+  if (GLOBAL) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return *p;
+}
+
+__device__ __forceinline__ uint32_t pow2_at_least(uint64_t x) {
+  uint32_t c = 2;
+  while (c < x) c <<= 1;
+  return c;
+}
+
+// Team argmax over TEAM threads (TEAM = 64 or a multiple); result in t == 0.
+template <int TEAM, int BLOCK>
+__device__ __forceinline__ void team_argmax(double &g, int &c, double *rg, int *rc) {
+  group_argmax<kWave>(g, c);
+  if (TEAM > kWave) {
+    const int w = threadIdx.x / kWave;
+    if (lane() == 0) { rg[w] = g; rc[w] = c; }
+    __syncthreads();
+    if ((threadIdx.x % TEAM) == 0) {
+      for (int k = 1; k < TEAM / kWave; ++k)
+        if (better(rg[w + k], rc[w + k], g, c)) { g = rg[w + k]; c = rc[w + k]; }
+    }
+    __syncthreads();
+  }
+}
+
+// ---- propose: a team (wavefront or workgroup) per vertex, hash table in LDS
+// (T slots per team) or in a global-memory region per workgroup.
+template <int TEAM, int T, int BLOCK, bool GLOBAL>
+__global__ __launch_bounds__(BLOCK) void k_propose_team(MoveArgs a, int b) {
+  constexpr int NT = BLOCK / TEAM;
+  constexpr int TL = GLOBAL ? 1 : T;
+  __shared__ int skeys[NT * TL];
+  __shared__ double svals[NT * TL];
+  __shared__ double sb[NT];
+  __shared__ double rg[BLOCK / kWave];
+  __shared__ int rc[BLOCK / kWave];
+  const int team = threadIdx.x / TEAM;
+  const int t = threadIdx.x % TEAM;
+  const int count = a.counts[a.s * kNB + b];
+  const int32_t *list = a.lists + a.region[a.s * kNB + b];
+  for (int64_t base = (int64_t)blockIdx.x * NT; base < count; base += (int64_t)gridDim.x * NT) {
+    const int64_t v = base + team;
+    const bool valid = v < count;
+    const int i = valid ? list[v] : 0;
+    int64_t e0 = 0, e1 = 0;
+    int d = 0;
+    if (valid) { e0 = a.off[i]; e1 = a.off[i + 1]; d = a.C[i]; }
+    int *keys;
+    double *vals;
+    uint32_t mask;
+    if (GLOBAL) {
+      keys = a.hub_keys + (int64_t)blockIdx.x * a.hub_cap;
+      vals = a.hub_vals + (int64_t)blockIdx.x * a.hub_cap;
+      uint32_t cap = pow2_at_least(2 * (uint64_t)(e1 - e0));
+      if (cap > (uint32_t)a.hub_cap) cap = (uint32_t)a.hub_cap;
+      mask = cap - 1;
+    } else {
+      keys = skeys + team * TL;
+      vals = svals + team * TL;
+      mask = T - 1;
+    }
+    for (uint32_t s = t; s <= mask; s += TEAM) { keys[s] = kEmpty; vals[s] = 0.0; }
+    if (t == 0) sb[team] = 0.0;
+    __syncthreads();
+    if (valid) {
+      for (int64_t e = e0 + t; e < e1; e += TEAM) {
+        const int j = a.idx[e];
+        if (j != i) table_add(keys, vals, mask, a.C[j], (double)a.w[e]);
+      }
+    }
+    __syncthreads();
+    if (valid)
+      for (uint32_t s = t; s <= mask; s += TEAM)
+        if (ld_key<GLOBAL>(&keys[s]) == d) sb[team] = ld_val<GLOBAL>(&vals[s]);
+    __syncthreads();
+    double bg = 0.0;
+    int bc = kNoComm;
+    if (valid) {
+      const double bown = sb[team];
+      const double Ki = a.K[i];
+      const double Sd = a.Sig[d];
+      for (uint32_t s = t; s <= mask; s += TEAM) {
+        const int c = ld_key<GLOBAL>(&keys[s]);
+        if (c == kEmpty || c == d) continue;
+        const double x = move_score(a.M2, ld_val<GLOBAL>(&vals[s]), bown, Ki, a.Sig[c], Sd);
+        if (x > 0.0 && better(x, c, bg, bc)) { bg = x; bc = c; }
+      }
+    }
+    team_argmax<TEAM, BLOCK>(bg, bc, rg, rc);
+    if (valid && t == 0) {
+      a.from[i] = d;
+      a.prop[i] = (bc == kNoComm) ? -1 : bc;
+      a.gp[i] = bg;
+    }
+    __syncthreads();
+  }
+}
+
+// ---- apply: reverse-move resolution and move application ------------------
+__device__ __forceinline__ bool reverse_wins(const MoveArgs &a, int j, int i, int fi, int p, double gi) {
+  const int pj = a.prop[j];
+  return pj >= 0 && pj == fi && a.from[j] == p && slice_of(j, a.nsl) == a.s && better(a.gp[j], j, gi, i);
+}
+
+__device__ __forceinline__ void flush_gain(const MoveArgs &a, double gsum, long long mv) {
+  __shared__ double sd[16];
+  __shared__ long long sl[16];
+  const double g = block_sum(gsum, sd);
+  const long long m = block_sum_ll(mv, sl);
+  if (threadIdx.x == 0) {
+    if (g != 0.0 && a.gain) unsafeAtomicAdd(a.gain, g);
+    if (m) atomicAdd(a.moves, (unsigned long long)m);
+  }
+}
+
+__device__ __forceinline__ void do_move(const MoveArgs &a, int i, int fi, int p, double g, double &gsum,
+                                        long long &mv) {
+  a.C[i] = p;
+  const double k = a.K[i];
+  unsafeAtomicAdd(&a.Sig[fi], -k);
+  unsafeAtomicAdd(&a.Sig[p], k);
+  if (a.track) { a.dC[fi] = 1; a.dC[p] = 1; }
+  if (a.gi) a.gi[i] = g;
+  else gsum += g;
+  mv += 1;
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_apply_small(MoveArgs a, int b) {
+  const int count = a.counts[a.s * kNB + b];
+  const int32_t *list = a.lists + a.region[a.s * kNB + b];
+  const int gl = threadIdx.x & (G - 1);
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwave = (int64_t)gridDim.x * blockDim.x / kWave;
+  const int gin = lane() / G;
+  double gsum = 0.0;
+  long long mv = 0;
+  const unsigned long long gm =
+      (G == kWave) ? ~0ull : (((1ull << G) - 1ull) << (unsigned)(lane() & ~(G - 1)));
+  for (int64_t v0 = wave * (kWave / G); v0 < count; v0 += nwave * (kWave / G)) {
+    const int64_t v = v0 + gin;
+    const int i = v < count ? list[v] : 0;
+    const int p = v < count ? a.prop[i] : -1;
+    bool blocked = false;
+    int j = -1;
+    int fi = 0;
+    double g = 0.0;
+    int deg = 0;
+    if (p >= 0) {
+      fi = a.from[i];
+      g = a.gp[i];
+      const int64_t e0 = a.off[i];
+      deg = (int)(a.off[i + 1] - e0);
+      if (gl < deg) {
+        j = a.idx[e0 + gl];
+        if (j != i) blocked = reverse_wins(a, j, i, fi, p, g);
+      }
+    }
+    const bool any = (__ballot(blocked) & gm) != 0ull;
+    if (p >= 0) {
+      if (!any) {
+        if (gl < deg && j != i) a.U[j] = 1;
+        if (gl == 0) do_move(a, i, fi, p, g, gsum, mv);
+      } else if (gl == 0) {
+        a.U[i] = 1;
+      }
+    }
+  }
+  flush_gain(a, gsum, mv);
+}
+
+template <int TEAM, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_apply_team(MoveArgs a, int b) {
+  constexpr int NT = BLOCK / TEAM;
+  __shared__ int sany[NT];
+  const int team = threadIdx.x / TEAM;
+  const int t = threadIdx.x % TEAM;
+  const int count = a.counts[a.s * kNB + b];
+  const int32_t *list = a.lists + a.region[a.s * kNB + b];
+  double gsum = 0.0;
+  long long mv = 0;
+  for (int64_t base = (int64_t)blockIdx.x * NT; base < count; base += (int64_t)gridDim.x * NT) {
+    const int64_t v = base + team;
+    const bool valid = v < count;
+    const int i = valid ? list[v] : 0;
+    const int p = valid ? a.prop[i] : -1;
+    int fi = 0;
+    double g = 0.0;
+    int64_t e0 = 0, e1 = 0;
+    bool blocked = false;
+    if (p >= 0) {
+      fi = a.from[i];
+      g = a.gp[i];
+      e0 = a.off[i];
+      e1 = a.off[i + 1];
+      for (int64_t e = e0 + t; e < e1 && !blocked; e += TEAM) {
+        const int j = a.idx[e];
+        if (j != i && reverse_wins(a, j, i, fi, p, g)) blocked = true;
+      }
+    }
+    bool any;
+    if (TEAM == kWave) {
+      any = __ballot(blocked) != 0ull;
+    } else {
+      if (t == 0) sany[team] = 0;
+      __syncthreads();
+      if (blocked) sany[team] = 1;
+      __syncthreads();
+      any = sany[team] != 0;
+    }
+    if (p >= 0) {
+      if (!any) {
+        for (int64_t e = e0 + t; e < e1; e += TEAM) {
+          const int j = a.idx[e];
+          if (j != i) a.U[j] = 1;
+        }
+        if (t == 0) do_move(a, i, fi, p, g, gsum, mv);
+      } else if (t == 0) {
+        a.U[i] = 1;
+      }
+    }
+    if (TEAM != kWave) __syncthreads();
+  }
+  flush_gain(a, gsum, mv);
+}
+
+// ---- launchers -----------------------------------------------------------------
+static int grid_for(int64_t cap, int per_block, int maxb = 4096) {
+  int64_t g = ceil_div(cap, per_block);
+  if (g < 1) g = 1;
+  return (int)(g < maxb ? g : maxb);
+}
+
+void move_frontier(const MoveArgs &a, hipStream_t s) {
+  if (a.vend > a.vbeg) hipLaunchKernelGGL(k_frontier, flat_grid(a.vend - a.vbeg), 256, 0, s, a);
+}
+
+void move_propose(const MoveArgs &a, const int64_t *region_h, hipStream_t s) {
+  for (int b = 0; b < kNB; ++b) {
+    const int64_t cap = region_h[a.s * kNB + b + 1] - region_h[a.s * kNB + b];
+    if (cap <= 0) continue;
+    switch (b) {
+      case 0: hipLaunchKernelGGL(k_propose_small<4>, grid_for(cap, 64), 256, 0, s, a, b); break;
+      case 1: hipLaunchKernelGGL(k_propose_small<8>, grid_for(cap, 32), 256, 0, s, a, b); break;
+      case 2: hipLaunchKernelGGL(k_propose_small<32>, grid_for(cap, 8), 256, 0, s, a, b); break;
+      case 3: hipLaunchKernelGGL((k_propose_team<64, 512, 256, false>), grid_for(cap, 4), 256, 0, s, a, b); break;
+      case 4: hipLaunchKernelGGL((k_propose_team<256, 4096, 256, false>), grid_for(cap, 1, 2048), 256, 0, s, a, b); break;
+      case 5: hipLaunchKernelGGL((k_propose_team<512, 1, 512, true>), grid_for(cap, 1, a.hub_blocks), 512, 0, s, a, b); break;
+    }
+  }
+}
+
+void move_apply(const MoveArgs &a, const int64_t *region_h, hipStream_t s) {
+  for (int b = 0; b < kNB; ++b) {
+    const int64_t cap = region_h[a.s * kNB + b + 1] - region_h[a.s * kNB + b];
+    if (cap <= 0) continue;
+    switch (b) {
+      case 0: hipLaunchKernelGGL(k_apply_small<4>, grid_for(cap, 64), 256, 0, s, a, b); break;
+      case 1: hipLaunchKernelGGL(k_apply_small<8>, grid_for(cap, 32), 256, 0, s, a, b); break;
+      case 2: hipLaunchKernelGGL(k_apply_small<32>, grid_for(cap, 8), 256, 0, s, a, b); break;
+      case 3: hipLaunchKernelGGL((k_apply_team<64, 256>), grid_for(cap, 4), 256, 0, s, a, b); break;
+      case 4: hipLaunchKernelGGL((k_apply_team<256, 256>), grid_for(cap, 1, 2048), 256, 0, s, a, b); break;
+      case 5: hipLaunchKernelGGL((k_apply_team<512, 512>), grid_for(cap, 1, 1024), 512, 0, s, a, b); break;
+    }
+  }
+}
+
+// ---- fixed-order gain total (synchronous mode) ------------------------------------
+__global__ void k_tile_sums(const double *x, int64_t n, double *tiles) {
+  const int64_t ntiles = ceil_div(n, 256);
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = t * 256;
+    const int64_t b = min(n, a + 256);
+    double s = 0.0;
+    for (int64_t k = a; k < b; ++k) s += x[k];
+    tiles[t] = s;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_tiles_total(const double *tiles, int64_t ntiles, double *out) {
+  __shared__ double buf[64];
+  double total = 0.0;
+  for (int64_t base = 0; base < ntiles; base += 64) {
+    const int64_t k = base + threadIdx.x;
+    buf[threadIdx.x] = k < ntiles ? tiles[k] : 0.0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int64_t m = min((int64_t)64, ntiles - base);
+      for (int64_t q = 0; q < m; ++q) total += buf[q];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = total;
+}
+
+void tiled_sum(const double *gi, int64_t n, double *tiles, double *out, hipStream_t s) {
+  const int64_t ntiles = ceil_div(n, 256);
+  if (ntiles > 0) hipLaunchKernelGGL(k_tile_sums, flat_grid(ntiles), 256, 0, s, gi, n, tiles);
+  hipLaunchKernelGGL(k_tiles_total, 1, 64, 0, s, tiles, ntiles, out);
+}
+
+}  // namespace lk

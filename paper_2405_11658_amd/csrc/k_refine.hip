@@ -1,0 +1,273 @@
+// Refinement side of a pass:
+//   subset renumber (Alg. "leidenSubsetRenumber"): every community is
+//     relabelled by its smallest member id, Sigma' and deltaC' re-keyed;
+//   break (function "breakChangedCommunities" of Alg. "leiden"): vertices of
+//     changed communities become singletons; the community bounds C'_B are
+//     kept;
+//   refine (Alg. "leidenRefine" with "scanBounded"): constrained merges of
+//     isolated vertices inside their bound, one sweep over the vertex slices
+//     in order - in a slice every isolated vertex of a changed bound proposes
+//     its best target inside the bound from the current state; a proposal is
+//     accepted when the target's representative is not proposing in the
+//     slice, or when the two propose to each other and the proposer has
+//     priority (larger gain, then smaller id).
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace lk {
+
+__device__ __forceinline__ int bucket_of_r(int64_t deg) {
+  return deg <= 4 ? 0 : deg <= 8 ? 1 : deg <= 32 ? 2 : deg <= 256 ? 3 : deg <= 2048 ? 4 : 5;
+}
+
+__global__ void k_rep_min(int64_t n, const int32_t *C, int32_t *rep) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int c = C[i];
+    // a (possibly stale) value <= i means a smaller member already won
+    if (rep[c] > (int32_t)i) atomicMin(&rep[c], (int32_t)i);
+  }
+}
+
+__global__ void k_subset_remap(int64_t n, int32_t *C, const int32_t *rep, const double *Sig, double *Sig2,
+                               const uint8_t *dC, uint8_t *dC2) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int c = C[i];
+    const int r = rep[c];
+    if (r == (int32_t)i) { Sig2[i] = Sig[c]; dC2[i] = dC[c]; }
+    else { Sig2[i] = 0.0; dC2[i] = 0; }
+    C[i] = r;
+  }
+}
+
+void subset_renumber(int64_t n, int32_t *C, int32_t *rep, const double *Sig, double *Sig2,
+                     const uint8_t *dC, uint8_t *dC2, hipStream_t s) {
+  if (n <= 0) return;
+  fill_i32(rep, INT_MAX, n, s);
+  hipLaunchKernelGGL(k_rep_min, flat_grid(n), 256, 0, s, n, C, rep);
+  hipLaunchKernelGGL(k_subset_remap, flat_grid(n), 256, 0, s, n, C, rep, Sig, Sig2, dC, dC2);
+}
+
+// Break changed communities; keep the bounds; bucket the refine candidates.
+__global__ __launch_bounds__(256) void k_break(RefineArgs a) {
+  unsigned long long nref = 0;
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < a.n; i0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = i0 + threadIdx.x;
+    int b = -1;
+    if (i < a.n) {
+      const int cb = a.C[i];
+      a.CB[i] = cb;
+      if (a.dC[cb]) {
+        a.C[i] = (int32_t)i;
+        a.Sig[i] = a.K[i];
+        a.S[i] = 1;
+        a.prop[i] = -1;
+        nref++;
+        const int64_t deg = a.off[i + 1] - a.off[i];
+        if (deg > 0) b = slice_of(i, a.nsl) * kNB + bucket_of_r(deg);
+      }
+    }
+    const int pos = wave_peel_inc(a.counts, b < 0 ? 0 : b, b >= 0);
+    if (b >= 0) a.lists[a.region[b] + pos] = (int32_t)i;
+  }
+  for (int o = 32; o > 0; o >>= 1) nref += __shfl_xor(nref, o);
+  if (lane() == 0 && nref) atomicAdd(a.refined, nref);
+}
+
+void refine_break(const RefineArgs &a, hipStream_t s) {
+  if (a.n > 0) hipLaunchKernelGGL(k_break, flat_grid(a.n), 256, 0, s, a);
+}
+
+// ---- refine propose ------------------------------------------------------------
+template <int G>
+__global__ __launch_bounds__(256) void k_rprop_small(RefineArgs a, int b) {
+  const int count = a.counts[a.s * kNB + b];
+  const int32_t *list = a.lists + a.region[a.s * kNB + b];
+  const int gl = threadIdx.x & (G - 1);
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwave = (int64_t)gridDim.x * blockDim.x / kWave;
+  const int gin = lane() / G;
+  for (int64_t v0 = wave * (kWave / G); v0 < count; v0 += nwave * (kWave / G)) {
+    const int64_t v = v0 + gin;
+    const bool valid = v < count;
+    const int i = valid ? list[v] : 0;
+    const bool active = valid && a.C[i] == i && a.S[i] == 1;
+    int64_t e0 = 0;
+    int deg = 0, cbi = 0;
+    if (active) {
+      e0 = a.off[i];
+      deg = (int)(a.off[i + 1] - e0);
+      cbi = a.CB[i];
+    }
+    int key = -1;
+    float wt = 0.0f;
+    if (gl < deg) {
+      const int j = a.idx[e0 + gl];
+      if (j != i && a.CB[j] == cbi) { key = a.C[j]; wt = a.w[e0 + gl]; }
+    }
+    double sum = 0.0;
+    bool first = true;
+#pragma unroll
+    for (int s = 0; s < G; ++s) {
+      const int ks = __shfl(key, s, G);
+      const float ws = __shfl(wt, s, G);
+      if (ks == key) {
+        sum += (double)ws;
+        if (s < gl) first = false;
+      }
+    }
+    const double bown = group_sum<G>((key == i && first) ? sum : 0.0);
+    double g = 0.0;
+    int c = kNoComm;
+    if (key >= 0 && key != i && first) {
+      const double x = move_score(a.M2, sum, bown, a.K[i], a.Sig[key], a.Sig[i]);
+      if (x > 0.0) { g = x; c = key; }
+    }
+    group_argmax<G>(g, c);
+    if (valid && gl == 0) {
+      a.prop[i] = (c == kNoComm) ? -1 : c;
+      a.gp[i] = g;
+    }
+  }
+}
+
+template <bool GLOBAL>
+__device__ __forceinline__ int rld_key(const int *p) {
+  if (GLOBAL) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return *p;
+}
+template <bool GLOBAL>
+__device__ __forceinline__ double rld_val(const double *p) {
+  if (GLOBAL) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return *p;
+}
+
+template <int TEAM, int T, int BLOCK, bool GLOBAL>
+__global__ __launch_bounds__(BLOCK) void k_rprop_team(RefineArgs a, int b) {
+  constexpr int NT = BLOCK / TEAM;
+  constexpr int TL = GLOBAL ? 1 : T;
+  __shared__ int skeys[NT * TL];
+  __shared__ double svals[NT * TL];
+  __shared__ double sb[NT];
+  __shared__ double rg[BLOCK / kWave];
+  __shared__ int rc[BLOCK / kWave];
+  const int team = threadIdx.x / TEAM;
+  const int t = threadIdx.x % TEAM;
+  const int count = a.counts[a.s * kNB + b];
+  const int32_t *list = a.lists + a.region[a.s * kNB + b];
+  for (int64_t base = (int64_t)blockIdx.x * NT; base < count; base += (int64_t)gridDim.x * NT) {
+    const int64_t v = base + team;
+    const bool valid = v < count;
+    const int i = valid ? list[v] : 0;
+    const bool active = valid && a.C[i] == i && a.S[i] == 1;
+    int64_t e0 = 0, e1 = 0;
+    int cbi = 0;
+    if (active) { e0 = a.off[i]; e1 = a.off[i + 1]; cbi = a.CB[i]; }
+    int *keys;
+    double *vals;
+    uint32_t mask;
+    if (GLOBAL) {
+      keys = a.hub_keys + (int64_t)blockIdx.x * a.hub_cap;
+      vals = a.hub_vals + (int64_t)blockIdx.x * a.hub_cap;
+      uint32_t cap = 2;
+      while (cap < 2 * (uint64_t)(e1 - e0)) cap <<= 1;
+      if (cap > (uint32_t)a.hub_cap) cap = (uint32_t)a.hub_cap;
+      mask = cap - 1;
+    } else {
+      keys = skeys + team * TL;
+      vals = svals + team * TL;
+      mask = T - 1;
+    }
+    for (uint32_t s = t; s <= mask; s += TEAM) { keys[s] = kEmpty; vals[s] = 0.0; }
+    if (t == 0) sb[team] = 0.0;
+    __syncthreads();
+    if (active) {
+      for (int64_t e = e0 + t; e < e1; e += TEAM) {
+        const int j = a.idx[e];
+        if (j != i && a.CB[j] == cbi) table_add(keys, vals, mask, a.C[j], (double)a.w[e]);
+      }
+    }
+    __syncthreads();
+    if (active)
+      for (uint32_t s = t; s <= mask; s += TEAM)
+        if (rld_key<GLOBAL>(&keys[s]) == i) sb[team] = rld_val<GLOBAL>(&vals[s]);
+    __syncthreads();
+    double bg = 0.0;
+    int bc = kNoComm;
+    if (active) {
+      const double bown = sb[team];
+      const double Ki = a.K[i];
+      const double Sd = a.Sig[i];
+      for (uint32_t s = t; s <= mask; s += TEAM) {
+        const int c = rld_key<GLOBAL>(&keys[s]);
+        if (c == kEmpty || c == i) continue;
+        const double x = move_score(a.M2, rld_val<GLOBAL>(&vals[s]), bown, Ki, a.Sig[c], Sd);
+        if (x > 0.0 && better(x, c, bg, bc)) { bg = x; bc = c; }
+      }
+    }
+    group_argmax<kWave>(bg, bc);
+    if (TEAM > kWave) {
+      const int w = threadIdx.x / kWave;
+      if (lane() == 0) { rg[w] = bg; rc[w] = bc; }
+      __syncthreads();
+      if (t == 0)
+        for (int k = 1; k < TEAM / kWave; ++k)
+          if (better(rg[w + k], rc[w + k], bg, bc)) { bg = rg[w + k]; bc = rc[w + k]; }
+      __syncthreads();
+    }
+    if (valid && t == 0) {
+      a.prop[i] = (bc == kNoComm) ? -1 : bc;
+      a.gp[i] = bg;
+    }
+    __syncthreads();
+  }
+}
+
+static int rgrid(int64_t cap, int per_block, int maxb = 4096) {
+  int64_t g = ceil_div(cap, per_block);
+  if (g < 1) g = 1;
+  return (int)(g < maxb ? g : maxb);
+}
+
+void refine_propose(const RefineArgs &a, const int64_t *region_h, hipStream_t s) {
+  for (int b = 0; b < kNB; ++b) {
+    const int64_t cap = region_h[a.s * kNB + b + 1] - region_h[a.s * kNB + b];
+    if (cap <= 0) continue;
+    switch (b) {
+      case 0: hipLaunchKernelGGL(k_rprop_small<4>, rgrid(cap, 64), 256, 0, s, a, b); break;
+      case 1: hipLaunchKernelGGL(k_rprop_small<8>, rgrid(cap, 32), 256, 0, s, a, b); break;
+      case 2: hipLaunchKernelGGL(k_rprop_small<32>, rgrid(cap, 8), 256, 0, s, a, b); break;
+      case 3: hipLaunchKernelGGL((k_rprop_team<64, 512, 256, false>), rgrid(cap, 4), 256, 0, s, a, b); break;
+      case 4: hipLaunchKernelGGL((k_rprop_team<256, 4096, 256, false>), rgrid(cap, 1, 2048), 256, 0, s, a, b); break;
+      case 5: hipLaunchKernelGGL((k_rprop_team<512, 1, 512, true>), rgrid(cap, 1, a.hub_blocks), 512, 0, s, a, b); break;
+    }
+  }
+}
+
+// Accept the proposals of slice s.  p "is proposing" only if p belongs to
+// slice s and proposed in it.  One thread per list slot of the slice.
+__global__ void k_raccept(RefineArgs a, int64_t beg, int64_t end) {
+  for (int64_t t = beg + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < end; t += (int64_t)gridDim.x * blockDim.x) {
+    int b = 0;
+    while (b + 1 < kNB && t >= a.region[a.s * kNB + b + 1]) ++b;
+    if (t - a.region[a.s * kNB + b] >= a.counts[a.s * kNB + b]) continue;
+    const int i = a.lists[t];
+    const int p = a.prop[i];
+    if (p < 0) continue;
+    const int pp = (slice_of(p, a.nsl) == a.s) ? a.prop[p] : -1;
+    const bool ok = pp < 0 || (pp == i && better(a.gp[i], i, a.gp[p], p));
+    if (!ok) continue;
+    a.C[i] = p;
+    const double k = a.K[i];
+    unsafeAtomicAdd(&a.Sig[i], -k);
+    unsafeAtomicAdd(&a.Sig[p], k);
+    a.S[i] = 0;
+    atomicAdd(&a.S[p], 1);
+  }
+}
+
+void refine_accept(const RefineArgs &a, const int64_t *region_h, hipStream_t s) {
+  const int64_t beg = region_h[a.s * kNB], end = region_h[(a.s + 1) * kNB];
+  if (end > beg) hipLaunchKernelGGL(k_raccept, flat_grid(end - beg), 256, 0, s, a, beg, end);
+}
+
+}  // namespace lk

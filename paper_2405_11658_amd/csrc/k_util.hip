@@ -1,0 +1,236 @@
+// Utility kernels: fills, label maps, CSR chunk mapping, row sums, checks,
+// degree buckets, and the rocPRIM-backed scans and sorts.
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+#include <rocprim/device/device_segmented_radix_sort.hpp>
+
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace lk {
+
+template <typename T>
+__global__ void k_fill(T *p, T v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_fill<int32_t>, flat_grid(n), 256, 0, s, p, v, n);
+}
+void fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_fill<uint8_t>, flat_grid(n), 256, 0, s, p, v, n);
+}
+void fill_f64(double *p, double v, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_fill<double>, flat_grid(n), 256, 0, s, p, v, n);
+}
+void fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_fill<unsigned long long>, flat_grid(n), 256, 0, s, p, v, n);
+}
+
+__global__ void k_iota(int32_t *p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = (int32_t)i;
+}
+void iota_i32(int32_t *p, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_iota, flat_grid(n), 256, 0, s, p, n);
+}
+
+__global__ void k_chunk_start_rows(const int64_t *off, int64_t nrows, int64_t nnz, int32_t *out) {
+  const int64_t nchunks = ceil_div(nnz, kChunk);
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[nchunks] = (int32_t)(nrows > 0 ? nrows - 1 : 0);
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * blockDim.x) {
+    int64_t a = off[r], b = off[r + 1];
+    if (a == b) continue;
+    int64_t q = ceil_div(a, kChunk) * kChunk;
+    for (; q < b; q += kChunk) out[q / kChunk] = (int32_t)r;
+  }
+}
+void chunk_start_rows(const int64_t *off, int64_t nrows, int64_t nnz, int32_t *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_chunk_start_rows, flat_grid(nrows), 256, 0, s, off, nrows, nnz, out);
+}
+
+// Row sums over CSR chunks: each block owns kChunk consecutive positions,
+// accumulates per-row partial sums in LDS and adds them to K once per row.
+__global__ __launch_bounds__(256) void k_row_sums(const int64_t *off, const float *w, int64_t nnz,
+                                                  const int32_t *crow, double *K) {
+  __shared__ int rowof[kChunk];
+  __shared__ double ksum[kChunk];
+  __shared__ int sh[16];
+  const int64_t q0 = (int64_t)blockIdx.x * kChunk;
+  const int len = (int)min((int64_t)kChunk, nnz - q0);
+  chunk_rows<kChunk>(off, q0, len, crow[blockIdx.x], crow[blockIdx.x + 1], rowof, sh);
+  for (int t = threadIdx.x; t < kChunk; t += blockDim.x) ksum[t] = 0.0;
+  __syncthreads();
+  for (int t = threadIdx.x; t < len; t += blockDim.x) {
+    const int r = rowof[t];
+    int64_t s0 = off[r] - q0;
+    if (s0 < 0) s0 = 0;
+    atomicAdd(&ksum[s0], (double)w[q0 + t]);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < len; t += blockDim.x) {
+    if (t == 0 || rowof[t] != rowof[t - 1]) unsafeAtomicAdd(&K[rowof[t]], ksum[t]);
+  }
+}
+void row_sums(const int64_t *off, const float *w, int64_t nrows, int64_t nnz, const int32_t *crow,
+              double *K, hipStream_t s) {
+  (void)nrows;
+  if (nnz > 0) hipLaunchKernelGGL(k_row_sums, (int)ceil_div(nnz, kChunk), 256, 0, s, off, w, nnz, crow, K);
+}
+
+__global__ void k_scatter_add(const double *v, const int32_t *C, int64_t n, double *out) {
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = i0 + threadIdx.x;
+    const bool act = i < n;
+    const int c = act ? C[i] : 0;
+    const double x = act ? v[i] : 0.0;
+    wave_peel_add_f64(out, c, x, act && x != 0.0);
+  }
+}
+void scatter_add(const double *v, const int32_t *C, int64_t n, double *out, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_scatter_add, flat_grid(n), 256, 0, s, v, C, n, out);
+}
+
+__global__ void k_gather_map(int32_t *C, const int32_t *map, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    C[i] = map[C[i]];
+}
+void gather_map(int32_t *C, const int32_t *map, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_gather_map, flat_grid(n), 256, 0, s, C, map, n);
+}
+
+__global__ void k_mark_used(const int32_t *C, int64_t n, int32_t *flags) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    flags[C[i]] = 1;
+}
+void mark_used(const int32_t *C, int64_t n, int32_t *flags, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_mark_used, flat_grid(n), 256, 0, s, C, n, flags);
+}
+
+__device__ __forceinline__ int bucket_of(int64_t deg) {
+  return deg <= 4 ? 0 : deg <= 8 ? 1 : deg <= 32 ? 2 : deg <= 256 ? 3 : deg <= 2048 ? 4 : 5;
+}
+
+__global__ void k_bucket_hist(const int64_t *off, int64_t n, int32_t *counts, unsigned long long *maxdeg) {
+  unsigned long long mx = 0;
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = i0 + threadIdx.x;
+    int64_t deg = 0;
+    if (i < n) deg = off[i + 1] - off[i];
+    const bool act = deg > 0;
+    wave_peel_inc(counts, act ? bucket_of(deg) : 0, act);
+    mx = max(mx, (unsigned long long)deg);
+  }
+  for (int o = 32; o > 0; o >>= 1) mx = max(mx, (unsigned long long)__shfl_xor(mx, o));
+  if (lane() == 0 && mx > 0) atomicMax(maxdeg, mx);
+}
+void bucket_hist(const int64_t *off, int64_t n, int32_t *counts, unsigned long long *maxdeg, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_bucket_hist, flat_grid(n), 256, 0, s, off, n, counts, maxdeg);
+}
+
+__global__ void k_check_labels(const int32_t *C, int64_t n, int64_t bound, int32_t *err) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (C[i] < 0 || (int64_t)C[i] >= bound) atomicOr(err, 1);
+}
+void check_labels(const int32_t *C, int64_t n, int64_t bound, int32_t *err, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_check_labels, flat_grid(n), 256, 0, s, C, n, bound, err);
+}
+
+__global__ void k_check_offsets(const int64_t *off, int64_t n, int64_t nnz, int32_t *err) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (off[i] > off[i + 1] || off[i] < 0 || off[i + 1] > nnz) atomicOr(err, 1);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && (off[0] != 0 || off[n] != nnz)) atomicOr(err, 1);
+}
+void check_offsets(const int64_t *off, int64_t n, int64_t nnz, int32_t *err, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_offsets, flat_grid(n > 0 ? n : 1), 256, 0, s, off, n, nnz, err);
+}
+
+// Rows must be strictly ascending (sorted, no duplicate entries), ids in
+// range, weights finite and > 0.  Chunked over positions.
+__global__ __launch_bounds__(256) void k_check_rows(const int64_t *off, const int32_t *idx, const float *w,
+                                                    int64_t n, int64_t nnz, const int32_t *crow,
+                                                    int32_t *err) {
+  __shared__ int rowof[kChunk];
+  __shared__ int sh[16];
+  const int64_t q0 = (int64_t)blockIdx.x * kChunk;
+  const int len = (int)min((int64_t)kChunk, nnz - q0);
+  chunk_rows<kChunk>(off, q0, len, crow[blockIdx.x], crow[blockIdx.x + 1], rowof, sh);
+  for (int t = threadIdx.x; t < len; t += blockDim.x) {
+    const int64_t q = q0 + t;
+    const int r = rowof[t];
+    const int j = idx[q];
+    const float x = w[q];
+    bool bad = j < 0 || (int64_t)j >= n || !(x > 0.0f) || !isfinite(x);
+    if (q > off[r] && idx[q - 1] >= j) bad = true;
+    if (bad) atomicOr(err, 1);
+  }
+}
+void check_rows_chunked(const int64_t *off, const int32_t *idx, const float *w, int64_t n, int64_t nnz,
+                        const int32_t *crow, int32_t *err, hipStream_t s) {
+  if (nnz > 0)
+    hipLaunchKernelGGL(k_check_rows, (int)ceil_div(nnz, kChunk), 256, 0, s, off, idx, w, n, nnz, crow, err);
+}
+
+// ---- rocPRIM wrappers ---------------------------------------------------------
+size_t scan_excl_i32(void *temp, size_t tbytes, const int32_t *in, int32_t *out, int64_t n, hipStream_t s) {
+  size_t bytes = tbytes;
+  (void)rocprim::exclusive_scan(temp, bytes, in, out, (int32_t)0, (size_t)n, rocprim::plus<int32_t>(), s);
+  return bytes;
+}
+size_t scan_excl_i64(void *temp, size_t tbytes, const int64_t *in, int64_t *out, int64_t n, hipStream_t s) {
+  size_t bytes = tbytes;
+  (void)rocprim::exclusive_scan(temp, bytes, in, out, (int64_t)0, (size_t)n, rocprim::plus<int64_t>(), s);
+  return bytes;
+}
+size_t scan_excl_i32_to_i64(void *temp, size_t tbytes, const int32_t *in, int64_t *out, int64_t n,
+                            hipStream_t s) {
+  size_t bytes = tbytes;
+  (void)rocprim::exclusive_scan(temp, bytes, in, out, (int64_t)0, (size_t)n, rocprim::plus<int64_t>(), s);
+  return bytes;
+}
+size_t sort_pairs_u64_i32(void *temp, size_t tbytes, const unsigned long long *kin,
+                          unsigned long long *kout, const int32_t *vin, int32_t *vout, int64_t n,
+                          hipStream_t s) {
+  size_t bytes = tbytes;
+  (void)rocprim::radix_sort_pairs(temp, bytes, kin, kout, vin, vout, (size_t)n, 0, 64, s);
+  return bytes;
+}
+size_t sort_pairs_u64_f64(void *temp, size_t tbytes, const unsigned long long *kin,
+                          unsigned long long *kout, const double *vin, double *vout, int64_t n,
+                          hipStream_t s) {
+  size_t bytes = tbytes;
+  (void)rocprim::radix_sort_pairs(temp, bytes, kin, kout, vin, vout, (size_t)n, 0, 64, s);
+  return bytes;
+}
+size_t seg_sort_i32_f32(void *temp, size_t tbytes, const int32_t *kin, int32_t *kout,
+                        const float *vin, float *vout, int64_t nnz, int64_t nseg,
+                        const int64_t *off, hipStream_t s) {
+  size_t bytes = tbytes;
+  (void)rocprim::segmented_radix_sort_pairs(temp, bytes, kin, kout, vin, vout, (unsigned int)nnz,
+                                      (unsigned int)nseg, off, off + 1, 0, 32, s);
+  return bytes;
+}
+
+}  // namespace lk
+
+namespace lk {
+__global__ __launch_bounds__(256) void k_count_nz(const uint8_t *p, int64_t n, unsigned long long *out) {
+  __shared__ long long sl[16];
+  long long c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    c += p[i] != 0;
+  c = block_sum_ll(c, sl);
+  if (threadIdx.x == 0 && c) atomicAdd(out, (unsigned long long)c);
+}
+void count_nonzero_u8(const uint8_t *p, int64_t n, unsigned long long *out, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_count_nz, flat_grid(n, 256, 1024), 256, 0, s, p, n, out);
+}
+__global__ void k_copy_bytes(const uint8_t *src, uint8_t *dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+void copy_u8(const uint8_t *src, uint8_t *dst, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_copy_bytes, flat_grid(n), 256, 0, s, src, dst, n);
+}
+}  // namespace lk

@@ -1,0 +1,275 @@
+// Host-side launchers of the library's HIP kernels (one translation unit per
+// phase).  Every launcher enqueues on `s` and returns without synchronising;
+// the driver checks hipGetLastError after each phase.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace lk {
+
+constexpr int kNB = 6;        // degree buckets: <=4, <=8, <=32, <=256, <=2048, >2048
+
+// Slice of a vertex in a sweep: MurmurHash3's 32-bit finaliser of the id,
+// modulo the number of slices.
+__host__ __device__ inline int slice_of(int64_t i, int S) {
+  uint32_t h = (uint32_t)i;
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return (int)(h % (uint32_t)S);
+}
+constexpr int kChunk = 1024;  // CSR positions per chunk in chunked edge kernels
+
+inline int bucket_of_host(int64_t deg) {
+  return deg <= 4 ? 0 : deg <= 8 ? 1 : deg <= 32 ? 2 : deg <= 256 ? 3 : deg <= 2048 ? 4 : 5;
+}
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int flat_grid(int64_t n, int block = 256, int cap = 4096) {
+  int64_t g = ceil_div(n > 0 ? n : 1, block);
+  return (int)(g < cap ? g : cap);
+}
+
+// ---- k_util.hip ------------------------------------------------------------
+void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+void fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
+void fill_f64(double *p, double v, int64_t n, hipStream_t s);
+void fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_t s);
+void iota_i32(int32_t *p, int64_t n, hipStream_t s);
+// out[b] = row owning position b*kChunk (b < nchunks); out[nchunks] = nrows-1.
+void chunk_start_rows(const int64_t *off, int64_t nrows, int64_t nnz, int32_t *out, hipStream_t s);
+// K[r] = sum of w over row r (FP64); K must be zeroed.
+void row_sums(const int64_t *off, const float *w, int64_t nrows, int64_t nnz, const int32_t *crow,
+              double *K, hipStream_t s);
+// out[C[i]] += v[i] (out zeroed by the caller).
+void scatter_add(const double *v, const int32_t *C, int64_t n, double *out, hipStream_t s);
+// C[i] = map[C[i]]
+void gather_map(int32_t *C, const int32_t *map, int64_t n, hipStream_t s);
+// flags[C[i]] = 1
+void mark_used(const int32_t *C, int64_t n, int32_t *flags, hipStream_t s);
+// Per-bucket vertex counts (deg > 0 only) and maximum degree; counts/maxdeg zeroed by caller.
+void bucket_hist(const int64_t *off, int64_t n, int32_t *counts, unsigned long long *maxdeg,
+                 hipStream_t s);
+// C[i] < bound for all i?  sets *err |= flag otherwise.
+void check_labels(const int32_t *C, int64_t n, int64_t bound, int32_t *err, hipStream_t s);
+// Rows strictly ascending (sorted, no duplicate entry), ids in range, weights
+// finite and > 0?  Sets *err |= 1 otherwise.  crow: chunk_start_rows of off.
+void check_rows_chunked(const int64_t *off, const int32_t *idx, const float *w, int64_t n, int64_t nnz,
+                        const int32_t *crow, int32_t *err, hipStream_t s);
+void check_offsets(const int64_t *off, int64_t n, int64_t nnz, int32_t *err, hipStream_t s);
+
+// rocPRIM-backed primitives.  temp == nullptr returns the temp size needed.
+size_t scan_excl_i32(void *temp, size_t tbytes, const int32_t *in, int32_t *out, int64_t n, hipStream_t s);
+size_t scan_excl_i64(void *temp, size_t tbytes, const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
+size_t scan_excl_i32_to_i64(void *temp, size_t tbytes, const int32_t *in, int64_t *out, int64_t n,
+                            hipStream_t s);
+size_t sort_pairs_u64_i32(void *temp, size_t tbytes, const unsigned long long *kin,
+                          unsigned long long *kout, const int32_t *vin, int32_t *vout, int64_t n,
+                          hipStream_t s);
+size_t sort_pairs_u64_f64(void *temp, size_t tbytes, const unsigned long long *kin,
+                          unsigned long long *kout, const double *vin, double *vout, int64_t n,
+                          hipStream_t s);
+size_t seg_sort_i32_f32(void *temp, size_t tbytes, const int32_t *kin, int32_t *kout,
+                        const float *vin, float *vout, int64_t nnz, int64_t nseg,
+                        const int64_t *off, hipStream_t s);
+
+// ---- k_move.hip -------------------------------------------------------------
+struct MoveArgs {
+  // level graph
+  int64_t n;
+  const int64_t *off;
+  const int32_t *idx;
+  const float *w;
+  // state
+  int32_t *C;
+  const double *K;
+  double *Sig;
+  uint8_t *dC;
+  uint8_t *U;
+  const uint8_t *rng;
+  double M2;
+  int track;
+  // work
+  int32_t *prop;
+  int32_t *from;
+  double *gp;
+  double *gi;            // per-vertex accepted gain (synchronous sums), nullable
+  int32_t *lists;        // frontier, bucketed by (slice, degree bucket)
+  const int32_t *region; // device: region starts [S*kNB+1], index s*kNB+b
+  int32_t *counts;       // device: frontier counts [S*kNB]
+  int nsl;               // slices per sweep
+  int s;                 // current slice
+  const int32_t *vbyslice;  // vertices grouped by slice
+  int64_t vbeg, vend;    // range of the current slice in vbyslice
+  double *gain;          // device scalar (atomic sums), nullable when gi is used
+  unsigned long long *moves;  // device scalar
+  int *hub_keys;         // global tables for the largest bucket
+  double *hub_vals;
+  int64_t hub_cap;       // slots per block (power of two)
+  int hub_blocks;
+};
+// Per level: counts[s*kNB+b] of vertices with edges, slice sizes, and the
+// vertex-by-slice grouping (slice_fill zeroed, slice_off = starts of slices).
+void slice_hist(const int64_t *off, int64_t n, int S, int32_t *counts, int32_t *slice_cnt, hipStream_t s);
+void slice_scatter(int64_t n, int S, const int32_t *slice_off, int32_t *slice_fill, int32_t *vbyslice,
+                   hipStream_t s);
+// region_h: host copy of the region starts of this level.
+void move_frontier(const MoveArgs &a, hipStream_t s);
+void move_propose(const MoveArgs &a, const int64_t *region_h, hipStream_t s);
+void move_apply(const MoveArgs &a, const int64_t *region_h, hipStream_t s);
+// out = sum of gi in ascending 256-tiles then sequentially (fixed order).
+void tiled_sum(const double *gi, int64_t n, double *tiles, double *out, hipStream_t s);
+
+// ---- k_refine.hip -------------------------------------------------------------
+void subset_renumber(int64_t n, int32_t *C, int32_t *rep, const double *Sig, double *Sig2,
+                     const uint8_t *dC, uint8_t *dC2, hipStream_t s);
+struct RefineArgs {
+  int64_t n;
+  const int64_t *off;
+  const int32_t *idx;
+  const float *w;
+  int32_t *C;
+  int32_t *CB;
+  const double *K;
+  double *Sig;
+  const uint8_t *dC;
+  int32_t *S;
+  double M2;
+  int32_t *prop;
+  double *gp;
+  int32_t *lists;
+  const int32_t *region;    // [S*kNB+1]
+  int32_t *counts;          // [S*kNB]
+  int nsl;
+  int s;
+  unsigned long long *refined;  // device scalar: vertices in changed bounds
+  int *hub_keys;
+  double *hub_vals;
+  int64_t hub_cap;
+  int hub_blocks;
+};
+void refine_break(const RefineArgs &a, hipStream_t s);
+void refine_propose(const RefineArgs &a, const int64_t *region_h, hipStream_t s);
+void refine_accept(const RefineArgs &a, const int64_t *region_h, hipStream_t s);
+
+// ---- k_aggregate.hip -----------------------------------------------------------
+struct AggArgs {
+  int64_t n, nnz, ncomm;
+  const int64_t *off;
+  const int32_t *idx;
+  const float *w;
+  const int32_t *C;
+  // work
+  int32_t *cnt;      // ncomm+1
+  int32_t *coff;     // ncomm+1
+  int32_t *mem;      // n
+  int64_t *mdeg;     // n+1
+  int64_t *mpos;     // n+1
+  int32_t *mcrow;    // nchunks+1 (slot chunk starts)
+  int64_t *toff;     // ncomm+1
+  int32_t *hidx;     // nnz (holey rows)
+  float *hw;         // nnz
+  int32_t *rowlen;   // ncomm+1
+  unsigned long long *pkey;  // nnz
+  double *pval;      // nnz
+  int32_t *pcnt_item;  // nchunks
+  int32_t *pcnt;     // ncomm
+  int64_t *tcap;     // ncomm+1
+  int64_t *tstart;   // ncomm+1
+  // outputs
+  int64_t *out_off;  // ncomm+1
+  int32_t *out_idx;
+  float *out_w;
+  double *out_K;     // ncomm, row sums
+  int32_t *out_crow; // chunk starts of the output
+};
+void agg_count(const AggArgs &a, hipStream_t s);
+void agg_scatter(const AggArgs &a, hipStream_t s);           // needs coff, cnt zeroed (reused as fill)
+void agg_mdeg(const AggArgs &a, int64_t M, hipStream_t s);
+void agg_toff(const AggArgs &a, hipStream_t s);
+void agg_items(const AggArgs &a, int64_t M, hipStream_t s);  // needs mcrow, toff; zeroes nothing
+void agg_caps(const AggArgs &a, hipStream_t s);
+void agg_part_insert(const AggArgs &a, int *tkeys, double *tvals, hipStream_t s);
+void agg_part_emit(const AggArgs &a, const int *tkeys, const double *tvals, int64_t tc, hipStream_t s);
+void agg_compact(const AggArgs &a, int64_t nnz_out, hipStream_t s);
+
+// ---- k_modularity.hip --------------------------------------------------------
+// acc[0] += sigma total, S[c] += K-contributions (S zeroed, ncomm = n)
+void modularity_edges(const int64_t *off, const int32_t *idx, const float *w, const int32_t *crow,
+                      int64_t n, int64_t nnz, const int32_t *C, double *acc, double *S,
+                      hipStream_t s);
+// acc[1] += sum_c S_c, acc[2] += sum_c (S_c)^2 scaled: computed as sum (S_c/M2)^2 after M2 known
+void modularity_comm(const double *S, int64_t n, double *acc, hipStream_t s);
+void modularity_comm_sq(const double *S, int64_t n, double M2, double *acc, hipStream_t s);
+
+// ---- k_batch.hip ---------------------------------------------------------------
+struct BatchArgs {
+  int64_t n, nnz;
+  const int64_t *off;
+  const int32_t *idx;
+  const float *w;
+  int64_t nd, ni;
+  const int32_t *du, *dv, *iu, *iv;
+  const float *iw;
+  int64_t E;                      // 2*(nd+ni)
+  unsigned long long *keys;       // E
+  int32_t *vals;                  // E
+  unsigned long long *skeys;      // E
+  int32_t *svals;                 // E
+  float *ew;                      // E, weight of directed entry (by entry id)
+  int32_t *err;                   // device scalar
+  int64_t *bstart;                // n (segment start in sorted order, -1 none)
+  int32_t *bcnt;                  // n
+  int32_t *dcnt;                  // n deletions per row
+  int32_t *icnt;                  // n insertions per row
+  int32_t *isdel;                 // E+1
+  int32_t *delpre;                // E+1
+  int64_t *newdeg;                // n+1
+  int64_t *newoff;                // n+1
+  const int32_t *crow;            // chunk starts of the old graph
+  int32_t *nidx;
+  float *nw;
+};
+void batch_build(const BatchArgs &a, hipStream_t s);
+void batch_dups_rows(const BatchArgs &a, hipStream_t s);  // dup check + per-row counts/segments
+void batch_newdeg(const BatchArgs &a, hipStream_t s);
+void batch_apply(const BatchArgs &a, hipStream_t s);      // needs newoff, delpre
+
+struct MarkArgs {
+  int64_t n;
+  const int64_t *off;   // G^t
+  const int32_t *idx;
+  int64_t E;
+  int64_t nd2;          // 2*nd: entry ids below are deletions
+  const unsigned long long *skeys;
+  const int32_t *svals;
+  const float *ew;
+  const int32_t *C;     // C^{t-1}
+  const double *K;      // K^{t-1}
+  const double *Sig;    // Sigma^{t-1}
+  double M2;
+  uint8_t *dV, *rng, *dC, *dE, *dCm;
+  // DS work
+  unsigned long long *k2, *k2s;
+  double *v2, *v2s;
+  int32_t *list;
+  int32_t *count;
+};
+void mark_df(const MarkArgs &a, hipStream_t s);   // DF marks + changedCommunities
+void mark_changed(const MarkArgs &a, hipStream_t s);
+void mark_ds_del(const MarkArgs &a, hipStream_t s);
+void mark_ds_keys(const MarkArgs &a, hipStream_t s);       // k2/v2 for cross insertions
+void mark_ds_best(const MarkArgs &a, hipStream_t s);       // on sorted k2s/v2s
+void mark_ds_expand(const MarkArgs &a, hipStream_t s);     // list of dE, neighbours, communities
+void update_weights(const MarkArgs &a, double *K, double *Sig, double *m2delta, hipStream_t s);
+
+}  // namespace lk
+
+namespace lk {
+// out[0] += number of nonzero bytes in p[0..n)
+void count_nonzero_u8(const uint8_t *p, int64_t n, unsigned long long *out, hipStream_t s);
+// dst = src (bytes), n elements
+void copy_u8(const uint8_t *src, uint8_t *dst, int64_t n, hipStream_t s);
+}  // namespace lk

@@ -102,9 +102,16 @@ def _symmetric_csr(n: int, u: np.ndarray, v: np.ndarray) -> CSR:
 
 
 def planted_partition(n: int = 4096, blocks: int = 64, p_in: float = 0.1, p_out: float = 0.001,
-                      seed: int = 1) -> CSR:
+                      seed: int = 1, permute: bool = False) -> CSR:
     """Planted-partition graph: `blocks` contiguous equal blocks; each vertex pair
-    is an edge independently with p_in inside a block, p_out across blocks."""
+    is an edge independently with p_in inside a block, p_out across blocks.
+    With ``permute`` the vertex ids are relabelled by a seeded permutation (so
+    blocks are not contiguous id ranges)."""
+    if permute:
+        g = planted_partition(n, blocks, p_in, p_out, seed, permute=False)
+        perm = _rng(seed + 7919).permutation(n)
+        src = np.repeat(np.arange(n), np.diff(g.off))
+        return _symmetric_csr(n, perm[src], perm[g.idx])
     rng = _rng(seed)
     bs = n // blocks
     block = np.minimum(np.arange(n) // max(bs, 1), blocks - 1)

@@ -1,0 +1,285 @@
+"""Thin Python binding of the HIP library ``libleiden_hip.so`` (C ABI in
+``include/leiden.h``).  Argument marshalling only: every step of the method
+runs in the library's kernels.  Tensors are torch tensors on the current HIP
+device; the current torch stream is passed to every call.
+
+The functions carry the C names.  Loading fails loudly when the library has
+not been built (run ``python paper_2405_11658_amd/build.py``) - there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libleiden_hip.so")
+
+OK, EINVAL, ENOMEM, ESTATE, EHIP = 0, 1, 2, 3, 4
+ND, DS, DF = 1, 2, 3
+MODES = {"nd": ND, "ds": DS, "df": DF}
+MAX_PASSES = 64
+
+
+class LeidenError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class leiden_params(ct.Structure):
+    _fields_ = [("tau0", ct.c_double), ("tol_drop", ct.c_double), ("agg_tol", ct.c_double),
+                ("max_iter", ct.c_int32), ("max_passes", ct.c_int32),
+                ("sync_mode", ct.c_int32), ("refine_variant", ct.c_int32), ("nslices", ct.c_int32)]
+
+
+class leiden_stats(ct.Structure):
+    _fields_ = [("passes", ct.c_int32),
+                ("move_iters", ct.c_int32 * MAX_PASSES),
+                ("refine_rounds", ct.c_int32 * MAX_PASSES),
+                ("level_vertices", ct.c_int64 * MAX_PASSES),
+                ("level_entries", ct.c_int64 * MAX_PASSES),
+                ("communities", ct.c_int64 * MAX_PASSES),
+                ("refined_vertices", ct.c_int64 * MAX_PASSES),
+                ("affected", ct.c_int64), ("changed", ct.c_int64), ("moves_pass0", ct.c_int64),
+                ("ms_total", ct.c_double), ("ms_apply", ct.c_double), ("ms_mark", ct.c_double),
+                ("ms_move", ct.c_double), ("ms_refine", ct.c_double), ("ms_aggregate", ct.c_double),
+                ("ms_other", ct.c_double)]
+
+    def to_dict(self) -> dict:
+        p = self.passes
+        d = {"passes": p, "move_iters": list(self.move_iters[:p]),
+             "refine_rounds": list(self.refine_rounds[:p]),
+             "level_vertices": list(self.level_vertices[:p]),
+             "level_entries": list(self.level_entries[:p]),
+             "communities": list(self.communities[:p]),
+             "refined_vertices": list(self.refined_vertices[:p]),
+             "affected": self.affected, "changed": self.changed, "moves_pass0": self.moves_pass0}
+        for k in ("ms_total", "ms_apply", "ms_mark", "ms_move", "ms_refine", "ms_aggregate", "ms_other"):
+            d[k] = getattr(self, k)
+        return d
+
+
+class leiden_batch(ct.Structure):
+    _fields_ = [("n_del", ct.c_int64), ("del_u", ct.c_void_p), ("del_v", ct.c_void_p),
+                ("n_ins", ct.c_int64), ("ins_u", ct.c_void_p), ("ins_v", ct.c_void_p),
+                ("ins_w", ct.c_void_p)]
+
+
+class leiden_trace(ct.Structure):
+    _fields_ = [("affected", ct.c_void_p), ("in_range", ct.c_void_p), ("changed", ct.c_void_p)]
+
+
+_lib = None
+
+
+def load() -> ct.CDLL:
+    """Load libleiden_hip.so; raises if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library not built: {LIB_PATH} (run paper_2405_11658_amd/build.py)")
+    lib = ct.CDLL(LIB_PATH)
+    P, i64, i32, dbl = ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_double
+    sig = {
+        "leiden_default_params": (None, [P]),
+        "leiden_create": (i32, [i64, i64, P, P, P, P, P, P]),
+        "leiden_destroy": (i32, [P]),
+        "leiden_set_params": (i32, [P, P]),
+        "leiden_static": (i32, [P, P, P, P, P]),
+        "leiden_update": (i32, [P, P, i32, P, P, P, P, P]),
+        "leiden_modularity": (i32, [i64, P, P, P, P, P, P]),
+        "leiden_aggregate": (i32, [i64, P, P, P, P, i64, P, P, P, P, P]),
+        "leiden_get_graph": (i32, [P, P, P, P, P, P]),
+        "leiden_get_state": (i32, [P, P, P, P, P, P]),
+        "leiden_set_state": (i32, [P, P, P]),
+        "leiden_num_vertices": (i64, [P]),
+        "leiden_num_entries": (i64, [P]),
+        "leiden_strerror": (ct.c_char_p, [i32]),
+        "leiden_last_error": (ct.c_char_p, [P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _stream():
+    return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    return ct.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ct.c_void_p(0)
+
+
+def _dev(x, dtype) -> torch.Tensor:
+    if isinstance(x, torch.Tensor):
+        return x.to(device="cuda", dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+def _check(st: int, handle=None, what: str = ""):
+    if st != OK:
+        lib = load()
+        msg = lib.leiden_last_error(handle).decode() if handle else ""
+        if not msg:
+            msg = lib.leiden_strerror(st).decode()
+        raise LeidenError(st, f"{what}: {msg}")
+
+
+def leiden_default_params(**overrides) -> leiden_params:
+    p = leiden_params()
+    load().leiden_default_params(ct.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+@dataclass
+class Handle:
+    ptr: ct.c_void_p
+    n: int
+
+    def __del__(self):
+        if self.ptr and _lib is not None:
+            _lib.leiden_destroy(self.ptr)
+            self.ptr = None
+
+
+def leiden_create(off, idx, w, params: leiden_params | None = None) -> Handle:
+    """Copy a CSR graph (int64 offsets, int32 ids, float32 weights) into a new handle."""
+    lib = load()
+    off = _dev(off, torch.int64)
+    idx = _dev(idx, torch.int32)
+    w = _dev(w, torch.float32)
+    n = off.numel() - 1
+    out = ct.c_void_p()
+    st = lib.leiden_create(n, idx.numel(), _ptr(off), _ptr(idx), _ptr(w),
+                           ct.byref(params) if params is not None else None, _stream(), ct.byref(out))
+    _check(st, None, "leiden_create")
+    return Handle(out, n)
+
+
+def leiden_destroy(h: Handle):
+    if h.ptr:
+        _check(load().leiden_destroy(h.ptr), None, "leiden_destroy")
+        h.ptr = None
+
+
+def leiden_set_params(h: Handle, params: leiden_params):
+    _check(load().leiden_set_params(h.ptr, ct.byref(params)), h.ptr, "leiden_set_params")
+
+
+def leiden_static(h: Handle, want_q: bool = True):
+    """Static Leiden.  Returns (membership int32 tensor, modularity or None, stats dict)."""
+    lib = load()
+    out = torch.empty(h.n, dtype=torch.int32, device="cuda")
+    q = ct.c_double(0.0)
+    st = leiden_stats()
+    _check(lib.leiden_static(h.ptr, _ptr(out), ct.byref(q) if want_q else None, ct.byref(st), _stream()),
+           h.ptr, "leiden_static")
+    return out, (q.value if want_q else None), st.to_dict()
+
+
+def make_batch(del_u, del_v, ins_u, ins_v, ins_w):
+    """Device tensors of an undirected batch (each edge once)."""
+    return (_dev(del_u, torch.int32), _dev(del_v, torch.int32), _dev(ins_u, torch.int32),
+            _dev(ins_v, torch.int32), _dev(ins_w, torch.float32))
+
+
+def leiden_update(h: Handle, batch, mode, want_q: bool = True, trace: bool = False):
+    """Apply a batch and run ND/DS/DF Leiden.  batch = (del_u, del_v, ins_u, ins_v, ins_w)
+    device tensors (see make_batch).  Returns (membership, q, stats, trace dict or None)."""
+    lib = load()
+    if isinstance(mode, str):
+        mode = MODES[mode]
+    du, dv, iu, iv, iw = batch
+    b = leiden_batch(du.numel(), _ptr(du), _ptr(dv), iu.numel(), _ptr(iu), _ptr(iv), _ptr(iw))
+    out = torch.empty(h.n, dtype=torch.int32, device="cuda")
+    q = ct.c_double(0.0)
+    st = leiden_stats()
+    tr = None
+    trs = None
+    if trace:
+        tr = {k: torch.zeros(max(h.n, 1), dtype=torch.uint8, device="cuda")
+              for k in ("affected", "in_range", "changed")}
+        trs = leiden_trace(_ptr(tr["affected"]), _ptr(tr["in_range"]), _ptr(tr["changed"]))
+    _check(lib.leiden_update(h.ptr, ct.byref(b), int(mode), _ptr(out), ct.byref(q) if want_q else None,
+                             ct.byref(st), ct.byref(trs) if trs is not None else None, _stream()),
+           h.ptr, "leiden_update")
+    if tr is not None:
+        tr = {k: v[:h.n] for k, v in tr.items()}
+    return out, (q.value if want_q else None), st.to_dict(), tr
+
+
+def leiden_modularity(off, idx, w, membership) -> float:
+    lib = load()
+    off = _dev(off, torch.int64)
+    idx = _dev(idx, torch.int32)
+    w = _dev(w, torch.float32)
+    C = _dev(membership, torch.int32)
+    q = ct.c_double(0.0)
+    _check(lib.leiden_modularity(off.numel() - 1, _ptr(off), _ptr(idx), _ptr(w), _ptr(C), ct.byref(q),
+                                 _stream()), None, "leiden_modularity")
+    return q.value
+
+
+def leiden_aggregate(off, idx, w, membership, ncomm: int):
+    """Super-vertex CSR (rows compacted, entry order inside a row unspecified)."""
+    lib = load()
+    off = _dev(off, torch.int64)
+    idx = _dev(idx, torch.int32)
+    w = _dev(w, torch.float32)
+    C = _dev(membership, torch.int32)
+    cap = max(idx.numel(), 1)
+    ooff = torch.zeros(ncomm + 1, dtype=torch.int64, device="cuda")
+    oidx = torch.empty(cap, dtype=torch.int32, device="cuda")
+    ow = torch.empty(cap, dtype=torch.float32, device="cuda")
+    nnz = ct.c_int64(0)
+    _check(lib.leiden_aggregate(off.numel() - 1, _ptr(off), _ptr(idx), _ptr(w), _ptr(C), ncomm, _ptr(ooff),
+                                _ptr(oidx), _ptr(ow), ct.byref(nnz), _stream()), None, "leiden_aggregate")
+    k = nnz.value
+    return ooff, oidx[:k], ow[:k]
+
+
+def leiden_get_graph(h: Handle):
+    lib = load()
+    nnz = ct.c_int64(0)
+    _check(lib.leiden_get_graph(h.ptr, None, None, None, ct.byref(nnz), _stream()), h.ptr, "leiden_get_graph")
+    off = torch.empty(h.n + 1, dtype=torch.int64, device="cuda")
+    idx = torch.empty(max(nnz.value, 1), dtype=torch.int32, device="cuda")
+    w = torch.empty(max(nnz.value, 1), dtype=torch.float32, device="cuda")
+    _check(lib.leiden_get_graph(h.ptr, _ptr(off), _ptr(idx), _ptr(w), ct.byref(nnz), _stream()), h.ptr,
+           "leiden_get_graph")
+    return off, idx[:nnz.value], w[:nnz.value]
+
+
+def leiden_get_state(h: Handle):
+    lib = load()
+    C = torch.empty(max(h.n, 1), dtype=torch.int32, device="cuda")
+    K = torch.empty(max(h.n, 1), dtype=torch.float64, device="cuda")
+    S = torch.empty(max(h.n, 1), dtype=torch.float64, device="cuda")
+    m2 = ct.c_double(0.0)
+    _check(lib.leiden_get_state(h.ptr, _ptr(C), _ptr(K), _ptr(S), ct.byref(m2), _stream()), h.ptr,
+           "leiden_get_state")
+    return C[:h.n], K[:h.n], S[:h.n], m2.value
+
+
+def leiden_set_state(h: Handle, membership):
+    C = _dev(membership, torch.int32)
+    _check(load().leiden_set_state(h.ptr, _ptr(C), _stream()), h.ptr, "leiden_set_state")
+
+
+def leiden_num_vertices(h: Handle) -> int:
+    return int(load().leiden_num_vertices(h.ptr))
+
+
+def leiden_num_entries(h: Handle) -> int:
+    return int(load().leiden_num_entries(h.ptr))
