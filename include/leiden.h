@@ -75,7 +75,7 @@ typedef struct {
   int32_t max_passes;
   int32_t sync_mode;
   int32_t refine_variant;
-  int32_t nslices; /* 1 .. 1024 */
+  int32_t nslices; /* 1 .. 256 */
 } leiden_params;
 
 #define LEIDEN_MAX_PASSES 64

@@ -40,7 +40,8 @@ enum Slot {
   A_cnt, A_coff, A_mem, A_mdeg, A_mpos, A_mcrow, A_toff, A_hidx, A_hw, A_rowlen, A_pkey, A_pval,
   A_pcnt_item, A_pcnt, A_tcap, A_tstart, A_tkeys, A_tvals,
   // hubs
-  H_keys, H_vals,
+  H_keys, H_vals, H_v, H_cnt, H_ch, H_tab, H_sg, H_chub, H_shub, H_tk, H_tv, H_own, H_pg, H_pc, H_soff,
+  H_fill, H_bnd, L_act,
   // primitives
   T_tmp,
   // batch
@@ -109,7 +110,7 @@ struct Fail {
 };
 
 constexpr size_t kPinBytes = 65536;
-constexpr int kMaxSlices = 1024;
+constexpr int kMaxSlices = 256;
 
 // Call context: workspace + stream; helpers throw Fail, caught at the ABI.
 struct Ctx {
@@ -344,6 +345,71 @@ void scan_i32_i64(Ctx &x, const int32_t *in, int64_t *out, int64_t n) {
   x.launched("scan_i32_i64");
 }
 
+// Multi-workgroup hub plan of a level (local-moving of the largest degree
+// bucket): hub list per slice, chunk / table / segment layout, tables
+// cleared, and per-slice bounds on the host.
+struct HubHost {
+  HubPlan p;
+  int64_t nhub = 0;
+  std::vector<int64_t> hs, qs, gs;  // per-slice starts (S+1): hubs, chunks, segments
+};
+
+HubHost hub_plan(Ctx &x, const Level &g, int S, const Layout &B) {
+  HubHost H;
+  memset(&H.p, 0, sizeof(H.p));
+  H.hs.assign(S + 1, 0);
+  H.qs.assign(S + 1, 0);
+  H.gs.assign(S + 1, 0);
+  for (int s = 0; s < S; ++s)
+    H.hs[s + 1] = H.hs[s] + (B.region[s * kNB + kNB] - B.region[s * kNB + kNB - 1]);
+  H.nhub = H.hs[S];
+  if (H.nhub == 0) return H;
+  const int64_t nh = H.nhub;
+  int32_t *hsoff = x.get<int32_t>(H_soff, S + 1);
+  int32_t *hfill = x.get<int32_t>(H_fill, S);
+  int32_t *up = (int32_t *)x.pin();
+  for (int s = 0; s <= S; ++s) up[s] = (int32_t)H.hs[s];
+  x.check(hipMemcpyAsync(hsoff, up, sizeof(int32_t) * (S + 1), hipMemcpyHostToDevice, x.s), "H2D");
+  x.zero(hfill, S);
+  H.p.hubv = x.get<int32_t>(H_v, nh);
+  hub_find(g.off, g.n, S, hsoff, hfill, H.p.hubv, x.s);
+  int64_t *cnt = x.get<int64_t>(H_cnt, 3 * (nh + 1));
+  hub_sizes(g.off, H.p.hubv, nh, cnt, cnt + (nh + 1), cnt + 2 * (nh + 1), x.s);
+  x.launched("hub plan");
+  H.p.hch = x.get<int64_t>(H_ch, nh + 1);
+  H.p.htab = x.get<int64_t>(H_tab, nh + 1);
+  H.p.hsg = x.get<int64_t>(H_sg, nh + 1);
+  scan_i64(x, cnt, H.p.hch, nh + 1);
+  scan_i64(x, cnt + (nh + 1), H.p.htab, nh + 1);
+  scan_i64(x, cnt + 2 * (nh + 1), H.p.hsg, nh + 1);
+  int64_t *bnd = x.get<int64_t>(H_bnd, 2 * (S + 1) + 1);
+  gather_bounds(H.p.hch, hsoff, S + 1, bnd, x.s);
+  gather_bounds(H.p.hsg, hsoff, S + 1, bnd + (S + 1), x.s);
+  gather_bounds(H.p.htab, hsoff + S, 1, bnd + 2 * (S + 1), x.s);
+  x.launched("hub bounds");
+  int64_t *hb = (int64_t *)((char *)x.pin() + 8192);
+  x.check(hipMemcpyAsync(hb, bnd, sizeof(int64_t) * (2 * (S + 1) + 1), hipMemcpyDeviceToHost, x.s), "D2H");
+  x.check(hipStreamSynchronize(x.s), "sync");
+  for (int s = 0; s <= S; ++s) {
+    H.qs[s] = hb[s];
+    H.gs[s] = hb[S + 1 + s];
+  }
+  const int64_t ntab = hb[2 * (S + 1)];
+  H.p.chub = x.get<int32_t>(H_chub, H.qs[S]);
+  H.p.shub = x.get<int32_t>(H_shub, H.gs[S]);
+  hub_expand(H.p, nh, x.s);
+  H.p.keys = x.get<int>(H_tk, ntab);
+  H.p.vals = x.get<double>(H_tv, ntab);
+  fill_i32(H.p.keys, -1, ntab, x.s);  // empty slots
+  x.zero(H.p.vals, ntab);
+  H.p.own = x.get<double>(H_own, nh);
+  x.zero(H.p.own, nh);
+  H.p.pg = x.get<double>(H_pg, H.gs[S]);
+  H.p.pc = x.get<int32_t>(H_pc, H.gs[S]);
+  x.launched("hub tables");
+  return H;
+}
+
 // Dense relabel of C[0..n) (labels < bound) in ascending order; returns count.
 int64_t renumber_dense(Ctx &x, int32_t *C, int64_t n, int64_t bound) {
   int32_t *flags = x.get<int32_t>(L_flags, bound + 1);
@@ -463,6 +529,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
   int32_t *soff = x.get<int32_t>(L_soff, NS + 1);
   int32_t *sfill = x.get<int32_t>(L_sfill, NS);
   double *tiles = x.get<double>(L_tiles, n / 256 + 2);
+  uint8_t *act = x.get<uint8_t>(L_act, n);
 
   if (p.refine_variant == 1) {
     fill_u8(dC, 1, n, x.s);
@@ -487,6 +554,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     const int64_t nl = g.n;
     const Layout B = level_layout(x, g, NS, region, counts, scnt, soff, sfill, vbs);
     const Hub hub = hub_tables(x, B.nhub, B.nhub > 0 ? max_degree(x, g) : 0);
+    const HubHost hh = hub_plan(x, g, NS, B);
     if (pass > 0) fill_u8(rng, 1, nl, x.s);
     const double Tp = tau * M2 * M2 / 2.0;
 
@@ -499,6 +567,8 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     ma.lists = lists; ma.region = region; ma.counts = counts; ma.nsl = NS; ma.vbyslice = vbs;
     ma.gain = gi ? nullptr : &sc->gain; ma.moves = &sc->moves;
     ma.hub_keys = hub.keys; ma.hub_vals = hub.vals; ma.hub_cap = hub.cap; ma.hub_blocks = hub.blocks;
+    ma.hp = hh.p;
+    ma.act = hh.nhub > 0 ? act : nullptr;
     int li = 0;
     int64_t moves_total = 0;
     tm.mark(CAT_OTHER);
@@ -511,6 +581,9 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
         ma.s = sl;
         ma.vbeg = B.soff[sl];
         ma.vend = B.soff[sl + 1];
+        ma.hbeg = hh.hs[sl]; ma.hend = hh.hs[sl + 1];
+        ma.qbeg = hh.qs[sl]; ma.qend = hh.qs[sl + 1];
+        ma.gbeg = hh.gs[sl]; ma.gend = hh.gs[sl + 1];
         move_frontier(ma, x.s);
         move_propose(ma, B.region.data(), x.s);
         move_apply(ma, B.region.data(), x.s);

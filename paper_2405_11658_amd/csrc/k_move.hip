@@ -25,60 +25,100 @@ __device__ __forceinline__ int bucket_of_d(int64_t deg) {
   return deg <= 4 ? 0 : deg <= 8 ? 1 : deg <= 32 ? 2 : deg <= 256 ? 3 : deg <= 2048 ? 4 : 5;
 }
 
+// Keyed appends are aggregated per workgroup: a tile of kTile vertices is
+// counted into LDS counters, one global atomic per non-empty key reserves
+// the workgroup's range, and a second pass places the items.
+constexpr int kTile = 4096;
+constexpr int kMaxKeys = 2048;  // >= 256 slices * (kNB + 1)
+
 __global__ __launch_bounds__(256) void k_slice_hist(const int64_t *off, int64_t n, int S, int32_t *counts,
                                                     int32_t *slice_cnt) {
-  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = i0 + threadIdx.x;
-    int64_t deg = 0;
-    int sl = 0;
-    if (i < n) {
-      deg = off[i + 1] - off[i];
-      sl = slice_of(i, S);
-    }
-    wave_peel_inc(slice_cnt, sl, i < n);
-    wave_peel_inc(counts, sl * kNB + (deg > 0 ? bucket_of_d(deg) : 0), deg > 0);
+  __shared__ int cnt[kMaxKeys];
+  const int K = S * kNB + S;  // bucket keys, then slice keys
+  for (int k = threadIdx.x; k < K; k += blockDim.x) cnt[k] = 0;
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t deg = off[i + 1] - off[i];
+    const int sl = slice_of(i, S);
+    atomicAdd(&cnt[S * kNB + sl], 1);
+    if (deg > 0) atomicAdd(&cnt[sl * kNB + bucket_of_d(deg)], 1);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const int c = cnt[k];
+    if (c) atomicAdd(k < S * kNB ? &counts[k] : &slice_cnt[k - S * kNB], c);
   }
 }
 void slice_hist(const int64_t *off, int64_t n, int S, int32_t *counts, int32_t *slice_cnt, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_slice_hist, flat_grid(n), 256, 0, s, off, n, S, counts, slice_cnt);
+  if (n > 0) hipLaunchKernelGGL(k_slice_hist, flat_grid(n, 256, 1024), 256, 0, s, off, n, S, counts, slice_cnt);
 }
 
 __global__ __launch_bounds__(256) void k_slice_scatter(int64_t n, int S, const int32_t *slice_off,
                                                        int32_t *slice_fill, int32_t *vbyslice) {
-  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = i0 + threadIdx.x;
-    const int sl = i < n ? slice_of(i, S) : 0;
-    const int pos = wave_peel_inc(slice_fill, sl, i < n);
-    if (i < n) vbyslice[slice_off[sl] + pos] = (int32_t)i;
+  __shared__ int cnt[kMaxKeys];
+  __shared__ int base[kMaxKeys];
+  for (int64_t t0 = (int64_t)blockIdx.x * kTile; t0 < n; t0 += (int64_t)gridDim.x * kTile) {
+    const int64_t t1 = min(t0 + (int64_t)kTile, n);
+    for (int k = threadIdx.x; k < S; k += blockDim.x) cnt[k] = 0;
+    __syncthreads();
+    for (int64_t i = t0 + threadIdx.x; i < t1; i += blockDim.x) atomicAdd(&cnt[slice_of(i, S)], 1);
+    __syncthreads();
+    for (int k = threadIdx.x; k < S; k += blockDim.x) {
+      const int c = cnt[k];
+      base[k] = c ? atomicAdd(&slice_fill[k], c) : 0;
+      cnt[k] = 0;
+    }
+    __syncthreads();
+    for (int64_t i = t0 + threadIdx.x; i < t1; i += blockDim.x) {
+      const int sl = slice_of(i, S);
+      vbyslice[slice_off[sl] + base[sl] + atomicAdd(&cnt[sl], 1)] = (int32_t)i;
+    }
+    __syncthreads();
   }
 }
 void slice_scatter(int64_t n, int S, const int32_t *slice_off, int32_t *slice_fill, int32_t *vbyslice,
                    hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_slice_scatter, flat_grid(n), 256, 0, s, n, S, slice_off, slice_fill, vbyslice);
+  if (n > 0) hipLaunchKernelGGL(k_slice_scatter, flat_grid(ceil_div(n, kTile), 1, 2048), 256, 0, s, n, S,
+                                slice_off, slice_fill, vbyslice);
 }
 
 // Frontier of slice s: its unprocessed vertices become processed; in-range
 // ones with edges are bucketed by degree.  Proposals of the slice are reset.
+__device__ __forceinline__ int frontier_key(const MoveArgs &a, int i) {
+  if (!a.U[i] || !a.rng[i]) return -1;
+  const int64_t deg = a.off[i + 1] - a.off[i];
+  return deg > 0 ? bucket_of_d(deg) : -1;
+}
+
 __global__ __launch_bounds__(256) void k_frontier(MoveArgs a) {
+  __shared__ int cnt[kNB];
+  __shared__ int base[kNB];
   int32_t *counts = a.counts + a.s * kNB;
   const int32_t *region = a.region + a.s * kNB;
-  for (int64_t t0 = a.vbeg + (int64_t)blockIdx.x * blockDim.x; t0 < a.vend; t0 += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t t = t0 + threadIdx.x;
-    int b = -1;
-    int i = 0;
-    if (t < a.vend) {
-      i = a.vbyslice[t];
-      a.prop[i] = -1;
-      if (a.U[i]) {
-        a.U[i] = 0;
-        if (a.rng[i]) {
-          const int64_t deg = a.off[i + 1] - a.off[i];
-          if (deg > 0) b = bucket_of_d(deg);
-        }
-      }
+  for (int64_t t0 = a.vbeg + (int64_t)blockIdx.x * kTile; t0 < a.vend; t0 += (int64_t)gridDim.x * kTile) {
+    const int64_t t1 = min(t0 + (int64_t)kTile, a.vend);
+    if (threadIdx.x < kNB) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
+      const int key = frontier_key(a, a.vbyslice[t]);
+      if (key >= 0) atomicAdd(&cnt[key], 1);
     }
-    const int pos = wave_peel_inc(counts, b < 0 ? 0 : b, b >= 0);
-    if (b >= 0) a.lists[region[b] + pos] = i;
+    __syncthreads();
+    if (threadIdx.x < kNB) {
+      const int c = cnt[threadIdx.x];
+      base[threadIdx.x] = c ? atomicAdd(&counts[threadIdx.x], c) : 0;
+      cnt[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
+      const int i = a.vbyslice[t];
+      const int key = frontier_key(a, i);
+      a.prop[i] = -1;
+      a.U[i] = 0;
+      if (a.act && a.off[i + 1] - a.off[i] > kHubDeg) a.act[i] = key >= 0;
+      if (key >= 0) a.lists[region[key] + base[key] + atomicAdd(&cnt[key], 1)] = i;
+    }
+    __syncthreads();
   }
 }
 
@@ -242,6 +282,133 @@ __global__ __launch_bounds__(BLOCK) void k_propose_team(MoveArgs a, int b) {
   }
 }
 
+// ---- propose: hubs, several workgroups per vertex --------------------------
+// gather: a workgroup merges one edge chunk of a frontier hub in an LDS
+// table, then adds its distinct communities into the hub's global table (the
+// hub's own community into `own`).
+__global__ __launch_bounds__(256) void k_hub_gather(MoveArgs a) {
+  constexpr int T = 2 * kHubEC;
+  __shared__ int keys[T];
+  __shared__ double vals[T];
+  const int64_t q = a.qbeg + blockIdx.x;
+  const int h = a.hp.chub[q];
+  const int i = a.hp.hubv[h];
+  if (!a.act[i]) return;
+  const int64_t e0 = a.off[i] + (q - a.hp.hch[h]) * kHubEC;
+  const int64_t e1 = min(e0 + (int64_t)kHubEC, a.off[i + 1]);
+  for (int s = threadIdx.x; s < T; s += blockDim.x) { keys[s] = kEmpty; vals[s] = 0.0; }
+  __syncthreads();
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const int j = a.idx[e];
+    if (j != i) table_add(keys, vals, T - 1, a.C[j], (double)a.w[e]);
+  }
+  __syncthreads();
+  const int d = a.C[i];
+  const int64_t t0 = a.hp.htab[h];
+  const uint32_t mask = (uint32_t)(a.hp.htab[h + 1] - t0 - 1);
+  for (int s = threadIdx.x; s < T; s += blockDim.x) {
+    const int c = keys[s];
+    if (c == kEmpty) continue;
+    if (c == d) unsafeAtomicAdd(&a.hp.own[h], vals[s]);
+    else table_add(a.hp.keys + t0, a.hp.vals + t0, mask, c, vals[s]);
+  }
+}
+
+// score: a workgroup scans one table segment of a frontier hub, frees the
+// slots it reads, and leaves the segment's best (gain, community).
+__global__ __launch_bounds__(256) void k_hub_score(MoveArgs a) {
+  __shared__ double rg[256 / kWave];
+  __shared__ int rc[256 / kWave];
+  const int64_t q = a.gbeg + blockIdx.x;
+  const int h = a.hp.shub[q];
+  const int i = a.hp.hubv[h];
+  if (!a.act[i]) return;
+  const int64_t s0 = a.hp.htab[h] + (q - a.hp.hsg[h]) * kHubSeg;
+  const int d = a.C[i];
+  const double Ki = a.K[i], Sd = a.Sig[d], bown = a.hp.own[h];
+  double bg = 0.0;
+  int bc = kNoComm;
+  for (int64_t s = s0 + threadIdx.x; s < s0 + kHubSeg; s += blockDim.x) {
+    const int c = a.hp.keys[s];
+    if (c == kEmpty) continue;
+    const double v = a.hp.vals[s];
+    a.hp.keys[s] = kEmpty;
+    a.hp.vals[s] = 0.0;
+    const double x = move_score(a.M2, v, bown, Ki, a.Sig[c], Sd);
+    if (x > 0.0 && better(x, c, bg, bc)) { bg = x; bc = c; }
+  }
+  team_argmax<256, 256>(bg, bc, rg, rc);
+  if (threadIdx.x == 0) { a.hp.pg[q] = bg; a.hp.pc[q] = bc; }
+}
+
+// final: a wavefront per hub of the slice reduces the segment results.
+__global__ __launch_bounds__(256) void k_hub_final(MoveArgs a) {
+  const int64_t h = a.hbeg + ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  if (h >= a.hend) return;  // uniform per wavefront
+  const int i = a.hp.hubv[h];
+  if (!a.act[i]) return;
+  double bg = 0.0;
+  int bc = kNoComm;
+  for (int64_t q = a.hp.hsg[h] + lane(); q < a.hp.hsg[h + 1]; q += kWave)
+    if (better(a.hp.pg[q], a.hp.pc[q], bg, bc)) { bg = a.hp.pg[q]; bc = a.hp.pc[q]; }
+  group_argmax<kWave>(bg, bc);
+  if (lane() == 0) {
+    a.from[i] = a.C[i];
+    a.prop[i] = (bc == kNoComm) ? -1 : bc;
+    a.gp[i] = bg;
+    a.hp.own[h] = 0.0;
+  }
+}
+
+// ---- hub plan -------------------------------------------------------------------
+__global__ void k_hub_find(const int64_t *off, int64_t n, int S, const int32_t *hub_soff, int32_t *hub_fill,
+                           int32_t *hubv) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (off[i + 1] - off[i] <= kHubDeg) continue;
+    const int sl = slice_of(i, S);
+    hubv[hub_soff[sl] + atomicAdd(&hub_fill[sl], 1)] = (int32_t)i;
+  }
+}
+void hub_find(const int64_t *off, int64_t n, int S, const int32_t *hub_soff, int32_t *hub_fill, int32_t *hubv,
+              hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_hub_find, flat_grid(n), 256, 0, s, off, n, S, hub_soff, hub_fill, hubv);
+}
+
+__global__ void k_hub_sizes(const int64_t *off, const int32_t *hubv, int64_t nhub, int64_t *nch, int64_t *ncap,
+                            int64_t *nseg) {
+  for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h <= nhub; h += (int64_t)gridDim.x * blockDim.x) {
+    if (h == nhub) { nch[h] = 0; ncap[h] = 0; nseg[h] = 0; continue; }
+    const int i = hubv[h];
+    const int64_t deg = off[i + 1] - off[i];
+    int64_t cap = kHubSeg;
+    while (cap < 2 * deg) cap <<= 1;
+    nch[h] = ceil_div(deg, (int64_t)kHubEC);
+    ncap[h] = cap;
+    nseg[h] = cap / kHubSeg;
+  }
+}
+void hub_sizes(const int64_t *off, const int32_t *hubv, int64_t nhub, int64_t *nch, int64_t *ncap, int64_t *nseg,
+               hipStream_t s) {
+  hipLaunchKernelGGL(k_hub_sizes, flat_grid(nhub + 1), 256, 0, s, off, hubv, nhub, nch, ncap, nseg);
+}
+
+__global__ void k_hub_expand(HubPlan p, int64_t nhub) {
+  for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < nhub; h += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t q = p.hch[h]; q < p.hch[h + 1]; ++q) p.chub[q] = (int32_t)h;
+    for (int64_t q = p.hsg[h]; q < p.hsg[h + 1]; ++q) p.shub[q] = (int32_t)h;
+  }
+}
+void hub_expand(const HubPlan &h, int64_t nhub, hipStream_t s) {
+  if (nhub > 0) hipLaunchKernelGGL(k_hub_expand, flat_grid(nhub), 256, 0, s, h, nhub);
+}
+
+__global__ void k_gather_bounds(const int64_t *arr, const int32_t *at, int count, int64_t *out) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < count; k += gridDim.x * blockDim.x) out[k] = arr[at[k]];
+}
+void gather_bounds(const int64_t *arr, const int32_t *at, int count, int64_t *out, hipStream_t s) {
+  if (count > 0) hipLaunchKernelGGL(k_gather_bounds, flat_grid(count), 256, 0, s, arr, at, count, out);
+}
+
 // ---- apply: reverse-move resolution and move application ------------------
 __device__ __forceinline__ bool reverse_wins(const MoveArgs &a, int j, int i, int fi, int p, double gi) {
   const int pj = a.prop[j];
@@ -378,7 +545,8 @@ static int grid_for(int64_t cap, int per_block, int maxb = 4096) {
 }
 
 void move_frontier(const MoveArgs &a, hipStream_t s) {
-  if (a.vend > a.vbeg) hipLaunchKernelGGL(k_frontier, flat_grid(a.vend - a.vbeg), 256, 0, s, a);
+  if (a.vend > a.vbeg)
+    hipLaunchKernelGGL(k_frontier, flat_grid(ceil_div(a.vend - a.vbeg, kTile), 1, 2048), 256, 0, s, a);
 }
 
 void move_propose(const MoveArgs &a, const int64_t *region_h, hipStream_t s) {
@@ -391,7 +559,13 @@ void move_propose(const MoveArgs &a, const int64_t *region_h, hipStream_t s) {
       case 2: hipLaunchKernelGGL(k_propose_small<32>, grid_for(cap, 8), 256, 0, s, a, b); break;
       case 3: hipLaunchKernelGGL((k_propose_team<64, 512, 256, false>), grid_for(cap, 4), 256, 0, s, a, b); break;
       case 4: hipLaunchKernelGGL((k_propose_team<256, 4096, 256, false>), grid_for(cap, 1, 2048), 256, 0, s, a, b); break;
-      case 5: hipLaunchKernelGGL((k_propose_team<512, 1, 512, true>), grid_for(cap, 1, a.hub_blocks), 512, 0, s, a, b); break;
+      case 5:
+        if (a.qend > a.qbeg) {
+          hipLaunchKernelGGL(k_hub_gather, (int)(a.qend - a.qbeg), 256, 0, s, a);
+          hipLaunchKernelGGL(k_hub_score, (int)(a.gend - a.gbeg), 256, 0, s, a);
+          hipLaunchKernelGGL(k_hub_final, (int)ceil_div(a.hend - a.hbeg, (int64_t)4), 256, 0, s, a);
+        }
+        break;
     }
   }
 }

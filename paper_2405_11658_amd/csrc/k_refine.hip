@@ -47,34 +47,58 @@ void subset_renumber(int64_t n, int32_t *C, int32_t *rep, const double *Sig, dou
   hipLaunchKernelGGL(k_subset_remap, flat_grid(n), 256, 0, s, n, C, rep, Sig, Sig2, dC, dC2);
 }
 
-// Break changed communities; keep the bounds; bucket the refine candidates.
+// Break changed communities; keep the bounds; bucket the refine candidates
+// by (slice, degree bucket), with per-workgroup reservation of list ranges.
+constexpr int kRTile = 4096;
+constexpr int kRMaxKeys = 2048;  // >= 256 slices * kNB
+
+__device__ __forceinline__ int break_key(const RefineArgs &a, int64_t i, int cb) {
+  if (!a.dC[cb]) return -2;  // not in a changed bound
+  const int64_t deg = a.off[i + 1] - a.off[i];
+  return deg > 0 ? slice_of(i, a.nsl) * kNB + bucket_of_r(deg) : -1;
+}
+
 __global__ __launch_bounds__(256) void k_break(RefineArgs a) {
-  unsigned long long nref = 0;
-  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < a.n; i0 += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = i0 + threadIdx.x;
-    int b = -1;
-    if (i < a.n) {
-      const int cb = a.C[i];
-      a.CB[i] = cb;
-      if (a.dC[cb]) {
-        a.C[i] = (int32_t)i;
-        a.Sig[i] = a.K[i];
-        a.S[i] = 1;
-        a.prop[i] = -1;
-        nref++;
-        const int64_t deg = a.off[i + 1] - a.off[i];
-        if (deg > 0) b = slice_of(i, a.nsl) * kNB + bucket_of_r(deg);
-      }
+  __shared__ int cnt[kRMaxKeys];
+  __shared__ int base[kRMaxKeys];
+  __shared__ long long sl_ref[16];
+  const int K = a.nsl * kNB;
+  long long nref = 0;
+  for (int64_t t0 = (int64_t)blockIdx.x * kRTile; t0 < a.n; t0 += (int64_t)gridDim.x * kRTile) {
+    const int64_t t1 = min(t0 + (int64_t)kRTile, a.n);
+    for (int k = threadIdx.x; k < K; k += blockDim.x) cnt[k] = 0;
+    __syncthreads();
+    for (int64_t i = t0 + threadIdx.x; i < t1; i += blockDim.x) {
+      const int key = break_key(a, i, a.C[i]);
+      if (key >= 0) atomicAdd(&cnt[key], 1);
     }
-    const int pos = wave_peel_inc(a.counts, b < 0 ? 0 : b, b >= 0);
-    if (b >= 0) a.lists[a.region[b] + pos] = (int32_t)i;
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+      const int c = cnt[k];
+      base[k] = c ? atomicAdd(&a.counts[k], c) : 0;
+      cnt[k] = 0;
+    }
+    __syncthreads();
+    for (int64_t i = t0 + threadIdx.x; i < t1; i += blockDim.x) {
+      const int cb = a.C[i];
+      const int key = break_key(a, i, cb);
+      a.CB[i] = cb;
+      if (key == -2) continue;
+      a.C[i] = (int32_t)i;
+      a.Sig[i] = a.K[i];
+      a.S[i] = 1;
+      a.prop[i] = -1;
+      nref++;
+      if (key >= 0) a.lists[a.region[key] + base[key] + atomicAdd(&cnt[key], 1)] = (int32_t)i;
+    }
+    __syncthreads();
   }
-  for (int o = 32; o > 0; o >>= 1) nref += __shfl_xor(nref, o);
-  if (lane() == 0 && nref) atomicAdd(a.refined, nref);
+  const long long tot = block_sum_ll(nref, sl_ref);
+  if (threadIdx.x == 0 && tot) atomicAdd(a.refined, (unsigned long long)tot);
 }
 
 void refine_break(const RefineArgs &a, hipStream_t s) {
-  if (a.n > 0) hipLaunchKernelGGL(k_break, flat_grid(a.n), 256, 0, s, a);
+  if (a.n > 0) hipLaunchKernelGGL(k_break, flat_grid(ceil_div(a.n, kRTile), 1, 2048), 256, 0, s, a);
 }
 
 // ---- refine propose ------------------------------------------------------------

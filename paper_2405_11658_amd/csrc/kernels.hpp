@@ -76,6 +76,26 @@ size_t seg_sort_i32_f32(void *temp, size_t tbytes, const int32_t *kin, int32_t *
                         const int64_t *off, hipStream_t s);
 
 // ---- k_move.hip -------------------------------------------------------------
+// Hub plan of a level: the vertices of the largest degree bucket grouped by
+// slice, each split into edge chunks (one gather workgroup each) and owning
+// a global open-addressing table split into scoring segments.
+constexpr int64_t kHubDeg = 2048;  // degree above which a vertex is a hub
+constexpr int kHubEC = 2048;       // edges per gather workgroup
+constexpr int kHubSeg = 4096;      // table slots per scoring workgroup
+struct HubPlan {
+  int32_t *hubv;   // [nhub] hub ids, slice-major
+  int64_t *hch;    // [nhub+1] first edge chunk of each hub
+  int64_t *htab;   // [nhub+1] first table slot (table sizes are powers of two)
+  int64_t *hsg;    // [nhub+1] first table segment
+  int32_t *chub;   // hub index of each chunk
+  int32_t *shub;   // hub index of each segment
+  int *keys;       // tables, kEmpty when free (scoring leaves them free again)
+  double *vals;
+  double *own;     // [nhub] weight to the hub's own community (zero between uses)
+  double *pg;      // per-segment best gain
+  int32_t *pc;     // per-segment best community
+};
+
 struct MoveArgs {
   // level graph
   int64_t n;
@@ -109,12 +129,27 @@ struct MoveArgs {
   double *hub_vals;
   int64_t hub_cap;       // slots per block (power of two)
   int hub_blocks;
+  // multi-workgroup hub path
+  HubPlan hp;
+  uint8_t *act;          // hub is in the frontier of its slice (written by the frontier)
+  int64_t hbeg, hend;    // hubs of the current slice
+  int64_t qbeg, qend;    // their edge chunks
+  int64_t gbeg, gend;    // their table segments
 };
 // Per level: counts[s*kNB+b] of vertices with edges, slice sizes, and the
 // vertex-by-slice grouping (slice_fill zeroed, slice_off = starts of slices).
 void slice_hist(const int64_t *off, int64_t n, int S, int32_t *counts, int32_t *slice_cnt, hipStream_t s);
 void slice_scatter(int64_t n, int S, const int32_t *slice_off, int32_t *slice_fill, int32_t *vbyslice,
                    hipStream_t s);
+// Hub plan construction (per level): hubs of each slice placed at
+// slice_off[s] + fill; per-hub chunk / slot / segment counts (to be scanned
+// into hch, htab, hsg); expansion into chub / shub; bounds[k] = arr[at[k]].
+void hub_find(const int64_t *off, int64_t n, int S, const int32_t *hub_soff, int32_t *hub_fill, int32_t *hubv,
+              hipStream_t s);
+void hub_sizes(const int64_t *off, const int32_t *hubv, int64_t nhub, int64_t *nch, int64_t *ncap, int64_t *nseg,
+               hipStream_t s);
+void hub_expand(const HubPlan &h, int64_t nhub, hipStream_t s);
+void gather_bounds(const int64_t *arr, const int32_t *at, int count, int64_t *out, hipStream_t s);
 // region_h: host copy of the region starts of this level.
 void move_frontier(const MoveArgs &a, hipStream_t s);
 void move_propose(const MoveArgs &a, const int64_t *region_h, hipStream_t s);

@@ -260,15 +260,10 @@ def batch_count(nnz_directed: int, fraction: float) -> int:
     return max(1, int(round(fraction * nnz_directed)))
 
 
-def random_batch(g: CSR, size: int, ins_frac: float = 0.8, seed: int = 0,
-                 weight: float = 1.0) -> UBatch:
-    """Random batch (Sec. 5.1.4): round(ins_frac*size) insertions of uniformly
-    random vertex pairs that are not edges (no self-loops, no repeats) and the
-    rest deletions of distinct, uniformly chosen existing undirected edges."""
-    rng = _rng(seed)
+def _draw_updates(g: CSR, n_del: int, n_ins: int, rng: np.random.Generator):
+    """n_del distinct existing undirected edges and n_ins distinct non-edge
+    vertex pairs (no self-loops), each in a random orientation for inserts."""
     n = g.n
-    n_ins = int(round(ins_frac * size))
-    n_del = size - n_ins
     src = np.repeat(np.arange(n, dtype=np.int64), np.diff(g.off))
     dst = g.idx.astype(np.int64)
     und = np.flatnonzero(src < dst)
@@ -300,5 +295,33 @@ def random_batch(g: CSR, size: int, ins_frac: float = 0.8, seed: int = 0,
     iu, iv = got // n, got % n
     flip = rng.random(len(iu)) < 0.5
     iu, iv = np.where(flip, iv, iu), np.where(flip, iu, iv)
+    return du, dv, iu, iv
+
+
+def random_batch(g: CSR, size: int, ins_frac: float = 0.8, seed: int = 0,
+                 weight: float = 1.0) -> UBatch:
+    """Random batch (Sec. 5.1.4): round(ins_frac*size) insertions of uniformly
+    random vertex pairs that are not edges (no self-loops, no repeats) and the
+    rest deletions of distinct, uniformly chosen existing undirected edges."""
+    n_ins = int(round(ins_frac * size))
+    du, dv, iu, iv = _draw_updates(g, size - n_ins, n_ins, _rng(seed))
     return UBatch(du.astype(np.int32), dv.astype(np.int32), iu.astype(np.int32),
                   iv.astype(np.int32), np.full(len(iu), weight, np.float32))
+
+
+def batch_stream(g: CSR, size: int, count: int, ins_frac: float = 0.8, seed: int = 0,
+                 weight: float = 1.0) -> list:
+    """`count` random batches of `size` updates each (split as in
+    random_batch) that can be applied one after another starting from g:
+    deletions are distinct edges of g across the whole stream, insertions
+    distinct non-edges of g across the whole stream."""
+    n_ins = int(round(ins_frac * size))
+    n_del = size - n_ins
+    du, dv, iu, iv = _draw_updates(g, n_del * count, n_ins * count, _rng(seed))
+    out = []
+    for k in range(count):
+        d = slice(k * n_del, (k + 1) * n_del)
+        i = slice(k * n_ins, (k + 1) * n_ins)
+        out.append(UBatch(du[d].astype(np.int32), dv[d].astype(np.int32), iu[i].astype(np.int32),
+                          iv[i].astype(np.int32), np.full(len(iu[i]), weight, np.float32)))
+    return out
