@@ -59,14 +59,18 @@ typedef enum { LEIDEN_ND = 1, LEIDEN_DS = 2, LEIDEN_DF = 3 } leiden_mode;
 /* Parameters (Sec. 4.6 and 5.1.2).  leiden_default_params fills the paper's
  * values: tau0 = 0.01, tol_drop = 10, max_iter = 20; max_passes = 10 (not
  * stated in the paper); agg_tol = 1.0 (aggregation never skipped, Sec. 4.6).
- * Local moving and refinement sweep the vertices in nslices hash-ordered
- * slices (default 16); the slices run in order, the vertices of a slice
- * synchronously (the GPU form of the paper's asynchronous sweep).
- * sync_mode = 1 sums the per-iteration gain in a fixed order so results are
- * bit-identical to the CPU oracle's synchronous mode; 0 uses atomics (the
- * move/refine decisions are the same).  refine_variant: 0 Subset Refine
+ * sync_mode = 0 (default): asynchronous local moving and refinement as in
+ * Sec. 4.6 - async_waves wavefronts (0 = 512) sweep the vertex ids in
+ * ascending order and apply each move at once; results depend on timing.
+ * Vertices of degree > 2048 are moved before each sweep, synchronously within
+ * each of nslices hash-ordered slices.  sync_mode = 1: deterministic test
+ * mode - every vertex is swept in nslices hash-ordered slices (default 16),
+ * the slices in order, the vertices of a slice synchronously, the gain summed
+ * in a fixed order; results are bit-identical to the CPU oracle's synchronous
+ * mode.  refine_variant: 0 Subset Refine
  * (Sec. 4.3, default), 1 Full Refine (Sec. 4.2), 2 no continued passes
- * (Sec. 4.1). */
+ * (Sec. 4.1).  profile = 1 times selected kernels with HIP events on the
+ * call's stream (see leiden_stats.prof_*); results are unaffected. */
 typedef struct {
   double tau0;
   double tol_drop;
@@ -76,9 +80,29 @@ typedef struct {
   int32_t sync_mode;
   int32_t refine_variant;
   int32_t nslices; /* 1 .. 256 */
+  int32_t profile; /* 0 or 1 */
+  int32_t async_waves; /* 0 .. 65536, rounded up to a multiple of 4 */
 } leiden_params;
 
 #define LEIDEN_MAX_PASSES 64
+
+/* Kernels timed when leiden_params.profile = 1 (index into leiden_stats.prof_*):
+ *   HUB_GATHER  - local-moving edge scan of vertices of degree > 2048 (one
+ *                 launch per slice and iteration with hubs in the frontier);
+ *                 entries = edges scanned;
+ *   AGG_MERGE   - aggregation entry merge, one launch per aggregated level;
+ *                 entries = level CSR entries, vertices = level vertices with
+ *                 edges;
+ *   MOD_SCAN    - modularity edge scan; entries / vertices of the graph;
+ *   BATCH_MERGE - graph update merge of the old rows with the batch;
+ *                 entries = CSR entries of G^t, vertices = n. */
+enum {
+  LEIDEN_PROF_HUB_GATHER = 0,
+  LEIDEN_PROF_AGG_MERGE = 1,
+  LEIDEN_PROF_MOD_SCAN = 2,
+  LEIDEN_PROF_BATCH_MERGE = 3,
+  LEIDEN_PROF_N = 4
+};
 
 /* Per-call statistics (host struct). */
 typedef struct {
@@ -99,6 +123,13 @@ typedef struct {
   double ms_refine;
   double ms_aggregate;
   double ms_other;      /* renumber, lookup, final relabel, Sigma recompute, modularity */
+  /* with leiden_params.profile = 1: per timed kernel, the number of launches,
+   * their summed duration (HIP events around each launch) and the work they
+   * covered; zero otherwise. */
+  int64_t prof_launches[LEIDEN_PROF_N];
+  double prof_ms[LEIDEN_PROF_N];
+  int64_t prof_entries[LEIDEN_PROF_N];
+  int64_t prof_vertices[LEIDEN_PROF_N];
 } leiden_stats;
 
 /* Batch update (Sec. 3.5, Sec. 5.1.4).  Device arrays; each undirected edge

@@ -41,7 +41,7 @@ enum Slot {
   A_pcnt_item, A_pcnt, A_tcap, A_tstart, A_tkeys, A_tvals,
   // hubs
   H_keys, H_vals, H_v, H_cnt, H_ch, H_tab, H_sg, H_chub, H_shub, H_tk, H_tv, H_own, H_pg, H_pc, H_soff,
-  H_fill, H_bnd, L_act,
+  H_fill, H_bnd, L_act, W_keys, W_vals,
   // primitives
   T_tmp,
   // batch
@@ -68,6 +68,8 @@ struct DevScal {
   int32_t list_count;
   int32_t pad;
   unsigned long long nz;
+  unsigned long long hub_scanned;
+  unsigned long long anext;
 };
 
 struct Workspace {
@@ -76,12 +78,14 @@ struct Workspace {
   void *hpin = nullptr;
   std::string err;
   std::vector<hipEvent_t> events;
+  std::vector<hipEvent_t> kevents;
   ~Workspace() {
     for (auto &b : ws)
       if (b.p) (void)hipFree(b.p);
     if (scal.p) (void)hipFree(scal.p);
     if (hpin) (void)hipHostFree(hpin);
     for (auto e : events) (void)hipEventDestroy(e);
+    for (auto e : kevents) (void)hipEventDestroy(e);
   }
 };
 
@@ -111,11 +115,16 @@ struct Fail {
 
 constexpr size_t kPinBytes = 65536;
 constexpr int kMaxSlices = 256;
+constexpr int kDefaultAsyncWaves = 512;  // wavefronts of the asynchronous sweeps
+constexpr int kMaxAsyncWaves = 65536;
+
+struct KProf;
 
 // Call context: workspace + stream; helpers throw Fail, caught at the ABI.
 struct Ctx {
   Workspace *w;
   hipStream_t s;
+  KProf *kp = nullptr;  // kernel timing, when requested
 
   void check(hipError_t e, const char *what) {
     if (e != hipSuccess) {
@@ -224,6 +233,49 @@ struct Timer {
   }
 };
 
+// Kernel-level timing (leiden_params.profile): HIP events on the call's
+// stream immediately before and after each launch of the timed kernels.
+struct KProf {
+  struct Rec {
+    hipEvent_t a, b;
+    int id;
+    int64_t entries, vertices;
+  };
+  Ctx &x;
+  bool on;
+  std::vector<Rec> recs;
+  size_t used = 0;
+  KProf(Ctx &c, bool enabled) : x(c), on(enabled) {}
+  hipEvent_t ev() {
+    if (used == x.w->kevents.size()) {
+      hipEvent_t e;
+      x.check(hipEventCreate(&e), "hipEventCreate");
+      x.w->kevents.push_back(e);
+    }
+    hipEvent_t e = x.w->kevents[used++];
+    x.check(hipEventRecord(e, x.s), "hipEventRecord");
+    return e;
+  }
+  hipEvent_t begin() { return on ? ev() : nullptr; }
+  void end(hipEvent_t a, int id, int64_t entries, int64_t vertices) {
+    if (!on) return;
+    recs.push_back({a, ev(), id, entries, vertices});
+  }
+  void finish(leiden_stats *st, const unsigned long long *hub_scanned) {
+    if (!on || !st || recs.empty()) return;
+    x.check(hipEventSynchronize(recs.back().b), "hipEventSynchronize");
+    for (const Rec &r : recs) {
+      float ms = 0.f;
+      x.check(hipEventElapsedTime(&ms, r.a, r.b), "hipEventElapsedTime");
+      st->prof_launches[r.id] += 1;
+      st->prof_ms[r.id] += ms;
+      st->prof_entries[r.id] += r.entries;
+      st->prof_vertices[r.id] += r.vertices;
+    }
+    if (hub_scanned) st->prof_entries[LEIDEN_PROF_HUB_GATHER] = (int64_t)x.read(hub_scanned);
+  }
+};
+
 struct Level {
   int64_t n, nnz;
   const int64_t *off;
@@ -244,7 +296,9 @@ double modularity_dev(Ctx &x, const Level &g, const int32_t *C) {
   double *S = x.get<double>(Q_S, g.n);
   x.zero(S, g.n);
   x.zero(sc->acc, 4);
+  hipEvent_t t0 = x.kp ? x.kp->begin() : nullptr;
   modularity_edges(g.off, g.idx, g.w, g.crow, g.n, g.nnz, C, sc->acc, S, x.s);
+  if (x.kp) x.kp->end(t0, LEIDEN_PROF_MOD_SCAN, g.nnz, g.n);
   modularity_comm(S, g.n, sc->acc, x.s);
   x.launched("modularity");
   double acc[4];
@@ -468,7 +522,9 @@ Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, i
   agg_toff(a, x.s);
   x.zero(a.rowlen, ncomm + 1);
   x.zero(a.pcnt, ncomm + 1);
+  hipEvent_t t0 = x.kp ? x.kp->begin() : nullptr;
   agg_items(a, M, x.s);
+  if (x.kp) x.kp->end(t0, LEIDEN_PROF_AGG_MERGE, g.nnz, M);
   agg_caps(a, x.s);
   x.launched("agg_items");
   scan_i64(x, a.tcap, a.tstart, ncomm + 1);
@@ -530,6 +586,10 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
   int32_t *sfill = x.get<int32_t>(L_sfill, NS);
   double *tiles = x.get<double>(L_tiles, n / 256 + 2);
   uint8_t *act = x.get<uint8_t>(L_act, n);
+  const bool async = p.sync_mode == 0;
+  const int NW = async ? (p.async_waves > 0 ? (p.async_waves + 3) / 4 * 4 : kDefaultAsyncWaves) : 0;
+  int *akeys = async ? x.get<int>(W_keys, (int64_t)NW * 2 * kHubDeg) : nullptr;
+  double *avals = async ? x.get<double>(W_vals, (int64_t)NW * 2 * kHubDeg) : nullptr;
 
   if (p.refine_variant == 1) {
     fill_u8(dC, 1, n, x.s);
@@ -569,6 +629,8 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     ma.hub_keys = hub.keys; ma.hub_vals = hub.vals; ma.hub_cap = hub.cap; ma.hub_blocks = hub.blocks;
     ma.hp = hh.p;
     ma.act = hh.nhub > 0 ? act : nullptr;
+    ma.hub_scanned = x.kp && x.kp->on ? &sc->hub_scanned : nullptr;
+    ma.anext = &sc->anext; ma.akeys = akeys; ma.avals = avals;
     int li = 0;
     int64_t moves_total = 0;
     tm.mark(CAT_OTHER);
@@ -584,9 +646,30 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
         ma.hbeg = hh.hs[sl]; ma.hend = hh.hs[sl + 1];
         ma.qbeg = hh.qs[sl]; ma.qend = hh.qs[sl + 1];
         ma.gbeg = hh.gs[sl]; ma.gend = hh.gs[sl + 1];
+        if (async) {
+          // hubs: synchronous among the hubs of the slice; the rest below
+          if (ma.hend == ma.hbeg) continue;
+          move_hub_frontier(ma, x.s);
+          hipEvent_t t0 = x.kp ? x.kp->begin() : nullptr;
+          move_hub_gather(ma, x.s);
+          if (x.kp) x.kp->end(t0, LEIDEN_PROF_HUB_GATHER, 0, 0);
+          move_hub_score(ma, x.s);
+          move_apply_bucket(ma, B.region.data(), kNB - 1, x.s);
+          continue;
+        }
         move_frontier(ma, x.s);
-        move_propose(ma, B.region.data(), x.s);
+        for (int b = 0; b + 1 < kNB; ++b) move_propose_bucket(ma, B.region.data(), b, x.s);
+        if (ma.qend > ma.qbeg) {
+          hipEvent_t t0 = x.kp ? x.kp->begin() : nullptr;
+          move_hub_gather(ma, x.s);
+          if (x.kp) x.kp->end(t0, LEIDEN_PROF_HUB_GATHER, 0, 0);
+          move_hub_score(ma, x.s);
+        }
         move_apply(ma, B.region.data(), x.s);
+      }
+      if (async) {
+        x.zero(&sc->anext, 1);
+        move_async(ma, NW, x.s);
       }
       if (gi) tiled_sum(gi, nl, tiles, &sc->gain, x.s);
       x.launched("move iteration");
@@ -626,14 +709,25 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     ra.prop = prop; ra.gp = gp; ra.lists = lists; ra.region = region; ra.counts = counts; ra.nsl = NS;
     ra.refined = &sc->refined;
     ra.hub_keys = hub.keys; ra.hub_vals = hub.vals; ra.hub_cap = hub.cap; ra.hub_blocks = hub.blocks;
+    ra.anext = &sc->anext; ra.akeys = akeys; ra.avals = avals;
     x.zero(counts, NS * kNB);
     x.zero(&sc->refined, 1);
     refine_break(ra, x.s);
     x.launched("break");
     for (int sl = 0; sl < NS; ++sl) {
       ra.s = sl;
-      refine_propose(ra, B.region.data(), x.s);
+      if (async) {
+        // hubs of the slice (synchronous among themselves), the rest below
+        if (B.region[sl * kNB + kNB] == B.region[sl * kNB + kNB - 1]) continue;
+        refine_propose_bucket(ra, B.region.data(), kNB - 1, x.s);
+      } else {
+        refine_propose(ra, B.region.data(), x.s);
+      }
       refine_accept(ra, B.region.data(), x.s);
+    }
+    if (async) {
+      x.zero(&sc->anext, 1);
+      refine_async(ra, NW, x.s);
     }
     x.launched("refine sweep");
     const int rounds = 1;
@@ -724,7 +818,8 @@ void refresh_crow(Ctx &x, leiden_handle *h) {
 bool valid_params(const leiden_params *p) {
   return p && p->tau0 >= 0 && p->tol_drop > 0 && p->agg_tol > 0 && p->max_iter >= 1 &&
          p->max_passes >= 1 && p->max_passes <= LEIDEN_MAX_PASSES && (p->sync_mode == 0 || p->sync_mode == 1) &&
-         p->refine_variant >= 0 && p->refine_variant <= 2 && p->nslices >= 1 && p->nslices <= kMaxSlices;
+         p->refine_variant >= 0 && p->refine_variant <= 2 && p->nslices >= 1 && p->nslices <= kMaxSlices &&
+         (p->profile == 0 || p->profile == 1) && p->async_waves >= 0 && p->async_waves <= kMaxAsyncWaves;
 }
 
 }  // namespace
@@ -742,6 +837,8 @@ void leiden_default_params(leiden_params *p) {
   p->sync_mode = 0;
   p->refine_variant = 0;
   p->nslices = 16;
+  p->profile = 0;
+  p->async_waves = 0;
 }
 
 const char *leiden_strerror(int32_t status) {
@@ -824,6 +921,9 @@ leiden_status leiden_static(leiden_handle *h, int32_t *membership_out, double *q
   Ctx x{&h->w, (hipStream_t)stream};
   return run_guarded(h->w, [&] {
     Timer tm(x, stats != nullptr);
+    KProf kp(x, stats != nullptr && h->prm.profile != 0);
+    x.kp = &kp;
+    if (kp.on) x.zero(&x.scal()->hub_scanned, 1);
     tm.mark(CAT_OTHER);
     const int64_t n = h->n;
     x.ensure(h->C, (size_t)std::max<int64_t>(n, 1) * sizeof(int32_t));
@@ -859,6 +959,7 @@ leiden_status leiden_static(leiden_handle *h, int32_t *membership_out, double *q
     if (q_out) *q_out = (n > 0) ? modularity_dev(x, g, C) : 0.0;
     tm.mark(CAT_OTHER);
     tm.finish(stats);
+    kp.finish(stats, kp.on ? &x.scal()->hub_scanned : nullptr);
     x.check(hipStreamSynchronize(x.s), "sync");
   });
 }
@@ -878,6 +979,9 @@ leiden_status leiden_update(leiden_handle *h, const leiden_batch *batch, int32_t
   Ctx x{&h->w, (hipStream_t)stream};
   return run_guarded(h->w, [&] {
     Timer tm(x, stats != nullptr);
+    KProf kp(x, stats != nullptr && h->prm.profile != 0);
+    x.kp = &kp;
+    if (kp.on) x.zero(&x.scal()->hub_scanned, 1);
     tm.mark(CAT_OTHER);
     const int64_t n = h->n;
     DevScal *sc = x.scal();
@@ -943,7 +1047,10 @@ leiden_status leiden_update(leiden_handle *h, const leiden_batch *batch, int32_t
     x.ensure(h->t_w, (size_t)std::max<int64_t>(nnz_new, 1) * sizeof(float));
     b.nidx = (int32_t *)h->t_idx.p;
     b.nw = (float *)h->t_w.p;
-    batch_apply(b, x.s);
+    hipEvent_t t0 = x.kp ? x.kp->begin() : nullptr;
+    batch_apply_old(b, x.s);
+    if (x.kp) x.kp->end(t0, LEIDEN_PROF_BATCH_MERGE, nnz_new, n);
+    batch_apply_ins(b, x.s);
     x.launched("batch_apply");
     std::swap(h->g_off, h->t_off);
     std::swap(h->g_idx, h->t_idx);
@@ -1031,6 +1138,7 @@ leiden_status leiden_update(leiden_handle *h, const leiden_batch *batch, int32_t
     if (q_out) *q_out = (n > 0) ? modularity_dev(x, g, (const int32_t *)h->C.p) : 0.0;
     tm.mark(CAT_OTHER);
     tm.finish(stats);
+    kp.finish(stats, kp.on ? &x.scal()->hub_scanned : nullptr);
     x.check(hipStreamSynchronize(x.s), "sync");
   });
 }

@@ -136,8 +136,10 @@ __global__ void k_batch_apply_ins(BatchArgs a) {
   }
 }
 
-void batch_apply(const BatchArgs &a, hipStream_t s) {
+void batch_apply_old(const BatchArgs &a, hipStream_t s) {
   if (a.nnz > 0) hipLaunchKernelGGL(k_batch_apply_old, (int)ceil_div(a.nnz, kChunk), 256, 0, s, a);
+}
+void batch_apply_ins(const BatchArgs &a, hipStream_t s) {
   if (a.E > 0) hipLaunchKernelGGL(k_batch_apply_ins, flat_grid(a.E), 256, 0, s, a);
 }
 

@@ -296,6 +296,7 @@ __global__ __launch_bounds__(256) void k_hub_gather(MoveArgs a) {
   if (!a.act[i]) return;
   const int64_t e0 = a.off[i] + (q - a.hp.hch[h]) * kHubEC;
   const int64_t e1 = min(e0 + (int64_t)kHubEC, a.off[i + 1]);
+  if (a.hub_scanned && threadIdx.x == 0) atomicAdd(a.hub_scanned, (unsigned long long)(e1 - e0));
   for (int s = threadIdx.x; s < T; s += blockDim.x) { keys[s] = kEmpty; vals[s] = 0.0; }
   __syncthreads();
   for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
@@ -550,9 +551,13 @@ void move_frontier(const MoveArgs &a, hipStream_t s) {
 }
 
 void move_propose(const MoveArgs &a, const int64_t *region_h, hipStream_t s) {
-  for (int b = 0; b < kNB; ++b) {
+  for (int b = 0; b < kNB; ++b) move_propose_bucket(a, region_h, b, s);
+}
+
+void move_propose_bucket(const MoveArgs &a, const int64_t *region_h, int b, hipStream_t s) {
+  {
     const int64_t cap = region_h[a.s * kNB + b + 1] - region_h[a.s * kNB + b];
-    if (cap <= 0) continue;
+    if (cap <= 0) return;
     switch (b) {
       case 0: hipLaunchKernelGGL(k_propose_small<4>, grid_for(cap, 64), 256, 0, s, a, b); break;
       case 1: hipLaunchKernelGGL(k_propose_small<8>, grid_for(cap, 32), 256, 0, s, a, b); break;
@@ -560,28 +565,38 @@ void move_propose(const MoveArgs &a, const int64_t *region_h, hipStream_t s) {
       case 3: hipLaunchKernelGGL((k_propose_team<64, 512, 256, false>), grid_for(cap, 4), 256, 0, s, a, b); break;
       case 4: hipLaunchKernelGGL((k_propose_team<256, 4096, 256, false>), grid_for(cap, 1, 2048), 256, 0, s, a, b); break;
       case 5:
-        if (a.qend > a.qbeg) {
-          hipLaunchKernelGGL(k_hub_gather, (int)(a.qend - a.qbeg), 256, 0, s, a);
-          hipLaunchKernelGGL(k_hub_score, (int)(a.gend - a.gbeg), 256, 0, s, a);
-          hipLaunchKernelGGL(k_hub_final, (int)ceil_div(a.hend - a.hbeg, (int64_t)4), 256, 0, s, a);
-        }
+        move_hub_gather(a, s);
+        move_hub_score(a, s);
         break;
     }
   }
 }
 
+void move_hub_gather(const MoveArgs &a, hipStream_t s) {
+  if (a.qend > a.qbeg) hipLaunchKernelGGL(k_hub_gather, (int)(a.qend - a.qbeg), 256, 0, s, a);
+}
+
+void move_hub_score(const MoveArgs &a, hipStream_t s) {
+  if (a.qend > a.qbeg) {
+    hipLaunchKernelGGL(k_hub_score, (int)(a.gend - a.gbeg), 256, 0, s, a);
+    hipLaunchKernelGGL(k_hub_final, (int)ceil_div(a.hend - a.hbeg, (int64_t)4), 256, 0, s, a);
+  }
+}
+
 void move_apply(const MoveArgs &a, const int64_t *region_h, hipStream_t s) {
-  for (int b = 0; b < kNB; ++b) {
-    const int64_t cap = region_h[a.s * kNB + b + 1] - region_h[a.s * kNB + b];
-    if (cap <= 0) continue;
-    switch (b) {
-      case 0: hipLaunchKernelGGL(k_apply_small<4>, grid_for(cap, 64), 256, 0, s, a, b); break;
-      case 1: hipLaunchKernelGGL(k_apply_small<8>, grid_for(cap, 32), 256, 0, s, a, b); break;
-      case 2: hipLaunchKernelGGL(k_apply_small<32>, grid_for(cap, 8), 256, 0, s, a, b); break;
-      case 3: hipLaunchKernelGGL((k_apply_team<64, 256>), grid_for(cap, 4), 256, 0, s, a, b); break;
-      case 4: hipLaunchKernelGGL((k_apply_team<256, 256>), grid_for(cap, 1, 2048), 256, 0, s, a, b); break;
-      case 5: hipLaunchKernelGGL((k_apply_team<512, 512>), grid_for(cap, 1, 1024), 512, 0, s, a, b); break;
-    }
+  for (int b = 0; b < kNB; ++b) move_apply_bucket(a, region_h, b, s);
+}
+
+void move_apply_bucket(const MoveArgs &a, const int64_t *region_h, int b, hipStream_t s) {
+  const int64_t cap = region_h[a.s * kNB + b + 1] - region_h[a.s * kNB + b];
+  if (cap <= 0) return;
+  switch (b) {
+    case 0: hipLaunchKernelGGL(k_apply_small<4>, grid_for(cap, 64), 256, 0, s, a, b); break;
+    case 1: hipLaunchKernelGGL(k_apply_small<8>, grid_for(cap, 32), 256, 0, s, a, b); break;
+    case 2: hipLaunchKernelGGL(k_apply_small<32>, grid_for(cap, 8), 256, 0, s, a, b); break;
+    case 3: hipLaunchKernelGGL((k_apply_team<64, 256>), grid_for(cap, 4), 256, 0, s, a, b); break;
+    case 4: hipLaunchKernelGGL((k_apply_team<256, 256>), grid_for(cap, 1, 2048), 256, 0, s, a, b); break;
+    case 5: hipLaunchKernelGGL((k_apply_team<512, 512>), grid_for(cap, 1, 1024), 512, 0, s, a, b); break;
   }
 }
 

@@ -253,17 +253,19 @@ static int rgrid(int64_t cap, int per_block, int maxb = 4096) {
 }
 
 void refine_propose(const RefineArgs &a, const int64_t *region_h, hipStream_t s) {
-  for (int b = 0; b < kNB; ++b) {
-    const int64_t cap = region_h[a.s * kNB + b + 1] - region_h[a.s * kNB + b];
-    if (cap <= 0) continue;
-    switch (b) {
-      case 0: hipLaunchKernelGGL(k_rprop_small<4>, rgrid(cap, 64), 256, 0, s, a, b); break;
-      case 1: hipLaunchKernelGGL(k_rprop_small<8>, rgrid(cap, 32), 256, 0, s, a, b); break;
-      case 2: hipLaunchKernelGGL(k_rprop_small<32>, rgrid(cap, 8), 256, 0, s, a, b); break;
-      case 3: hipLaunchKernelGGL((k_rprop_team<64, 512, 256, false>), rgrid(cap, 4), 256, 0, s, a, b); break;
-      case 4: hipLaunchKernelGGL((k_rprop_team<256, 4096, 256, false>), rgrid(cap, 1, 2048), 256, 0, s, a, b); break;
-      case 5: hipLaunchKernelGGL((k_rprop_team<512, 1, 512, true>), rgrid(cap, 1, a.hub_blocks), 512, 0, s, a, b); break;
-    }
+  for (int b = 0; b < kNB; ++b) refine_propose_bucket(a, region_h, b, s);
+}
+
+void refine_propose_bucket(const RefineArgs &a, const int64_t *region_h, int b, hipStream_t s) {
+  const int64_t cap = region_h[a.s * kNB + b + 1] - region_h[a.s * kNB + b];
+  if (cap <= 0) return;
+  switch (b) {
+    case 0: hipLaunchKernelGGL(k_rprop_small<4>, rgrid(cap, 64), 256, 0, s, a, b); break;
+    case 1: hipLaunchKernelGGL(k_rprop_small<8>, rgrid(cap, 32), 256, 0, s, a, b); break;
+    case 2: hipLaunchKernelGGL(k_rprop_small<32>, rgrid(cap, 8), 256, 0, s, a, b); break;
+    case 3: hipLaunchKernelGGL((k_rprop_team<64, 512, 256, false>), rgrid(cap, 4), 256, 0, s, a, b); break;
+    case 4: hipLaunchKernelGGL((k_rprop_team<256, 4096, 256, false>), rgrid(cap, 1, 2048), 256, 0, s, a, b); break;
+    case 5: hipLaunchKernelGGL((k_rprop_team<512, 1, 512, true>), rgrid(cap, 1, a.hub_blocks), 512, 0, s, a, b); break;
   }
 }
 

@@ -135,6 +135,11 @@ struct MoveArgs {
   int64_t hbeg, hend;    // hubs of the current slice
   int64_t qbeg, qend;    // their edge chunks
   int64_t gbeg, gend;    // their table segments
+  unsigned long long *hub_scanned;  // nullable: edges scanned by the hub gather
+  // asynchronous sweep
+  unsigned long long *anext;  // device counter of the next vertex id chunk (zeroed per sweep)
+  int *akeys;                 // per-wavefront global tables, 2*kHubDeg slots each
+  double *avals;
 };
 // Per level: counts[s*kNB+b] of vertices with edges, slice sizes, and the
 // vertex-by-slice grouping (slice_fill zeroed, slice_off = starts of slices).
@@ -153,6 +158,11 @@ void gather_bounds(const int64_t *arr, const int32_t *at, int count, int64_t *ou
 // region_h: host copy of the region starts of this level.
 void move_frontier(const MoveArgs &a, hipStream_t s);
 void move_propose(const MoveArgs &a, const int64_t *region_h, hipStream_t s);
+void move_propose_bucket(const MoveArgs &a, const int64_t *region_h, int b, hipStream_t s);
+void move_apply_bucket(const MoveArgs &a, const int64_t *region_h, int b, hipStream_t s);
+// the two halves of bucket kNB-1 (hubs): chunk gather, then segment scoring + final argmax
+void move_hub_gather(const MoveArgs &a, hipStream_t s);
+void move_hub_score(const MoveArgs &a, hipStream_t s);
 void move_apply(const MoveArgs &a, const int64_t *region_h, hipStream_t s);
 // out = sum of gi in ascending 256-tiles then sequentially (fixed order).
 void tiled_sum(const double *gi, int64_t n, double *tiles, double *out, hipStream_t s);
@@ -184,10 +194,24 @@ struct RefineArgs {
   double *hub_vals;
   int64_t hub_cap;
   int hub_blocks;
+  // asynchronous sweep
+  unsigned long long *anext;
+  int *akeys;
+  double *avals;
 };
 void refine_break(const RefineArgs &a, hipStream_t s);
+void refine_propose_bucket(const RefineArgs &a, const int64_t *region_h, int b, hipStream_t s);
 void refine_propose(const RefineArgs &a, const int64_t *region_h, hipStream_t s);
 void refine_accept(const RefineArgs &a, const int64_t *region_h, hipStream_t s);
+
+// ---- k_async.hip ---------------------------------------------------------------
+constexpr int kAsyncChunk = 64;  // vertex ids taken per grab of the asynchronous sweeps
+// `waves` wavefronts (a multiple of 4) sweep the ids; vertices of degree
+// <= kHubDeg only.  Tables: 2*kHubDeg slots per wavefront in akeys/avals.
+void move_async(const MoveArgs &a, int waves, hipStream_t s);
+void refine_async(const RefineArgs &a, int waves, hipStream_t s);
+// hub frontier of slice a.s (a.hbeg..a.hend of the hub plan) for the hub-only sliced phase
+void move_hub_frontier(const MoveArgs &a, hipStream_t s);
 
 // ---- k_aggregate.hip -----------------------------------------------------------
 struct AggArgs {
@@ -270,7 +294,8 @@ struct BatchArgs {
 void batch_build(const BatchArgs &a, hipStream_t s);
 void batch_dups_rows(const BatchArgs &a, hipStream_t s);  // dup check + per-row counts/segments
 void batch_newdeg(const BatchArgs &a, hipStream_t s);
-void batch_apply(const BatchArgs &a, hipStream_t s);      // needs newoff, delpre
+void batch_apply_old(const BatchArgs &a, hipStream_t s);  // surviving old entries, merge positions
+void batch_apply_ins(const BatchArgs &a, hipStream_t s);  // inserted entries
 
 struct MarkArgs {
   int64_t n;

@@ -31,10 +31,16 @@ class LeidenError(RuntimeError):
         self.status = status
 
 
+# kernels timed with leiden_params.profile = 1, in LEIDEN_PROF_* order
+PROF_KERNELS = ("hub_gather", "agg_merge", "mod_scan", "batch_merge")
+PROF_N = len(PROF_KERNELS)
+
+
 class leiden_params(ct.Structure):
     _fields_ = [("tau0", ct.c_double), ("tol_drop", ct.c_double), ("agg_tol", ct.c_double),
                 ("max_iter", ct.c_int32), ("max_passes", ct.c_int32),
-                ("sync_mode", ct.c_int32), ("refine_variant", ct.c_int32), ("nslices", ct.c_int32)]
+                ("sync_mode", ct.c_int32), ("refine_variant", ct.c_int32), ("nslices", ct.c_int32),
+                ("profile", ct.c_int32), ("async_waves", ct.c_int32)]
 
 
 class leiden_stats(ct.Structure):
@@ -48,7 +54,9 @@ class leiden_stats(ct.Structure):
                 ("affected", ct.c_int64), ("changed", ct.c_int64), ("moves_pass0", ct.c_int64),
                 ("ms_total", ct.c_double), ("ms_apply", ct.c_double), ("ms_mark", ct.c_double),
                 ("ms_move", ct.c_double), ("ms_refine", ct.c_double), ("ms_aggregate", ct.c_double),
-                ("ms_other", ct.c_double)]
+                ("ms_other", ct.c_double),
+                ("prof_launches", ct.c_int64 * PROF_N), ("prof_ms", ct.c_double * PROF_N),
+                ("prof_entries", ct.c_int64 * PROF_N), ("prof_vertices", ct.c_int64 * PROF_N)]
 
     def to_dict(self) -> dict:
         p = self.passes
@@ -61,6 +69,9 @@ class leiden_stats(ct.Structure):
              "affected": self.affected, "changed": self.changed, "moves_pass0": self.moves_pass0}
         for k in ("ms_total", "ms_apply", "ms_mark", "ms_move", "ms_refine", "ms_aggregate", "ms_other"):
             d[k] = getattr(self, k)
+        d["prof"] = {name: {"launches": self.prof_launches[k], "ms": self.prof_ms[k],
+                            "entries": self.prof_entries[k], "vertices": self.prof_vertices[k]}
+                     for k, name in enumerate(PROF_KERNELS)}
         return d
 
 
