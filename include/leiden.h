@@ -188,6 +188,43 @@ leiden_status leiden_update(leiden_handle *h, const leiden_batch *batch, int32_t
                             int32_t *membership_out, double *q_out, leiden_stats *stats,
                             const leiden_trace *trace, void *stream);
 
+/* Batched form of leiden_update for many independent graphs (the update of
+ * Sec. 3.5 applied to each).  handles[k] (host array of distinct handles),
+ * batches[k], modes[k] and, when non-NULL, membership_out[k] (host array of
+ * device pointers), q_out[k] (host), stats[k] (host) and status_out[k]
+ * (host) are as for one leiden_update call.  The updates run concurrently,
+ * each on a library-created stream driven by one of max_parallel host worker
+ * threads (0 = 8, at most 64), ordered after the work already enqueued on
+ * `stream`; `stream` waits for all of them.  A failing update does not stop
+ * the others; the return value is the first non-OK status in index order.
+ * A handle listed twice is LEIDEN_EINVAL (nothing runs). */
+leiden_status leiden_update_many(leiden_handle *const *handles, const leiden_batch *batches,
+                                 const int32_t *modes, int32_t count, int32_t *const *membership_out,
+                                 double *q_out, leiden_stats *stats, leiden_status *status_out,
+                                 int32_t max_parallel, void *stream);
+
+/* Serving loop over many resident graphs (handles): update requests are
+ * queued by leiden_server_submit and run as they are admitted - up to
+ * `slots` at a time (1 .. 64), each on a stream and host worker of its own,
+ * while the summed device-memory estimate of the running requests stays
+ * within memory_budget bytes (0 = unlimited; a request is always admitted
+ * when nothing else runs) and no other request of the same handle runs.  A
+ * request that does not fit lets later ones that do go first.  The batch
+ * arrays and membership_out (device, nullable) must stay valid, and the
+ * handle must not be used by the caller, until leiden_server_wait for the
+ * request returns.  wait blocks until the request is done and returns its
+ * status, modularity, stats (host, each nullable), the latency from
+ * submission to completion and the service time (host clock, ms); each id
+ * can be waited for once.  destroy finishes every submitted request first. */
+typedef struct leiden_server leiden_server;
+leiden_status leiden_server_create(int32_t slots, int64_t memory_budget, leiden_server **out);
+leiden_status leiden_server_submit(leiden_server *server, leiden_handle *h, const leiden_batch *batch,
+                                   int32_t mode, int32_t *membership_out, int64_t *request_id /* host */);
+leiden_status leiden_server_wait(leiden_server *server, int64_t request_id, leiden_status *status,
+                                 double *q_out, leiden_stats *stats, double *latency_ms,
+                                 double *service_ms);
+leiden_status leiden_server_destroy(leiden_server *server);
+
 /* Eq. 1 in FP64 for any CSR graph and membership (labels in [0, n));
  * q_out (host) is 0 when the graph has no edges.  Stateless. */
 leiden_status leiden_modularity(int64_t n, const int64_t *offsets, const int32_t *indices,

@@ -1,0 +1,206 @@
+// Serving loop for many resident dynamic graphs (see leiden_server_* in
+// include/leiden.h).  Requests (an update batch for one handle) are queued on
+// submission; a dispatcher admits them into free worker slots as long as the
+// device-memory estimate of the admitted work stays within the budget and the
+// request's handle is not already being updated (a handle is used by one
+// thread at a time).  A request that does not fit does not block later ones
+// that do (continuous batching).  Each worker drives its own stream, so the
+// admitted updates overlap on the device.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
+#include "leiden.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+  int64_t id;
+  leiden_handle *h;
+  leiden_batch b;
+  int32_t mode;
+  int32_t *out;
+  int64_t bytes;
+  Clock::time_point submitted;
+  // results
+  leiden_status st = LEIDEN_OK;
+  double q = 0.0;
+  leiden_stats stats;
+  double latency_ms = 0.0;
+  double service_ms = 0.0;
+  bool done = false;
+};
+
+// Device bytes an update of this batch may add to the handle's working set:
+// the directed batch (keys, values, sorted copies, weights, flags) and the
+// grown CSR.
+int64_t request_bytes(const leiden_handle *h, const leiden_batch &b) {
+  const int64_t E = 2 * (b.n_del + b.n_ins);
+  return 64 * E + 8 * 2 * b.n_ins + 16 * (leiden_num_vertices(h) + 1) / 64;
+}
+
+}  // namespace
+
+struct leiden_server {
+  int slots = 0;
+  int64_t budget = 0;
+  int device = 0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Request *> queue;
+  std::unordered_map<int64_t, Request *> reqs;
+  std::unordered_set<const leiden_handle *> busy;
+  int64_t in_use = 0;
+  int64_t next_id = 1;
+  bool stop = false;
+  std::vector<std::thread> workers;
+  // counters
+  int64_t completed = 0;
+
+  // first queued request that fits; nullptr if none (called with mu held)
+  Request *admit() {
+    for (auto it = queue.begin(); it != queue.end(); ++it) {
+      Request *r = *it;
+      if (busy.count(r->h)) continue;
+      if (in_use > 0 && in_use + r->bytes > budget) continue;
+      queue.erase(it);
+      busy.insert(r->h);
+      in_use += r->bytes;
+      return r;
+    }
+    return nullptr;
+  }
+
+  void worker() {
+    (void)hipSetDevice(device);
+    hipStream_t s;
+    const bool ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+    for (;;) {
+      Request *r = nullptr;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv_work.wait(lk, [&] { return stop || (r = admit()) != nullptr; });
+      }
+      if (!r) break;
+      const Clock::time_point t0 = Clock::now();
+      if (ok)
+        r->st = leiden_update(r->h, &r->b, r->mode, r->out, &r->q, &r->stats, nullptr, s);
+      else
+        r->st = LEIDEN_EHIP;
+      const Clock::time_point t1 = Clock::now();
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        r->service_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        r->latency_ms = std::chrono::duration<double, std::milli>(t1 - r->submitted).count();
+        r->done = true;
+        busy.erase(r->h);
+        in_use -= r->bytes;
+        ++completed;
+      }
+      cv_work.notify_all();
+      cv_done.notify_all();
+    }
+    if (ok) (void)hipStreamDestroy(s);
+  }
+};
+
+extern "C" leiden_status leiden_server_create(int32_t slots, int64_t memory_budget, leiden_server **out) {
+  if (!out || slots < 1 || slots > 64 || memory_budget < 0) return LEIDEN_EINVAL;
+  *out = nullptr;
+  leiden_server *sv = new (std::nothrow) leiden_server();
+  if (!sv) return LEIDEN_ENOMEM;
+  sv->slots = slots;
+  sv->budget = memory_budget > 0 ? memory_budget : ((int64_t)1 << 62);
+  if (hipGetDevice(&sv->device) != hipSuccess) {
+    delete sv;
+    return LEIDEN_EHIP;
+  }
+  try {
+    for (int k = 0; k < slots; ++k) sv->workers.emplace_back([sv] { sv->worker(); });
+  } catch (...) {
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      sv->stop = true;
+    }
+    sv->cv_work.notify_all();
+    for (auto &t : sv->workers) t.join();
+    delete sv;
+    return LEIDEN_ENOMEM;
+  }
+  *out = sv;
+  return LEIDEN_OK;
+}
+
+extern "C" leiden_status leiden_server_submit(leiden_server *sv, leiden_handle *h, const leiden_batch *batch,
+                                              int32_t mode, int32_t *membership_out, int64_t *request_id) {
+  if (!sv || !h || !batch || !request_id) return LEIDEN_EINVAL;
+  if (mode != LEIDEN_ND && mode != LEIDEN_DS && mode != LEIDEN_DF) return LEIDEN_EINVAL;
+  Request *r = new (std::nothrow) Request();
+  if (!r) return LEIDEN_ENOMEM;
+  r->h = h;
+  r->b = *batch;
+  r->mode = mode;
+  r->out = membership_out;
+  r->bytes = request_bytes(h, *batch);
+  r->submitted = Clock::now();
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->stop) {
+      delete r;
+      return LEIDEN_EINVAL;
+    }
+    r->id = sv->next_id++;
+    sv->reqs[r->id] = r;
+    sv->queue.push_back(r);
+    *request_id = r->id;
+  }
+  sv->cv_work.notify_all();
+  return LEIDEN_OK;
+}
+
+extern "C" leiden_status leiden_server_wait(leiden_server *sv, int64_t request_id, leiden_status *status,
+                                            double *q_out, leiden_stats *stats, double *latency_ms,
+                                            double *service_ms) {
+  if (!sv) return LEIDEN_EINVAL;
+  std::unique_lock<std::mutex> lk(sv->mu);
+  auto it = sv->reqs.find(request_id);
+  if (it == sv->reqs.end()) return LEIDEN_EINVAL;
+  Request *r = it->second;
+  sv->cv_done.wait(lk, [&] { return r->done; });
+  if (status) *status = r->st;
+  if (q_out) *q_out = r->q;
+  if (stats) *stats = r->stats;
+  if (latency_ms) *latency_ms = r->latency_ms;
+  if (service_ms) *service_ms = r->service_ms;
+  sv->reqs.erase(it);
+  delete r;
+  return LEIDEN_OK;
+}
+
+extern "C" leiden_status leiden_server_destroy(leiden_server *sv) {
+  if (!sv) return LEIDEN_EINVAL;
+  {
+    std::unique_lock<std::mutex> lk(sv->mu);
+    // finish everything already submitted
+    sv->cv_done.wait(lk, [&] {
+      for (auto &kv : sv->reqs)
+        if (!kv.second->done) return false;
+      return true;
+    });
+    sv->stop = true;
+  }
+  sv->cv_work.notify_all();
+  for (auto &t : sv->workers) t.join();
+  for (auto &kv : sv->reqs) delete kv.second;
+  delete sv;
+  return LEIDEN_OK;
+}

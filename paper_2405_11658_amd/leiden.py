@@ -104,6 +104,11 @@ def load() -> ct.CDLL:
         "leiden_set_params": (i32, [P, P]),
         "leiden_static": (i32, [P, P, P, P, P]),
         "leiden_update": (i32, [P, P, i32, P, P, P, P, P]),
+        "leiden_update_many": (i32, [P, P, P, i32, P, P, P, P, i32, P]),
+        "leiden_server_create": (i32, [i32, i64, P]),
+        "leiden_server_submit": (i32, [P, P, P, i32, P, P]),
+        "leiden_server_wait": (i32, [P, i64, P, P, P, P, P]),
+        "leiden_server_destroy": (i32, [P]),
         "leiden_modularity": (i32, [i64, P, P, P, P, P, P]),
         "leiden_aggregate": (i32, [i64, P, P, P, P, i64, P, P, P, P, P]),
         "leiden_get_graph": (i32, [P, P, P, P, P, P]),
@@ -228,6 +233,76 @@ def leiden_update(h: Handle, batch, mode, want_q: bool = True, trace: bool = Fal
     if tr is not None:
         tr = {k: v[:h.n] for k, v in tr.items()}
     return out, (q.value if want_q else None), st.to_dict(), tr
+
+
+def leiden_update_many(handles, batches, modes, want_q: bool = True, max_parallel: int = 0):
+    """Batched updates of distinct handles (run concurrently by the library).
+    Returns a list of (membership, q or None, stats dict, status) per handle;
+    raises LeidenError only for a malformed call (nothing ran)."""
+    lib = load()
+    k = len(handles)
+    H = (ct.c_void_p * k)(*[h.ptr for h in handles])
+    B = (leiden_batch * k)()
+    keep = []
+    for j, (du, dv, iu, iv, iw) in enumerate(batches):
+        B[j] = leiden_batch(du.numel(), _ptr(du), _ptr(dv), iu.numel(), _ptr(iu), _ptr(iv), _ptr(iw))
+        keep.append((du, dv, iu, iv, iw))
+    M = (ct.c_int32 * k)(*[MODES[m] if isinstance(m, str) else int(m) for m in modes])
+    outs = [torch.empty(h.n, dtype=torch.int32, device="cuda") for h in handles]
+    O = (ct.c_void_p * k)(*[_ptr(o) for o in outs])
+    Q = (ct.c_double * k)()
+    S = (leiden_stats * k)()
+    ST = (ct.c_int32 * k)()
+    st = lib.leiden_update_many(H, B, M, k, O, Q if want_q else None, S, ST, max_parallel, _stream())
+    if st != OK and all(x == OK for x in ST):
+        raise LeidenError(st, "leiden_update_many")
+    return [(outs[j], (Q[j] if want_q else None), S[j].to_dict(), int(ST[j])) for j in range(k)]
+
+
+class Server:
+    """leiden_server_*: queued update requests over resident handles."""
+
+    def __init__(self, slots: int = 4, memory_budget: int = 0):
+        self.ptr = ct.c_void_p()
+        _check(load().leiden_server_create(slots, memory_budget, ct.byref(self.ptr)), None,
+               "leiden_server_create")
+        self._pending = {}
+
+    def submit(self, h: Handle, batch, mode) -> int:
+        """Queue an update of handle h; returns the request id."""
+        if isinstance(mode, str):
+            mode = MODES[mode]
+        du, dv, iu, iv, iw = batch
+        b = leiden_batch(du.numel(), _ptr(du), _ptr(dv), iu.numel(), _ptr(iu), _ptr(iv), _ptr(iw))
+        out = torch.empty(h.n, dtype=torch.int32, device="cuda")
+        rid = ct.c_int64()
+        _check(load().leiden_server_submit(self.ptr, h.ptr, ct.byref(b), int(mode), _ptr(out), ct.byref(rid)),
+               None, "leiden_server_submit")
+        self._pending[rid.value] = (out, b, batch, h)  # keep buffers alive until wait
+        return rid.value
+
+    def wait(self, rid: int):
+        """Block until request rid is done: (status, membership, q, stats, latency_ms, service_ms)."""
+        st = ct.c_int32()
+        q = ct.c_double()
+        s = leiden_stats()
+        lat = ct.c_double()
+        svc = ct.c_double()
+        _check(load().leiden_server_wait(self.ptr, rid, ct.byref(st), ct.byref(q), ct.byref(s), ct.byref(lat),
+                                         ct.byref(svc)), None, "leiden_server_wait")
+        out, _, _, _ = self._pending.pop(rid)
+        return st.value, out, q.value, s.to_dict(), lat.value, svc.value
+
+    def close(self):
+        if self.ptr:
+            load().leiden_server_destroy(self.ptr)
+            self.ptr = None
+            self._pending.clear()
+
+    def __del__(self):
+        if self.ptr and _lib is not None:
+            _lib.leiden_server_destroy(self.ptr)
+            self.ptr = None
 
 
 def leiden_modularity(off, idx, w, membership) -> float:

@@ -57,3 +57,39 @@ def test_binding_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(L, "_lib", None)
     with pytest.raises(ImportError):
         L.load()
+
+
+def test_update_many_argument_checks_without_a_device():
+    lib = ct.CDLL(LIB)
+    f = lib.leiden_update_many
+    f.restype = ct.c_int32
+    P, i32 = ct.c_void_p, ct.c_int32
+    f.argtypes = [P, P, P, i32, P, P, P, P, i32, P]
+    assert f(None, None, None, 0, None, None, None, None, 0, None) == 0      # nothing to do
+    assert f(None, None, None, -1, None, None, None, None, 0, None) == 1     # negative count
+    assert f(None, None, None, 2, None, None, None, None, 0, None) == 1     # missing arrays
+    fake = (ct.c_void_p * 2)(0x1000, 0x1000)                                 # the same handle twice
+    modes = (ct.c_int32 * 2)(3, 3)
+    batches = (ct.c_char * 256)()
+    assert f(fake, batches, modes, 2, None, None, None, None, 0, None) == 1
+    nulls = (ct.c_void_p * 2)(None, None)
+    assert f(nulls, batches, modes, 2, None, None, None, None, 0, None) == 1
+    assert f(fake, batches, modes, 1, None, None, None, None, 65, None) == 1  # too many workers
+
+
+def test_server_argument_checks_without_a_device():
+    lib = ct.CDLL(LIB)
+    P = ct.c_void_p
+    lib.leiden_server_create.restype = ct.c_int32
+    lib.leiden_server_create.argtypes = [ct.c_int32, ct.c_int64, P]
+    out = ct.c_void_p()
+    assert lib.leiden_server_create(0, 0, ct.byref(out)) == 1     # no slots
+    assert lib.leiden_server_create(65, 0, ct.byref(out)) == 1    # too many
+    assert lib.leiden_server_create(2, -1, ct.byref(out)) == 1    # negative budget
+    assert lib.leiden_server_create(2, 0, None) == 1
+    for name, args in (("leiden_server_submit", (None, None, None, 3, None, None)),
+                       ("leiden_server_wait", (None, 1, None, None, None, None, None)),
+                       ("leiden_server_destroy", (None,))):
+        f = getattr(lib, name)
+        f.restype = ct.c_int32
+        assert f(*args) == 1

@@ -247,3 +247,61 @@ def test_create_rejects_bad_graphs():
     h = L.leiden_create(g.off, perm_idx, perm_w)
     off, idx, w = [to_np(t) for t in L.leiden_get_graph(h)]
     assert np.array_equal(idx, g.idx) and np.array_equal(w, g.w)
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("name,g", [
+    ("C1_planted4096", gen.planted_partition(4096, 64, 0.1, 0.001, seed=1)),
+    ("rmat13", gen.rmat(13, 8, seed=6)),
+])
+def test_refine_variants_sync_bit_exact(variant, name, g):
+    """Full Refine (Sec. 4.2) and no continued passes (Sec. 4.1): static and
+    one DF update, identical to the oracle in synchronous mode."""
+    h = L.leiden_create(g.off, g.idx, g.w, sync_params(refine_variant=variant))
+    prm = oracle.make_params(sync=True, refine_variant=variant)
+    say("refine variant", variant, name)
+    C, q, st = L.leiden_static(h)
+    state, ostats = oracle.static(og(g), prm)
+    assert np.array_equal(to_np(C), state.C)
+    for k in STAT_KEYS:
+        assert st[k] == ostats[k], (k, st[k], ostats[k])
+    b = gen.random_batch(g, gen.batch_count(g.nnz, 1e-3), seed=11)
+    C, q, st, _ = L.leiden_update(h, dev_batch(b), "df")
+    new, _, _, ostats = oracle.update(state, ob(b), "df", prm)
+    assert np.array_equal(to_np(C), new.C)
+    for k in STAT_KEYS:
+        assert st[k] == ostats[k], (k, st[k], ostats[k])
+    qo = oracle.modularity(new.g, new.C)
+    assert abs(q - qo) <= 1e-9 * max(1.0, abs(qo))
+
+
+def test_update_many_matches_single_updates():
+    """Batched updates of several graphs equal the same updates run one at a
+    time (synchronous mode: identical memberships); a malformed batch fails
+    alone."""
+    graphs = [gen.planted_partition(4096, 64, 0.1, 0.001, seed=1), gen.rmat(13, 8, seed=6),
+              gen.grid2d(64, 0.05, 0.02, seed=1), gen.planted_partition(1024, 16, 0.15, 0.004, seed=7)]
+    many, single, batches = [], [], []
+    for k, g in enumerate(graphs):
+        a = L.leiden_create(g.off, g.idx, g.w, sync_params())
+        b = L.leiden_create(g.off, g.idx, g.w, sync_params())
+        L.leiden_static(a)
+        L.leiden_static(b)
+        many.append(a)
+        single.append(b)
+        batches.append(gen.random_batch(g, gen.batch_count(g.nnz, 1e-3), seed=20 + k))
+    bad = gen.UBatch(np.array([0], np.int32), np.array([0], np.int32), np.zeros(0, np.int32),
+                     np.zeros(0, np.int32), np.zeros(0, np.float32))  # self-loop deletion: invalid
+    say("update_many over", len(graphs), "graphs + 1 invalid")
+    g5 = gen.clique_ring(4, 5)
+    h5 = L.leiden_create(g5.off, g5.idx, g5.w, sync_params())
+    L.leiden_static(h5)
+    res = L.leiden_update_many(many + [h5], [dev_batch(b) for b in batches] + [dev_batch(bad)],
+                               ["df", "ds", "nd", "df", "df"], max_parallel=3)
+    assert res[-1][3] == L.EINVAL
+    for k, (h, b) in enumerate(zip(single, batches)):
+        C, q, st, _ = L.leiden_update(h, dev_batch(b), ["df", "ds", "nd", "df"][k])
+        Cm, qm, stm, status = res[k]
+        assert status == L.OK
+        assert np.array_equal(to_np(Cm), to_np(C)), k
+        assert qm == q

@@ -1,0 +1,52 @@
+"""GPU: the batched (leiden_update_many) and served (leiden_server_*) forms.
+
+Synchronous mode makes every update deterministic, so a result computed in
+the mix must equal the same update run alone, element by element."""
+import numpy as np
+import pytest
+
+from paper_2405_11658_amd import inputs as gen
+from paper_2405_11658_amd import leiden as L
+
+from .gpu_common import dev_batch, say, sync_params, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _graphs():
+    return [gen.planted_partition(4096, 64, 0.1, 0.001, seed=1), gen.rmat(13, 8, seed=6),
+            gen.grid2d(64, 0.05, 0.02, seed=1), gen.planted_partition(1024, 16, 0.15, 0.004, seed=7),
+            gen.rmat(12, 16, seed=9)]
+
+
+@pytest.mark.parametrize("slots,budget", [(3, 0), (8, 0), (4, 1)])
+def test_server_results_equal_alone(slots, budget):
+    graphs = _graphs()
+    served, alone, streams = [], [], []
+    for k, g in enumerate(graphs):
+        a = L.leiden_create(g.off, g.idx, g.w, sync_params())
+        b = L.leiden_create(g.off, g.idx, g.w, sync_params())
+        L.leiden_static(a)
+        L.leiden_static(b)
+        served.append(a)
+        alone.append(b)
+        streams.append(gen.batch_stream(g, gen.batch_count(g.nnz, 2e-3), 3, seed=40 + k))
+    modes = ["df", "ds", "nd"]
+    sv = L.Server(slots=slots, memory_budget=budget)
+    say("server slots", slots, "budget", budget, "requests", 3 * len(graphs))
+    ids = {}
+    for r in range(3):                      # interleaved arrivals over the graphs
+        for k in range(len(graphs)):
+            ids[(k, r)] = sv.submit(served[k], dev_batch(streams[k][r]), modes[(k + r) % 3])
+    got = {key: sv.wait(rid) for key, rid in ids.items()}
+    sv.close()
+    lat = [v[4] for v in got.values()]
+    say("latency ms p50", round(float(np.percentile(lat, 50)), 2), "p99", round(float(np.percentile(lat, 99)), 2))
+    for k in range(len(graphs)):
+        for r in range(3):
+            C, q, st, _ = L.leiden_update(alone[k], dev_batch(streams[k][r]), modes[(k + r) % 3])
+            status, Cs, qs, sts, latency, service = got[(k, r)]
+            assert status == L.OK
+            assert np.array_equal(to_np(Cs), to_np(C)), (k, r)
+            assert qs == q
+            assert latency >= service > 0.0
