@@ -41,7 +41,7 @@ enum Slot {
   A_pcnt_item, A_pcnt, A_tcap, A_tstart, A_tkeys, A_tvals,
   // hubs
   H_keys, H_vals, H_v, H_cnt, H_ch, H_tab, H_sg, H_chub, H_shub, H_tk, H_tv, H_own, H_pg, H_pc, H_soff,
-  H_fill, H_bnd, L_act, W_keys, W_vals,
+  H_fill, H_bnd, L_act, W_keys, W_vals, W_list,
   // primitives
   T_tmp,
   // batch
@@ -115,8 +115,19 @@ struct Fail {
 
 constexpr size_t kPinBytes = 65536;
 constexpr int kMaxSlices = 256;
-constexpr int kDefaultAsyncWaves = 512;  // wavefronts of the asynchronous sweeps
+constexpr int kDefaultAsyncWaves = 2048;  // wavefronts of the asynchronous sweeps, at most
 constexpr int kMaxAsyncWaves = 65536;
+constexpr int64_t kVertsPerWave = 1024;  // level vertices with edges per sweeping wavefront, at least
+
+// Wavefronts of an asynchronous sweep over a level with n vertices that have
+// edges: at most `cap`, and few enough that the vertices in flight stay a
+// small fraction of the level (with much of a level in flight the sweep
+// degenerates into a synchronous update that oscillates and loses modularity).
+int level_waves(int cap, int64_t n) {
+  int64_t w = n / kVertsPerWave;
+  w = std::max<int64_t>(4, std::min<int64_t>(w, cap));
+  return (int)((w + 3) / 4 * 4);
+}
 
 struct KProf;
 
@@ -615,6 +626,17 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     const Layout B = level_layout(x, g, NS, region, counts, scnt, soff, sfill, vbs);
     const Hub hub = hub_tables(x, B.nhub, B.nhub > 0 ? max_degree(x, g) : 0);
     const HubHost hh = hub_plan(x, g, NS, B);
+    const int64_t alen = B.region[NS * kNB];  // vertices with edges
+    int32_t *alist = nullptr;
+    if (async && alen > 0) {
+      int32_t *flags = x.get<int32_t>(L_flags, nl + 1);
+      int32_t *pos = x.get<int32_t>(L_map, nl + 1);
+      alist = x.get<int32_t>(W_list, alen);
+      edge_flags(g.off, nl, flags, x.s);
+      scan_i32(x, flags, pos, nl);
+      edge_list(g.off, nl, pos, alist, x.s);
+      x.launched("edge list");
+    }
     if (pass > 0) fill_u8(rng, 1, nl, x.s);
     const double Tp = tau * M2 * M2 / 2.0;
 
@@ -631,6 +653,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     ma.act = hh.nhub > 0 ? act : nullptr;
     ma.hub_scanned = x.kp && x.kp->on ? &sc->hub_scanned : nullptr;
     ma.anext = &sc->anext; ma.akeys = akeys; ma.avals = avals;
+    ma.alist = alist; ma.alen = alen;
     int li = 0;
     int64_t moves_total = 0;
     tm.mark(CAT_OTHER);
@@ -669,7 +692,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
       }
       if (async) {
         x.zero(&sc->anext, 1);
-        move_async(ma, NW, x.s);
+        move_async(ma, level_waves(NW, alen), x.s);
       }
       if (gi) tiled_sum(gi, nl, tiles, &sc->gain, x.s);
       x.launched("move iteration");
@@ -710,6 +733,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     ra.refined = &sc->refined;
     ra.hub_keys = hub.keys; ra.hub_vals = hub.vals; ra.hub_cap = hub.cap; ra.hub_blocks = hub.blocks;
     ra.anext = &sc->anext; ra.akeys = akeys; ra.avals = avals;
+    ra.alist = alist; ra.alen = alen;
     x.zero(counts, NS * kNB);
     x.zero(&sc->refined, 1);
     refine_break(ra, x.s);
@@ -727,7 +751,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     }
     if (async) {
       x.zero(&sc->anext, 1);
-      refine_async(ra, NW, x.s);
+      refine_async(ra, level_waves(NW, alen), x.s);
     }
     x.launched("refine sweep");
     const int rounds = 1;

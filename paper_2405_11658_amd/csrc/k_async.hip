@@ -101,7 +101,8 @@ __device__ __forceinline__ void best_move(const WaveTable &t, double M2, int d, 
   group_argmax<kWave>(bg, bc);
 }
 
-// Next chunk of kAsyncChunk ids for the calling wavefront (uniform value).
+// First position of the next chunk of kAsyncChunk list positions for the
+// calling wavefront (uniform value); chunks are taken in ascending order.
 __device__ __forceinline__ int64_t grab(unsigned long long *next) {
   unsigned long long base = 0;
   if (lane() == 0) base = atomicAdd(next, (unsigned long long)kAsyncChunk);
@@ -119,18 +120,19 @@ __global__ __launch_bounds__(256) void k_move_async(MoveArgs a) {
   long long mv = 0;
   for (;;) {
     const int64_t base = grab(a.anext);
-    if (base >= a.n) break;
-    const int64_t v = base + lane();
+    if (base >= a.alen) break;
+    const int64_t p = base + lane();
+    int v = 0;
     bool cand = false;
-    if (v < a.n) {
-      const int64_t deg = a.off[v + 1] - a.off[v];
-      cand = deg > 0 && deg <= kHubDeg && a.rng[v];
+    if (p < a.alen) {
+      v = a.alist[p];
+      cand = a.off[v + 1] - a.off[v] <= kHubDeg && a.rng[v];
     }
     unsigned long long m = __ballot(cand);
     while (m) {
       const int k = __ffsll(m) - 1;
       m &= m - 1;
-      const int i = (int)(base + k);
+      const int i = __shfl(v, k);
       int u = 0;
       if (lane() == 0) u = ld_u8(&a.U[i]);
       if (!__shfl(u, 0)) continue;
@@ -182,18 +184,19 @@ __global__ __launch_bounds__(256) void k_refine_async(RefineArgs a) {
   double *gv = a.avals + gw * kHubDeg * 2;
   for (;;) {
     const int64_t base = grab(a.anext);
-    if (base >= a.n) break;
-    const int64_t v = base + lane();
+    if (base >= a.alen) break;
+    const int64_t p = base + lane();
+    int v = 0;
     bool cand = false;
-    if (v < a.n) {
-      const int64_t deg = a.off[v + 1] - a.off[v];
-      cand = deg > 0 && deg <= kHubDeg && a.dC[a.CB[v]];
+    if (p < a.alen) {
+      v = a.alist[p];
+      cand = a.off[v + 1] - a.off[v] <= kHubDeg && a.dC[a.CB[v]];
     }
     unsigned long long m = __ballot(cand);
     while (m) {
       const int k = __ffsll(m) - 1;
       m &= m - 1;
-      const int i = (int)(base + k);
+      const int i = __shfl(v, k);
       const int c = a.C[i];  // only this wavefront moves vertex i
       const double Ki = a.K[i];
       int iso = 0;
@@ -227,6 +230,21 @@ __global__ __launch_bounds__(256) void k_refine_async(RefineArgs a) {
 
 void refine_async(const RefineArgs &a, int waves, hipStream_t s) {
   if (a.n > 0) hipLaunchKernelGGL(k_refine_async, waves / kAsyncWaves, kAsyncWaves * kWave, 0, s, a);
+}
+
+__global__ void k_edge_flags(const int64_t *off, int64_t n, int32_t *flags) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    flags[i] = off[i + 1] > off[i];
+}
+void edge_flags(const int64_t *off, int64_t n, int32_t *flags, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_edge_flags, flat_grid(n), 256, 0, s, off, n, flags);
+}
+__global__ void k_edge_list(const int64_t *off, int64_t n, const int32_t *pos, int32_t *list) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (off[i + 1] > off[i]) list[pos[i]] = (int32_t)i;
+}
+void edge_list(const int64_t *off, int64_t n, const int32_t *pos, int32_t *list, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_edge_list, flat_grid(n), 256, 0, s, off, n, pos, list);
 }
 
 // Hubs of slice a.s enter the frontier: processed flag cleared, proposal

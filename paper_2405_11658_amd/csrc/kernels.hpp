@@ -137,7 +137,9 @@ struct MoveArgs {
   int64_t gbeg, gend;    // their table segments
   unsigned long long *hub_scanned;  // nullable: edges scanned by the hub gather
   // asynchronous sweep
-  unsigned long long *anext;  // device counter of the next vertex id chunk (zeroed per sweep)
+  unsigned long long *anext;  // device counter: next list position (zeroed per sweep)
+  const int32_t *alist;       // vertices with edges, ascending
+  int64_t alen;
   int *akeys;                 // per-wavefront global tables, 2*kHubDeg slots each
   double *avals;
 };
@@ -196,6 +198,8 @@ struct RefineArgs {
   int hub_blocks;
   // asynchronous sweep
   unsigned long long *anext;
+  const int32_t *alist;
+  int64_t alen;
   int *akeys;
   double *avals;
 };
@@ -209,6 +213,9 @@ constexpr int kAsyncChunk = 64;  // vertex ids taken per grab of the asynchronou
 // `waves` wavefronts (a multiple of 4) sweep the ids; vertices of degree
 // <= kHubDeg only.  Tables: 2*kHubDeg slots per wavefront in akeys/avals.
 void move_async(const MoveArgs &a, int waves, hipStream_t s);
+// list of vertices with edges in ascending order: flags then scan then scatter
+void edge_flags(const int64_t *off, int64_t n, int32_t *flags, hipStream_t s);
+void edge_list(const int64_t *off, int64_t n, const int32_t *pos, int32_t *list, hipStream_t s);
 void refine_async(const RefineArgs &a, int waves, hipStream_t s);
 // hub frontier of slice a.s (a.hbeg..a.hend of the hub plan) for the hub-only sliced phase
 void move_hub_frontier(const MoveArgs &a, hipStream_t s);

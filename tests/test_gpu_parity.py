@@ -304,4 +304,4 @@ def test_update_many_matches_single_updates():
         Cm, qm, stm, status = res[k]
         assert status == L.OK
         assert np.array_equal(to_np(Cm), to_np(C)), k
-        assert qm == q
+        assert abs(qm - q) <= 1e-12 * abs(q)  # modularity sums with atomics: last bits vary

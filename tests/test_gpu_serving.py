@@ -48,5 +48,5 @@ def test_server_results_equal_alone(slots, budget):
             status, Cs, qs, sts, latency, service = got[(k, r)]
             assert status == L.OK
             assert np.array_equal(to_np(Cs), to_np(C)), (k, r)
-            assert qs == q
+            assert abs(qs - q) <= 1e-12 * abs(q)  # modularity sums with atomics: last bits vary
             assert latency >= service > 0.0
