@@ -73,6 +73,26 @@ def ratio(a, b):
     return round(a / b, 4) if b else None
 
 
+def measured_traffic(kernel: str):
+    """Bytes per launch of `kernel` from the committed counter runs
+    (profiles/traffic.json: FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy),
+    or None when there is none for the kernels as they are now (the entry
+    records a hash of the kernel sources it was measured on)."""
+    import glob
+    import hashlib
+    path = os.path.join(HERE, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    entry = json.load(open(path)).get(kernel)
+    if not entry:
+        return None
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(HERE, "paper_2405_11658_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return entry["bytes_per_launch"] if entry.get("source_sha256") == h.hexdigest() else None
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -96,6 +116,8 @@ def main() -> int:
     ap.add_argument("--static-reps", type=int, default=3)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with a 1 GiB device-to-device copy (reference for counter runs)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -184,7 +206,7 @@ def main() -> int:
         avg_ms = pd["ms"] / pd["launches"]
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(PROF_KERNEL_NAMES[dom]),
                     "kernel": PROF_KERNEL_NAMES[dom], "avg_launch_us": round(avg_ms * 1e3, 2),
                     "launches_per_step": pd["launches"] / args.steps,
                     "algorithmic_bytes_per_launch": round(bytes_per_launch),
@@ -211,6 +233,14 @@ def main() -> int:
                "sample": (f"one {args.mode.upper()} update (batch 0, {B} updates) of the serial oracle on "
                           f"the same graph after its own static run ({t_static:.1f}s, untimed); "
                           f"update {t_upd:.2f}s; host CPU {cpu_model()}, os.cpu_count()={os.cpu_count()}")}
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("1 GiB calibration copy done")
 
     out = {
         "metric": METRIC,

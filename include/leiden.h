@@ -61,8 +61,9 @@ typedef enum { LEIDEN_ND = 1, LEIDEN_DS = 2, LEIDEN_DF = 3 } leiden_mode;
  * stated in the paper); agg_tol = 1.0 (aggregation never skipped, Sec. 4.6).
  * sync_mode = 0 (default): asynchronous local moving and refinement as in
  * Sec. 4.6 - up to async_waves wavefronts (0 = 2048; at most one per 1024
- * vertices with edges of the level) sweep the vertices in ascending id order
- * and apply each move at once; results depend on timing.
+ * vertices with edges on the first level, per 256 on aggregated levels) sweep
+ * the vertices in ascending id order and apply each move at once; results
+ * depend on timing.
  * Vertices of degree > 2048 are moved before each sweep, synchronously within
  * each of nslices hash-ordered slices.  sync_mode = 1: deterministic test
  * mode - every vertex is swept in nslices hash-ordered slices (default 16),
@@ -131,6 +132,10 @@ typedef struct {
   double prof_ms[LEIDEN_PROF_N];
   int64_t prof_entries[LEIDEN_PROF_N];
   int64_t prof_vertices[LEIDEN_PROF_N];
+  /* device time of each pass's local-moving, refinement and aggregation */
+  double pass_move_ms[LEIDEN_MAX_PASSES];
+  double pass_refine_ms[LEIDEN_MAX_PASSES];
+  double pass_agg_ms[LEIDEN_MAX_PASSES];
 } leiden_stats;
 
 /* Batch update (Sec. 3.5, Sec. 5.1.4).  Device arrays; each undirected edge

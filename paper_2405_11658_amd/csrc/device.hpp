@@ -67,6 +67,24 @@ __device__ __forceinline__ uint32_t mix64(uint64_t x) {
   return mix32((uint32_t)x ^ mix32((uint32_t)(x >> 32)));
 }
 
+// Argmax over a team of TEAM threads (TEAM a multiple of the wavefront or
+// smaller); the result is valid in the team's first thread.  With TEAM >
+// kWave every thread of the workgroup must call it.
+template <int TEAM, int BLOCK>
+__device__ __forceinline__ void team_argmax(double &g, int &c, double *rg, int *rc) {
+  group_argmax<kWave>(g, c);
+  if (TEAM > kWave) {
+    const int w = threadIdx.x / kWave;
+    if (lane() == 0) { rg[w] = g; rc[w] = c; }
+    __syncthreads();
+    if ((threadIdx.x % TEAM) == 0) {
+      for (int k = 1; k < TEAM / kWave; ++k)
+        if (better(rg[w + k], rc[w + k], g, c)) { g = rg[w + k]; c = rc[w + k]; }
+    }
+    __syncthreads();
+  }
+}
+
 // Open addressing with linear probing.  keys[] holds kEmpty for free slots,
 // vals[] starts at 0.  Capacity (mask+1) must exceed the number of distinct
 // keys inserted; the probe loop is bounded by the capacity in any case.

@@ -40,7 +40,7 @@ enum Slot {
   A_cnt, A_coff, A_mem, A_mdeg, A_mpos, A_mcrow, A_toff, A_hidx, A_hw, A_rowlen, A_pkey, A_pval,
   A_pcnt_item, A_pcnt, A_tcap, A_tstart, A_tkeys, A_tvals,
   // hubs
-  H_keys, H_vals, H_v, H_cnt, H_ch, H_tab, H_sg, H_chub, H_shub, H_tk, H_tv, H_own, H_pg, H_pc, H_soff,
+  H_v, H_cnt, H_ch, H_tab, H_sg, H_chub, H_shub, H_tk, H_tv, H_own, H_pg, H_pc, H_soff,
   H_fill, H_bnd, L_act, W_keys, W_vals, W_list,
   // primitives
   T_tmp,
@@ -55,8 +55,6 @@ enum Slot {
 };
 
 struct DevScal {
-  int32_t bucket_n[8];
-  unsigned long long maxdeg;
   double gain;
   unsigned long long moves;
   int32_t accepted;
@@ -117,14 +115,17 @@ constexpr size_t kPinBytes = 65536;
 constexpr int kMaxSlices = 256;
 constexpr int kDefaultAsyncWaves = 2048;  // wavefronts of the asynchronous sweeps, at most
 constexpr int kMaxAsyncWaves = 65536;
-constexpr int64_t kVertsPerWave = 1024;  // level vertices with edges per sweeping wavefront, at least
+constexpr int64_t kVertsPerWave = 1024;  // level-0 vertices with edges per sweeping wavefront, at least
+constexpr int64_t kVertsPerWaveUpper = 256;  // the same for the aggregated levels
 
 // Wavefronts of an asynchronous sweep over a level with n vertices that have
 // edges: at most `cap`, and few enough that the vertices in flight stay a
 // small fraction of the level (with much of a level in flight the sweep
 // degenerates into a synchronous update that oscillates and loses modularity).
-int level_waves(int cap, int64_t n) {
-  int64_t w = n / kVertsPerWave;
+// The first level decides most of the final modularity; the aggregated ones
+// tolerate four times as many vertices in flight.
+int level_waves(int cap, int64_t n, int pass) {
+  int64_t w = n / (pass == 0 ? kVertsPerWave : kVertsPerWaveUpper);
   w = std::max<int64_t>(4, std::min<int64_t>(w, cap));
   return (int)((w + 3) / 4 * 4);
 }
@@ -209,8 +210,14 @@ enum Cat { CAT_APPLY, CAT_MARK, CAT_MOVE, CAT_REFINE, CAT_AGG, CAT_OTHER, NCAT }
 struct Timer {
   Ctx &x;
   bool on;
-  std::vector<std::pair<hipEvent_t, int>> marks;
+  struct Mark {
+    hipEvent_t e;
+    int cat;
+    int pass;
+  };
+  std::vector<Mark> marks;
   size_t used = 0;
+  int pass = -1;  // pass the following intervals belong to (-1: none)
   Timer(Ctx &c, bool enabled) : x(c), on(enabled) {}
   void mark(int cat) {  // the interval ending here is attributed to `cat`
     if (!on) return;
@@ -221,19 +228,25 @@ struct Timer {
     }
     hipEvent_t e = x.w->events[used++];
     x.check(hipEventRecord(e, x.s), "hipEventRecord");
-    marks.push_back({e, cat});
+    marks.push_back({e, cat, pass});
   }
   void finish(leiden_stats *st) {
     if (!on || !st || marks.size() < 2) return;
-    x.check(hipEventSynchronize(marks.back().first), "hipEventSynchronize");
+    x.check(hipEventSynchronize(marks.back().e), "hipEventSynchronize");
     double t[NCAT] = {0};
     for (size_t k = 1; k < marks.size(); ++k) {
       float ms = 0.f;
-      x.check(hipEventElapsedTime(&ms, marks[k - 1].first, marks[k].first), "hipEventElapsedTime");
-      t[marks[k].second] += ms;
+      x.check(hipEventElapsedTime(&ms, marks[k - 1].e, marks[k].e), "hipEventElapsedTime");
+      t[marks[k].cat] += ms;
+      const int ps = marks[k].pass;
+      if (ps >= 0 && ps < LEIDEN_MAX_PASSES) {
+        if (marks[k].cat == CAT_MOVE) st->pass_move_ms[ps] += ms;
+        if (marks[k].cat == CAT_REFINE) st->pass_refine_ms[ps] += ms;
+        if (marks[k].cat == CAT_AGG) st->pass_agg_ms[ps] += ms;
+      }
     }
     float tot = 0.f;
-    x.check(hipEventElapsedTime(&tot, marks.front().first, marks.back().first), "hipEventElapsedTime");
+    x.check(hipEventElapsedTime(&tot, marks.front().e, marks.back().e), "hipEventElapsedTime");
     st->ms_total = tot;
     st->ms_apply = t[CAT_APPLY];
     st->ms_mark = t[CAT_MARK];
@@ -364,34 +377,6 @@ Layout level_layout(Ctx &x, const Level &g, int S, int32_t *region_dev, int32_t 
   return L;
 }
 
-int64_t max_degree(Ctx &x, const Level &g) {
-  DevScal *sc = x.scal();
-  x.zero(sc->bucket_n, 8);
-  x.zero(&sc->maxdeg, 1);
-  bucket_hist(g.off, g.n, sc->bucket_n, &sc->maxdeg, x.s);
-  x.launched("bucket_hist");
-  return (int64_t)x.read(&sc->maxdeg);
-}
-
-struct Hub {
-  int *keys = nullptr;
-  double *vals = nullptr;
-  int64_t cap = 0;
-  int blocks = 0;
-};
-
-Hub hub_tables(Ctx &x, int64_t nhub, int64_t maxdeg) {
-  Hub h;
-  if (nhub <= 0) return h;
-  h.cap = pow2_at_least(2 * maxdeg);
-  const int64_t budget = (int64_t)8 << 30;  // bytes for hub tables
-  int64_t blocks = std::min<int64_t>(nhub, 256);
-  blocks = std::max<int64_t>(1, std::min<int64_t>(blocks, budget / (h.cap * 12)));
-  h.blocks = (int)blocks;
-  h.keys = x.get<int>(H_keys, h.cap * blocks);
-  h.vals = x.get<double>(H_vals, h.cap * blocks);
-  return h;
-}
 
 // exclusive scans through the shared temp buffer
 void scan_i32(Ctx &x, const int32_t *in, int32_t *out, int64_t n) {
@@ -622,9 +607,9 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
   double tau = p.tau0;
   int pass = 0;
   for (pass = 0; pass < p.max_passes; ++pass) {
+    tm.pass = pass;
     const int64_t nl = g.n;
     const Layout B = level_layout(x, g, NS, region, counts, scnt, soff, sfill, vbs);
-    const Hub hub = hub_tables(x, B.nhub, B.nhub > 0 ? max_degree(x, g) : 0);
     const HubHost hh = hub_plan(x, g, NS, B);
     const int64_t alen = B.region[NS * kNB];  // vertices with edges
     int32_t *alist = nullptr;
@@ -648,7 +633,6 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     ma.prop = prop; ma.from = from; ma.gp = gp; ma.gi = gi;
     ma.lists = lists; ma.region = region; ma.counts = counts; ma.nsl = NS; ma.vbyslice = vbs;
     ma.gain = gi ? nullptr : &sc->gain; ma.moves = &sc->moves;
-    ma.hub_keys = hub.keys; ma.hub_vals = hub.vals; ma.hub_cap = hub.cap; ma.hub_blocks = hub.blocks;
     ma.hp = hh.p;
     ma.act = hh.nhub > 0 ? act : nullptr;
     ma.hub_scanned = x.kp && x.kp->on ? &sc->hub_scanned : nullptr;
@@ -692,7 +676,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
       }
       if (async) {
         x.zero(&sc->anext, 1);
-        move_async(ma, level_waves(NW, alen), x.s);
+        move_async(ma, level_waves(NW, alen, pass), x.s);
       }
       if (gi) tiled_sum(gi, nl, tiles, &sc->gain, x.s);
       x.launched("move iteration");
@@ -731,15 +715,19 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     ra.C = C; ra.CB = CB; ra.K = K; ra.Sig = S; ra.dC = dC; ra.S = Sz; ra.M2 = M2;
     ra.prop = prop; ra.gp = gp; ra.lists = lists; ra.region = region; ra.counts = counts; ra.nsl = NS;
     ra.refined = &sc->refined;
-    ra.hub_keys = hub.keys; ra.hub_vals = hub.vals; ra.hub_cap = hub.cap; ra.hub_blocks = hub.blocks;
     ra.anext = &sc->anext; ra.akeys = akeys; ra.avals = avals;
     ra.alist = alist; ra.alen = alen;
     x.zero(counts, NS * kNB);
     x.zero(&sc->refined, 1);
     refine_break(ra, x.s);
     x.launched("break");
+    ra.hp = hh.p;
+    ra.act = act;
     for (int sl = 0; sl < NS; ++sl) {
       ra.s = sl;
+      ra.hbeg = hh.hs[sl]; ra.hend = hh.hs[sl + 1];
+      ra.qbeg = hh.qs[sl]; ra.qend = hh.qs[sl + 1];
+      ra.gbeg = hh.gs[sl]; ra.gend = hh.gs[sl + 1];
       if (async) {
         // hubs of the slice (synchronous among themselves), the rest below
         if (B.region[sl * kNB + kNB] == B.region[sl * kNB + kNB - 1]) continue;
@@ -751,7 +739,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     }
     if (async) {
       x.zero(&sc->anext, 1);
-      refine_async(ra, level_waves(NW, alen), x.s);
+      refine_async(ra, level_waves(NW, alen, pass), x.s);
     }
     x.launched("refine sweep");
     const int rounds = 1;
@@ -791,6 +779,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     x.launched("pass reset");
     tau = tau / p.tol_drop;
   }
+  tm.pass = -1;
   if (st && pass >= p.max_passes) st->passes = p.max_passes;
   gather_map(Ctop, C, n, x.s);
   renumber_dense(x, Ctop, n, n);

@@ -176,16 +176,6 @@ __global__ __launch_bounds__(256) void k_propose_small(MoveArgs a, int b) {
   }
 }
 
-template <bool GLOBAL>
-__device__ __forceinline__ int ld_key(const int *p) {
-  if (GLOBAL) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return *p;
-}
-template <bool GLOBAL>
-__device__ __forceinline__ double ld_val(const double *p) {
-  if (GLOBAL) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return *p;
-}
 
 __device__ __forceinline__ uint32_t pow2_at_least(uint64_t x) {
   uint32_t c = 2;
@@ -194,29 +184,14 @@ __device__ __forceinline__ uint32_t pow2_at_least(uint64_t x) {
 }
 
 // Team argmax over TEAM threads (TEAM = 64 or a multiple); result in t == 0.
-template <int TEAM, int BLOCK>
-__device__ __forceinline__ void team_argmax(double &g, int &c, double *rg, int *rc) {
-  group_argmax<kWave>(g, c);
-  if (TEAM > kWave) {
-    const int w = threadIdx.x / kWave;
-    if (lane() == 0) { rg[w] = g; rc[w] = c; }
-    __syncthreads();
-    if ((threadIdx.x % TEAM) == 0) {
-      for (int k = 1; k < TEAM / kWave; ++k)
-        if (better(rg[w + k], rc[w + k], g, c)) { g = rg[w + k]; c = rc[w + k]; }
-    }
-    __syncthreads();
-  }
-}
 
-// ---- propose: a team (wavefront or workgroup) per vertex, hash table in LDS
-// (T slots per team) or in a global-memory region per workgroup.
-template <int TEAM, int T, int BLOCK, bool GLOBAL>
+// ---- propose: a team (wavefront or workgroup) per vertex, hash table of T
+// slots per team in LDS.
+template <int TEAM, int T, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_propose_team(MoveArgs a, int b) {
   constexpr int NT = BLOCK / TEAM;
-  constexpr int TL = GLOBAL ? 1 : T;
-  __shared__ int skeys[NT * TL];
-  __shared__ double svals[NT * TL];
+  __shared__ int skeys[NT * T];
+  __shared__ double svals[NT * T];
   __shared__ double sb[NT];
   __shared__ double rg[BLOCK / kWave];
   __shared__ int rc[BLOCK / kWave];
@@ -231,20 +206,9 @@ __global__ __launch_bounds__(BLOCK) void k_propose_team(MoveArgs a, int b) {
     int64_t e0 = 0, e1 = 0;
     int d = 0;
     if (valid) { e0 = a.off[i]; e1 = a.off[i + 1]; d = a.C[i]; }
-    int *keys;
-    double *vals;
-    uint32_t mask;
-    if (GLOBAL) {
-      keys = a.hub_keys + (int64_t)blockIdx.x * a.hub_cap;
-      vals = a.hub_vals + (int64_t)blockIdx.x * a.hub_cap;
-      uint32_t cap = pow2_at_least(2 * (uint64_t)(e1 - e0));
-      if (cap > (uint32_t)a.hub_cap) cap = (uint32_t)a.hub_cap;
-      mask = cap - 1;
-    } else {
-      keys = skeys + team * TL;
-      vals = svals + team * TL;
-      mask = T - 1;
-    }
+    int *keys = skeys + team * T;
+    double *vals = svals + team * T;
+    const uint32_t mask = T - 1;
     for (uint32_t s = t; s <= mask; s += TEAM) { keys[s] = kEmpty; vals[s] = 0.0; }
     if (t == 0) sb[team] = 0.0;
     __syncthreads();
@@ -257,7 +221,7 @@ __global__ __launch_bounds__(BLOCK) void k_propose_team(MoveArgs a, int b) {
     __syncthreads();
     if (valid)
       for (uint32_t s = t; s <= mask; s += TEAM)
-        if (ld_key<GLOBAL>(&keys[s]) == d) sb[team] = ld_val<GLOBAL>(&vals[s]);
+        if (keys[s] == d) sb[team] = vals[s];
     __syncthreads();
     double bg = 0.0;
     int bc = kNoComm;
@@ -266,9 +230,9 @@ __global__ __launch_bounds__(BLOCK) void k_propose_team(MoveArgs a, int b) {
       const double Ki = a.K[i];
       const double Sd = a.Sig[d];
       for (uint32_t s = t; s <= mask; s += TEAM) {
-        const int c = ld_key<GLOBAL>(&keys[s]);
+        const int c = keys[s];
         if (c == kEmpty || c == d) continue;
-        const double x = move_score(a.M2, ld_val<GLOBAL>(&vals[s]), bown, Ki, a.Sig[c], Sd);
+        const double x = move_score(a.M2, vals[s], bown, Ki, a.Sig[c], Sd);
         if (x > 0.0 && better(x, c, bg, bc)) { bg = x; bc = c; }
       }
     }
@@ -562,8 +526,8 @@ void move_propose_bucket(const MoveArgs &a, const int64_t *region_h, int b, hipS
       case 0: hipLaunchKernelGGL(k_propose_small<4>, grid_for(cap, 64), 256, 0, s, a, b); break;
       case 1: hipLaunchKernelGGL(k_propose_small<8>, grid_for(cap, 32), 256, 0, s, a, b); break;
       case 2: hipLaunchKernelGGL(k_propose_small<32>, grid_for(cap, 8), 256, 0, s, a, b); break;
-      case 3: hipLaunchKernelGGL((k_propose_team<64, 512, 256, false>), grid_for(cap, 4), 256, 0, s, a, b); break;
-      case 4: hipLaunchKernelGGL((k_propose_team<256, 4096, 256, false>), grid_for(cap, 1, 2048), 256, 0, s, a, b); break;
+      case 3: hipLaunchKernelGGL((k_propose_team<64, 512, 256>), grid_for(cap, 4), 256, 0, s, a, b); break;
+      case 4: hipLaunchKernelGGL((k_propose_team<256, 4096, 256>), grid_for(cap, 1, 2048), 256, 0, s, a, b); break;
       case 5:
         move_hub_gather(a, s);
         move_hub_score(a, s);

@@ -154,23 +154,12 @@ __global__ __launch_bounds__(256) void k_rprop_small(RefineArgs a, int b) {
   }
 }
 
-template <bool GLOBAL>
-__device__ __forceinline__ int rld_key(const int *p) {
-  if (GLOBAL) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return *p;
-}
-template <bool GLOBAL>
-__device__ __forceinline__ double rld_val(const double *p) {
-  if (GLOBAL) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return *p;
-}
 
-template <int TEAM, int T, int BLOCK, bool GLOBAL>
+template <int TEAM, int T, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_rprop_team(RefineArgs a, int b) {
   constexpr int NT = BLOCK / TEAM;
-  constexpr int TL = GLOBAL ? 1 : T;
-  __shared__ int skeys[NT * TL];
-  __shared__ double svals[NT * TL];
+  __shared__ int skeys[NT * T];
+  __shared__ double svals[NT * T];
   __shared__ double sb[NT];
   __shared__ double rg[BLOCK / kWave];
   __shared__ int rc[BLOCK / kWave];
@@ -186,21 +175,9 @@ __global__ __launch_bounds__(BLOCK) void k_rprop_team(RefineArgs a, int b) {
     int64_t e0 = 0, e1 = 0;
     int cbi = 0;
     if (active) { e0 = a.off[i]; e1 = a.off[i + 1]; cbi = a.CB[i]; }
-    int *keys;
-    double *vals;
-    uint32_t mask;
-    if (GLOBAL) {
-      keys = a.hub_keys + (int64_t)blockIdx.x * a.hub_cap;
-      vals = a.hub_vals + (int64_t)blockIdx.x * a.hub_cap;
-      uint32_t cap = 2;
-      while (cap < 2 * (uint64_t)(e1 - e0)) cap <<= 1;
-      if (cap > (uint32_t)a.hub_cap) cap = (uint32_t)a.hub_cap;
-      mask = cap - 1;
-    } else {
-      keys = skeys + team * TL;
-      vals = svals + team * TL;
-      mask = T - 1;
-    }
+    int *keys = skeys + team * T;
+    double *vals = svals + team * T;
+    const uint32_t mask = T - 1;
     for (uint32_t s = t; s <= mask; s += TEAM) { keys[s] = kEmpty; vals[s] = 0.0; }
     if (t == 0) sb[team] = 0.0;
     __syncthreads();
@@ -213,7 +190,7 @@ __global__ __launch_bounds__(BLOCK) void k_rprop_team(RefineArgs a, int b) {
     __syncthreads();
     if (active)
       for (uint32_t s = t; s <= mask; s += TEAM)
-        if (rld_key<GLOBAL>(&keys[s]) == i) sb[team] = rld_val<GLOBAL>(&vals[s]);
+        if (keys[s] == i) sb[team] = vals[s];
     __syncthreads();
     double bg = 0.0;
     int bc = kNoComm;
@@ -222,9 +199,9 @@ __global__ __launch_bounds__(BLOCK) void k_rprop_team(RefineArgs a, int b) {
       const double Ki = a.K[i];
       const double Sd = a.Sig[i];
       for (uint32_t s = t; s <= mask; s += TEAM) {
-        const int c = rld_key<GLOBAL>(&keys[s]);
+        const int c = keys[s];
         if (c == kEmpty || c == i) continue;
-        const double x = move_score(a.M2, rld_val<GLOBAL>(&vals[s]), bown, Ki, a.Sig[c], Sd);
+        const double x = move_score(a.M2, vals[s], bown, Ki, a.Sig[c], Sd);
         if (x > 0.0 && better(x, c, bg, bc)) { bg = x; bc = c; }
       }
     }
@@ -252,6 +229,99 @@ static int rgrid(int64_t cap, int per_block, int maxb = 4096) {
   return (int)(g < maxb ? g : maxb);
 }
 
+// ---- refine propose for hubs: several workgroups per candidate -------------------
+// Same decomposition as the local-moving hub path (edge chunks merged in LDS,
+// then a global table per hub; segments scored and cleared; a final
+// wavefront reduces).  Candidates: hubs of the slice in a changed bound that
+// are isolated at the start of the slice; only neighbours in the same bound
+// count; the own community is the vertex itself.
+__global__ void k_rhub_frontier(RefineArgs a) {
+  for (int64_t h = a.hbeg + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < a.hend;
+       h += (int64_t)gridDim.x * blockDim.x) {
+    const int i = a.hp.hubv[h];
+    a.act[i] = a.dC[a.CB[i]] && a.C[i] == i && a.S[i] == 1;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_rhub_gather(RefineArgs a) {
+  constexpr int T = 2 * kHubEC;
+  __shared__ int keys[T];
+  __shared__ double vals[T];
+  const int64_t q = a.qbeg + blockIdx.x;
+  const int h = a.hp.chub[q];
+  const int i = a.hp.hubv[h];
+  if (!a.act[i]) return;
+  const int64_t e0 = a.off[i] + (q - a.hp.hch[h]) * kHubEC;
+  const int64_t e1 = min(e0 + (int64_t)kHubEC, a.off[i + 1]);
+  const int cbi = a.CB[i];
+  for (int s = threadIdx.x; s < T; s += blockDim.x) { keys[s] = kEmpty; vals[s] = 0.0; }
+  __syncthreads();
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const int j = a.idx[e];
+    if (j != i && a.CB[j] == cbi) table_add(keys, vals, T - 1, a.C[j], (double)a.w[e]);
+  }
+  __syncthreads();
+  const int64_t t0 = a.hp.htab[h];
+  const uint32_t mask = (uint32_t)(a.hp.htab[h + 1] - t0 - 1);
+  for (int s = threadIdx.x; s < T; s += blockDim.x) {
+    const int c = keys[s];
+    if (c == kEmpty) continue;
+    if (c == i) unsafeAtomicAdd(&a.hp.own[h], vals[s]);
+    else table_add(a.hp.keys + t0, a.hp.vals + t0, mask, c, vals[s]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_rhub_score(RefineArgs a) {
+  __shared__ double rg[256 / kWave];
+  __shared__ int rc[256 / kWave];
+  const int64_t q = a.gbeg + blockIdx.x;
+  const int h = a.hp.shub[q];
+  const int i = a.hp.hubv[h];
+  if (!a.act[i]) return;
+  const int64_t s0 = a.hp.htab[h] + (q - a.hp.hsg[h]) * kHubSeg;
+  const double Ki = a.K[i], Sd = a.Sig[i], bown = a.hp.own[h];
+  double bg = 0.0;
+  int bc = kNoComm;
+  for (int64_t s = s0 + threadIdx.x; s < s0 + kHubSeg; s += blockDim.x) {
+    const int c = a.hp.keys[s];
+    if (c == kEmpty) continue;
+    const double v = a.hp.vals[s];
+    a.hp.keys[s] = kEmpty;
+    a.hp.vals[s] = 0.0;
+    const double x = move_score(a.M2, v, bown, Ki, a.Sig[c], Sd);
+    if (x > 0.0 && better(x, c, bg, bc)) { bg = x; bc = c; }
+  }
+  team_argmax<256, 256>(bg, bc, rg, rc);
+  if (threadIdx.x == 0) { a.hp.pg[q] = bg; a.hp.pc[q] = bc; }
+}
+
+__global__ __launch_bounds__(256) void k_rhub_final(RefineArgs a) {
+  const int64_t h = a.hbeg + ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  if (h >= a.hend) return;  // uniform per wavefront
+  const int i = a.hp.hubv[h];
+  if (!a.act[i]) return;
+  double bg = 0.0;
+  int bc = kNoComm;
+  for (int64_t q = a.hp.hsg[h] + lane(); q < a.hp.hsg[h + 1]; q += kWave)
+    if (better(a.hp.pg[q], a.hp.pc[q], bg, bc)) { bg = a.hp.pg[q]; bc = a.hp.pc[q]; }
+  group_argmax<kWave>(bg, bc);
+  if (lane() == 0) {
+    a.prop[i] = (bc == kNoComm) ? -1 : bc;
+    a.gp[i] = bg;
+    a.hp.own[h] = 0.0;
+  }
+}
+
+static void refine_hubs(const RefineArgs &a, hipStream_t s) {
+  if (a.hend <= a.hbeg) return;
+  hipLaunchKernelGGL(k_rhub_frontier, flat_grid(a.hend - a.hbeg), 256, 0, s, a);
+  if (a.qend > a.qbeg) {
+    hipLaunchKernelGGL(k_rhub_gather, (int)(a.qend - a.qbeg), 256, 0, s, a);
+    hipLaunchKernelGGL(k_rhub_score, (int)(a.gend - a.gbeg), 256, 0, s, a);
+  }
+  hipLaunchKernelGGL(k_rhub_final, (int)ceil_div(a.hend - a.hbeg, (int64_t)4), 256, 0, s, a);
+}
+
 void refine_propose(const RefineArgs &a, const int64_t *region_h, hipStream_t s) {
   for (int b = 0; b < kNB; ++b) refine_propose_bucket(a, region_h, b, s);
 }
@@ -263,9 +333,9 @@ void refine_propose_bucket(const RefineArgs &a, const int64_t *region_h, int b, 
     case 0: hipLaunchKernelGGL(k_rprop_small<4>, rgrid(cap, 64), 256, 0, s, a, b); break;
     case 1: hipLaunchKernelGGL(k_rprop_small<8>, rgrid(cap, 32), 256, 0, s, a, b); break;
     case 2: hipLaunchKernelGGL(k_rprop_small<32>, rgrid(cap, 8), 256, 0, s, a, b); break;
-    case 3: hipLaunchKernelGGL((k_rprop_team<64, 512, 256, false>), rgrid(cap, 4), 256, 0, s, a, b); break;
-    case 4: hipLaunchKernelGGL((k_rprop_team<256, 4096, 256, false>), rgrid(cap, 1, 2048), 256, 0, s, a, b); break;
-    case 5: hipLaunchKernelGGL((k_rprop_team<512, 1, 512, true>), rgrid(cap, 1, a.hub_blocks), 512, 0, s, a, b); break;
+    case 3: hipLaunchKernelGGL((k_rprop_team<64, 512, 256>), rgrid(cap, 4), 256, 0, s, a, b); break;
+    case 4: hipLaunchKernelGGL((k_rprop_team<256, 4096, 256>), rgrid(cap, 1, 2048), 256, 0, s, a, b); break;
+    case 5: refine_hubs(a, s); break;
   }
 }
 

@@ -108,29 +108,7 @@ void mark_used(const int32_t *C, int64_t n, int32_t *flags, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_mark_used, flat_grid(n), 256, 0, s, C, n, flags);
 }
 
-__device__ __forceinline__ int bucket_of(int64_t deg) {
-  return deg <= 4 ? 0 : deg <= 8 ? 1 : deg <= 32 ? 2 : deg <= 256 ? 3 : deg <= 2048 ? 4 : 5;
-}
 
-__global__ __launch_bounds__(256) void k_bucket_hist(const int64_t *off, int64_t n, int32_t *counts,
-                                                     unsigned long long *maxdeg) {
-  __shared__ int cnt[8];
-  if (threadIdx.x < 8) cnt[threadIdx.x] = 0;
-  __syncthreads();
-  unsigned long long mx = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t deg = off[i + 1] - off[i];
-    if (deg > 0) atomicAdd(&cnt[bucket_of(deg)], 1);
-    mx = max(mx, (unsigned long long)deg);
-  }
-  for (int o = 32; o > 0; o >>= 1) mx = max(mx, (unsigned long long)__shfl_xor(mx, o));
-  if (lane() == 0 && mx > 0) atomicMax(maxdeg, mx);
-  __syncthreads();
-  if (threadIdx.x < 8 && cnt[threadIdx.x]) atomicAdd(&counts[threadIdx.x], cnt[threadIdx.x]);
-}
-void bucket_hist(const int64_t *off, int64_t n, int32_t *counts, unsigned long long *maxdeg, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_bucket_hist, flat_grid(n, 256, 1024), 256, 0, s, off, n, counts, maxdeg);
-}
 
 __global__ void k_check_labels(const int32_t *C, int64_t n, int64_t bound, int32_t *err) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)

@@ -49,9 +49,6 @@ void scatter_add(const double *v, const int32_t *C, int64_t n, double *out, hipS
 void gather_map(int32_t *C, const int32_t *map, int64_t n, hipStream_t s);
 // flags[C[i]] = 1
 void mark_used(const int32_t *C, int64_t n, int32_t *flags, hipStream_t s);
-// Per-bucket vertex counts (deg > 0 only) and maximum degree; counts/maxdeg zeroed by caller.
-void bucket_hist(const int64_t *off, int64_t n, int32_t *counts, unsigned long long *maxdeg,
-                 hipStream_t s);
 // C[i] < bound for all i?  sets *err |= flag otherwise.
 void check_labels(const int32_t *C, int64_t n, int64_t bound, int32_t *err, hipStream_t s);
 // Rows strictly ascending (sorted, no duplicate entry), ids in range, weights
@@ -125,10 +122,6 @@ struct MoveArgs {
   int64_t vbeg, vend;    // range of the current slice in vbyslice
   double *gain;          // device scalar (atomic sums), nullable when gi is used
   unsigned long long *moves;  // device scalar
-  int *hub_keys;         // global tables for the largest bucket
-  double *hub_vals;
-  int64_t hub_cap;       // slots per block (power of two)
-  int hub_blocks;
   // multi-workgroup hub path
   HubPlan hp;
   uint8_t *act;          // hub is in the frontier of its slice (written by the frontier)
@@ -192,16 +185,16 @@ struct RefineArgs {
   int nsl;
   int s;
   unsigned long long *refined;  // device scalar: vertices in changed bounds
-  int *hub_keys;
-  double *hub_vals;
-  int64_t hub_cap;
-  int hub_blocks;
   // asynchronous sweep
   unsigned long long *anext;
   const int32_t *alist;
   int64_t alen;
   int *akeys;
   double *avals;
+  // multi-workgroup path for hub candidates (as in MoveArgs)
+  HubPlan hp;
+  uint8_t *act;
+  int64_t hbeg, hend, qbeg, qend, gbeg, gend;
 };
 void refine_break(const RefineArgs &a, hipStream_t s);
 void refine_propose_bucket(const RefineArgs &a, const int64_t *region_h, int b, hipStream_t s);

@@ -56,7 +56,9 @@ class leiden_stats(ct.Structure):
                 ("ms_move", ct.c_double), ("ms_refine", ct.c_double), ("ms_aggregate", ct.c_double),
                 ("ms_other", ct.c_double),
                 ("prof_launches", ct.c_int64 * PROF_N), ("prof_ms", ct.c_double * PROF_N),
-                ("prof_entries", ct.c_int64 * PROF_N), ("prof_vertices", ct.c_int64 * PROF_N)]
+                ("prof_entries", ct.c_int64 * PROF_N), ("prof_vertices", ct.c_int64 * PROF_N),
+                ("pass_move_ms", ct.c_double * MAX_PASSES), ("pass_refine_ms", ct.c_double * MAX_PASSES),
+                ("pass_agg_ms", ct.c_double * MAX_PASSES)]
 
     def to_dict(self) -> dict:
         p = self.passes
@@ -66,7 +68,9 @@ class leiden_stats(ct.Structure):
              "level_entries": list(self.level_entries[:p]),
              "communities": list(self.communities[:p]),
              "refined_vertices": list(self.refined_vertices[:p]),
-             "affected": self.affected, "changed": self.changed, "moves_pass0": self.moves_pass0}
+             "affected": self.affected, "changed": self.changed, "moves_pass0": self.moves_pass0,
+             "pass_move_ms": list(self.pass_move_ms[:p]), "pass_refine_ms": list(self.pass_refine_ms[:p]),
+             "pass_agg_ms": list(self.pass_agg_ms[:p])}
         for k in ("ms_total", "ms_apply", "ms_mark", "ms_move", "ms_refine", "ms_aggregate", "ms_other"):
             d[k] = getattr(self, k)
         d["prof"] = {name: {"launches": self.prof_launches[k], "ms": self.prof_ms[k],
