@@ -117,6 +117,27 @@ __device__ __forceinline__ void table_add64(unsigned long long *keys, double *va
   }
 }
 
+// Wave-cooperative insertion of 64-bit keys: every lane of the wavefront
+// calls it (inactive lanes with active = false).  The keys of the first two
+// distinct leaders are summed across the wavefront and inserted once each;
+// the remaining lanes insert on their own.  Hot keys then cost one atomic
+// per wavefront instead of one per lane.
+__device__ __forceinline__ void table_add64_wave(unsigned long long *keys, double *vals, uint32_t mask,
+                                                 unsigned long long key, double w, bool active) {
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const unsigned long long m = __ballot(active);
+    if (!m) return;
+    const int leader = __ffsll(m) - 1;
+    const unsigned long long k = __shfl(key, leader);
+    const bool mine = active && key == k;
+    const double sum = group_sum<kWave>(mine ? w : 0.0);
+    if (lane() == leader) table_add64(keys, vals, mask, k, sum);
+    if (mine) active = false;
+  }
+  if (active) table_add64(keys, vals, mask, key, w);
+}
+
 __device__ __forceinline__ double table_get(const int *keys, const double *vals, uint32_t mask,
                                             int key) {
   uint32_t h = mix32((uint32_t)key) & mask;

@@ -126,8 +126,8 @@ constexpr int64_t kVertsPerWaveUpper = 256;  // the same for the aggregated leve
 // tolerate four times as many vertices in flight.
 int level_waves(int cap, int64_t n, int pass) {
   int64_t w = n / (pass == 0 ? kVertsPerWave : kVertsPerWaveUpper);
-  w = std::max<int64_t>(4, std::min<int64_t>(w, cap));
-  return (int)((w + 3) / 4 * 4);
+  w = std::max<int64_t>(1, std::min<int64_t>(w, cap));
+  return (int)(w < 4 ? w : (w + 3) / 4 * 4);
 }
 
 struct KProf;

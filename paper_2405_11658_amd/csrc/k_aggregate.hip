@@ -85,14 +85,20 @@ __global__ __launch_bounds__(256) void k_agg_items(AggArgs a, int64_t M) {
   for (int s = threadIdx.x; s < kAggT; s += blockDim.x) { tkeys[s] = ~0ull; tvals[s] = 0.0; }
   if (threadIdx.x == 0) np = 0;
   __syncthreads();
-  for (int t = threadIdx.x; t < len; t += blockDim.x) {
-    const int k = slotof[t];
-    const int u = a.mem[k];
-    const int64_t e = a.off[u] + (base + t - a.mpos[k]);
-    const int v = a.idx[e];
-    const double x = (double)a.w[e];
-    const unsigned long long key = ((unsigned long long)(uint32_t)a.C[u] << 32) | (uint32_t)a.C[v];
-    table_add64(tkeys, tvals, kAggT - 1, key, x);
+  for (int t0 = 0; t0 < len; t0 += blockDim.x) {
+    const int t = t0 + threadIdx.x;
+    const bool on = t < len;
+    unsigned long long key = 0;
+    double x = 0.0;
+    if (on) {
+      const int k = slotof[t];
+      const int u = a.mem[k];
+      const int64_t e = a.off[u] + (base + t - a.mpos[k]);
+      const int v = a.idx[e];
+      x = (double)a.w[e];
+      key = ((unsigned long long)(uint32_t)a.C[u] << 32) | (uint32_t)a.C[v];
+    }
+    table_add64_wave(tkeys, tvals, kAggT - 1, key, x, on);
   }
   __syncthreads();
   for (int s0 = 0; s0 < kAggT; s0 += blockDim.x) {

@@ -121,25 +121,33 @@ __global__ __launch_bounds__(256) void k_move_async(MoveArgs a) {
   for (;;) {
     const int64_t base = grab(a.anext);
     if (base >= a.alen) break;
+    // each lane fetches the state of one vertex of the chunk; unprocessed
+    // candidates are claimed (marked processed) at once and then handled one
+    // after another by the whole wavefront
     const int64_t p = base + lane();
-    int v = 0;
+    int v = 0, dv = 0;
+    int64_t e0v = 0, e1v = 0;
+    double kv = 0.0;
     bool cand = false;
     if (p < a.alen) {
       v = a.alist[p];
-      cand = a.off[v + 1] - a.off[v] <= kHubDeg && a.rng[v];
+      e0v = a.off[v];
+      e1v = a.off[v + 1];
+      cand = e1v - e0v <= kHubDeg && a.rng[v] && ld_u8(&a.U[v]);
+      if (cand) {
+        st_u8(&a.U[v], 0);
+        dv = a.C[v];  // only this wavefront writes C[v] during the sweep
+        kv = a.K[v];
+      }
     }
     unsigned long long m = __ballot(cand);
     while (m) {
       const int k = __ffsll(m) - 1;
       m &= m - 1;
       const int i = __shfl(v, k);
-      int u = 0;
-      if (lane() == 0) u = ld_u8(&a.U[i]);
-      if (!__shfl(u, 0)) continue;
-      if (lane() == 0) st_u8(&a.U[i], 0);
-      const int64_t e0 = a.off[i], e1 = a.off[i + 1];
-      const int d = a.C[i];  // only this wavefront writes C[i] during the sweep
-      const double Ki = a.K[i];
+      const int64_t e0 = __shfl(e0v, k), e1 = __shfl(e1v, k);
+      const int d = __shfl(dv, k);
+      const double Ki = __shfl(kv, k);
       WaveTable t = wave_table(skeys[wv], svals[wv], gk, gv, e1 - e0);
       for (int64_t e = e0 + lane(); e < e1; e += kWave) {
         const int j = a.idx[e];
@@ -171,8 +179,11 @@ __global__ __launch_bounds__(256) void k_move_async(MoveArgs a) {
   }
 }
 
+// `waves` below kAsyncWaves: one workgroup of that many wavefronts
 void move_async(const MoveArgs &a, int waves, hipStream_t s) {
-  if (a.n > 0) hipLaunchKernelGGL(k_move_async, waves / kAsyncWaves, kAsyncWaves * kWave, 0, s, a);
+  if (a.n <= 0 || waves <= 0) return;
+  const int per = waves < kAsyncWaves ? waves : kAsyncWaves;
+  hipLaunchKernelGGL(k_move_async, waves / per, per * kWave, 0, s, a);
 }
 
 __global__ __launch_bounds__(256) void k_refine_async(RefineArgs a) {
@@ -185,25 +196,35 @@ __global__ __launch_bounds__(256) void k_refine_async(RefineArgs a) {
   for (;;) {
     const int64_t base = grab(a.anext);
     if (base >= a.alen) break;
+    // each lane fetches one vertex of the chunk: isolated vertices of a
+    // changed bound are candidates (their isolation is confirmed again by the
+    // compare-and-swap when they move)
     const int64_t p = base + lane();
-    int v = 0;
+    int v = 0, cv = 0, cbv = 0;
+    int64_t e0v = 0, e1v = 0;
+    double kv = 0.0;
     bool cand = false;
     if (p < a.alen) {
       v = a.alist[p];
-      cand = a.off[v + 1] - a.off[v] <= kHubDeg && a.dC[a.CB[v]];
+      e0v = a.off[v];
+      e1v = a.off[v + 1];
+      cbv = a.CB[v];
+      cand = e1v - e0v <= kHubDeg && a.dC[cbv];
+      if (cand) {
+        cv = a.C[v];  // only this wavefront moves vertex v
+        kv = a.K[v];
+        cand = ld_dbl(&a.Sig[cv]) == kv;
+      }
     }
     unsigned long long m = __ballot(cand);
     while (m) {
       const int k = __ffsll(m) - 1;
       m &= m - 1;
       const int i = __shfl(v, k);
-      const int c = a.C[i];  // only this wavefront moves vertex i
-      const double Ki = a.K[i];
-      int iso = 0;
-      if (lane() == 0) iso = ld_dbl(&a.Sig[c]) == Ki;
-      if (!__shfl(iso, 0)) continue;  // not isolated
-      const int cb = a.CB[i];
-      const int64_t e0 = a.off[i], e1 = a.off[i + 1];
+      const int c = __shfl(cv, k);
+      const double Ki = __shfl(kv, k);
+      const int cb = __shfl(cbv, k);
+      const int64_t e0 = __shfl(e0v, k), e1 = __shfl(e1v, k);
       WaveTable t = wave_table(skeys[wv], svals[wv], gk, gv, e1 - e0);
       for (int64_t e = e0 + lane(); e < e1; e += kWave) {
         const int j = a.idx[e];
@@ -229,7 +250,9 @@ __global__ __launch_bounds__(256) void k_refine_async(RefineArgs a) {
 }
 
 void refine_async(const RefineArgs &a, int waves, hipStream_t s) {
-  if (a.n > 0) hipLaunchKernelGGL(k_refine_async, waves / kAsyncWaves, kAsyncWaves * kWave, 0, s, a);
+  if (a.n <= 0 || waves <= 0) return;
+  const int per = waves < kAsyncWaves ? waves : kAsyncWaves;
+  hipLaunchKernelGGL(k_refine_async, waves / per, per * kWave, 0, s, a);
 }
 
 __global__ void k_edge_flags(const int64_t *off, int64_t n, int32_t *flags) {
