@@ -8,4 +8,4 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (HIP) device")
-    config.addinivalue_line("markers", "slow: larger CPU-only case")
+    config.addinivalue_line("markers", "slow: larger case (the full benchmark size on the GPU)")

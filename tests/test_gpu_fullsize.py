@@ -1,0 +1,78 @@
+"""GPU parity at the benchmark's full size: RMAT scale 22, edge factor 16
+(4,194,304 vertices, ~128M directed entries), in the configuration bench.py
+times (default asynchronous mode, DF updates of 1e-4 |E|).
+
+Everything the oracle can compute at this size in seconds is compared in
+full: modularity of the returned membership (relative 1e-9), the stored K,
+Sigma and 2m (exact, unit weights), the aggregated super-vertex CSR for the
+returned membership (exact after sorting each row), the graph after a batch
+(exact) and the DF and DS affected / in-range / changed flags (exact)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_11658_amd import inputs as gen
+from paper_2405_11658_amd import leiden as L
+
+from .gpu_common import dev_batch, ob, og, say, to_np
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def _sorted_rows(off, idx, w):
+    """Rows sorted by neighbour id (row order kept): (idx, w) arrays."""
+    off, idx, w = np.asarray(off), np.asarray(idx), np.asarray(w)
+    rows = np.repeat(np.arange(len(off) - 1, dtype=np.int64), np.diff(off))
+    order = np.argsort((rows << 31) | idx.astype(np.int64), kind="stable")
+    return idx[order], w[order]
+
+
+def _state_checks(h, g, C, q):
+    C = to_np(C)
+    qo = oracle.modularity(og(g), C)
+    assert abs(q - qo) <= 1e-9 * abs(qo), (q, qo)
+    _, K, S, m2 = L.leiden_get_state(h)
+    K, S = to_np(K), to_np(S)
+    rows = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.off))
+    Kr = np.bincount(rows, weights=g.w.astype(np.float64), minlength=g.n)
+    assert np.array_equal(K, Kr)
+    Sr = np.bincount(C, weights=Kr, minlength=g.n)
+    assert np.array_equal(S, Sr)
+    assert m2 == float(Kr.sum())
+    return C
+
+
+def test_rmat22_full_size():
+    g = gen.rmat(22, 16, seed=1)
+    say("rmat22 n", g.n, "entries", g.nnz)
+    h = L.leiden_create(g.off, g.idx, g.w)
+    C, q, st = L.leiden_static(h)
+    say("static Q", q, "passes", st["passes"], "ms", round(st["ms_total"], 1))
+    C = _state_checks(h, g, C, q)
+
+    ncomm = int(C.max()) + 1
+    say("aggregate, communities", ncomm)
+    off, idx, w = L.leiden_aggregate(g.off, g.idx, g.w, C, ncomm)
+    ref = oracle.aggregate(og(g), C, ncomm)
+    assert np.array_equal(to_np(off), ref.off)
+    gi, gw = _sorted_rows(to_np(off), to_np(idx), to_np(w))
+    assert np.array_equal(gi, ref.idx) and np.array_equal(gw, ref.w)
+
+    cur = g
+    for k, mode in enumerate(("df", "ds")):
+        _, K0, S0, m20 = L.leiden_get_state(h)
+        C0 = to_np(L.leiden_get_state(h)[0])
+        b = gen.random_batch(cur, gen.batch_count(cur.nnz, 1e-4), seed=300 + k)
+        say("update", mode, "batch", b.size)
+        C, q, st, tr = L.leiden_update(h, dev_batch(b), mode, trace=True)
+        gt, _ = oracle.apply_batch(og(cur), ob(b))
+        off, idx, w = L.leiden_get_graph(h)
+        assert np.array_equal(to_np(off), gt.off)
+        assert np.array_equal(to_np(idx), gt.idx) and np.array_equal(to_np(w), gt.w)
+        dV, rng, dC = oracle.mark(mode, gt, ob(b), C0, to_np(K0), to_np(S0), m20)
+        assert np.array_equal(to_np(tr["affected"]), dV)
+        assert np.array_equal(to_np(tr["in_range"]), rng)
+        assert np.array_equal(to_np(tr["changed"]), dC)
+        say(mode, "affected", int(dV.sum()), "changed", int(dC.sum()), "Q", q)
+        cur = gen.CSR(gt.n, gt.off, gt.idx, gt.w)
+        _state_checks(h, cur, C, q)
