@@ -38,7 +38,7 @@ enum Slot {
   G0_off, G0_idx, G0_w, G0_crow, G1_off, G1_idx, G1_w, G1_crow,
   // aggregation
   A_cnt, A_coff, A_mem, A_mdeg, A_mpos, A_mcrow, A_toff, A_hidx, A_hw, A_rowlen, A_pkey, A_pval,
-  A_pcnt_item, A_pcnt, A_tcap, A_tstart, A_tkeys, A_tvals,
+  A_pcnt_item, A_pcnt, A_tcap, A_tstart, A_tkeys, A_tvals, A_pcrow,
   // hubs
   H_v, H_cnt, H_ch, H_tab, H_sg, H_chub, H_shub, H_tk, H_tv, H_own, H_pg, H_pc, H_soff,
   H_fill, H_bnd, L_act, W_keys, W_vals, W_list,
@@ -531,7 +531,9 @@ Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, i
     fill_i32(tk, -1, tc, x.s);
     x.zero(tv, tc);
     agg_part_insert(a, tk, tv, x.s);
-    agg_part_emit(a, tk, tv, tc, x.s);
+    int32_t *pcrow = x.get<int32_t>(A_pcrow, ceil_div(tc, (int64_t)kChunk) + 2);
+    chunk_start_rows_search(a.tstart, ncomm, tc, pcrow, x.s);
+    agg_part_emit(a, tk, tv, tc, pcrow, x.s);
     x.launched("agg_parts");
   }
   scan_i32_i64(x, a.rowlen, a.out_off, ncomm + 1);

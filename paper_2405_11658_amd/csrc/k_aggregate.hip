@@ -163,25 +163,52 @@ void agg_part_insert(const AggArgs &a, int *tkeys, double *tvals, hipStream_t s)
   if (a.nnz > 0) hipLaunchKernelGGL(k_agg_part_insert, (int)ceil_div(a.nnz, kChunk), 256, 0, s, a, tkeys, tvals);
 }
 
-__global__ void k_agg_part_emit(AggArgs a, const int *tkeys, const double *tvals, int64_t tc) {
-  for (int64_t s0 = (int64_t)blockIdx.x * blockDim.x; s0 < tc; s0 += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t s = s0 + threadIdx.x;
-    int d = kEmpty;
-    int c = 0;
-    if (s < tc) {
-      d = tkeys[s];
-      if (d != kEmpty) c = (int)(upper_bound_i64(a.tstart, 0, a.ncomm + 1, s) - 1);
-    }
-    const bool used = d != kEmpty;
-    const int pos = wave_peel_inc(a.rowlen, c, used);
-    if (used) {
-      a.hidx[a.toff[c] + pos] = d;
-      a.hw[a.toff[c] + pos] = (float)tvals[s];
+// Emission of the merged partials: the table slots (community c owns
+// [tstart[c], tstart[c+1])) are cut into chunks; each workgroup maps its
+// slots to communities with an LDS max-scan, counts its used slots per
+// community, reserves their output range with one atomic per community and
+// writes them.
+__global__ __launch_bounds__(256) void k_agg_part_emit(AggArgs a, const int *tkeys, const double *tvals,
+                                                      int64_t tc, const int32_t *crow) {
+  __shared__ int rowof[kChunk];
+  __shared__ int cnt[kChunk];
+  __shared__ int base[kChunk];
+  __shared__ int sh[16];
+  const int64_t q0 = (int64_t)blockIdx.x * kChunk;
+  const int len = (int)min((int64_t)kChunk, tc - q0);
+  chunk_rows<kChunk>(a.tstart, q0, len, crow[blockIdx.x], crow[blockIdx.x + 1], rowof, sh);
+  for (int t = threadIdx.x; t < kChunk; t += blockDim.x) cnt[t] = 0;
+  __syncthreads();
+  for (int t = threadIdx.x; t < len; t += blockDim.x) {
+    if (tkeys[q0 + t] == kEmpty) continue;
+    int64_t s0 = a.tstart[rowof[t]] - q0;
+    if (s0 < 0) s0 = 0;
+    atomicAdd(&cnt[s0], 1);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < len; t += blockDim.x) {
+    const int c = cnt[t];
+    if (c > 0) {
+      base[t] = atomicAdd(&a.rowlen[rowof[t]], c);
+      cnt[t] = 0;
     }
   }
+  __syncthreads();
+  for (int t = threadIdx.x; t < len; t += blockDim.x) {
+    const int d = tkeys[q0 + t];
+    if (d == kEmpty) continue;
+    const int r = rowof[t];
+    int64_t s0 = a.tstart[r] - q0;
+    if (s0 < 0) s0 = 0;
+    const int pos = base[s0] + atomicAdd(&cnt[s0], 1);
+    a.hidx[a.toff[r] + pos] = d;
+    a.hw[a.toff[r] + pos] = (float)tvals[q0 + t];
+  }
 }
-void agg_part_emit(const AggArgs &a, const int *tkeys, const double *tvals, int64_t tc, hipStream_t s) {
-  if (tc > 0) hipLaunchKernelGGL(k_agg_part_emit, flat_grid(tc), 256, 0, s, a, tkeys, tvals, tc);
+void agg_part_emit(const AggArgs &a, const int *tkeys, const double *tvals, int64_t tc, const int32_t *crow,
+                   hipStream_t s) {
+  if (tc > 0) hipLaunchKernelGGL(k_agg_part_emit, (int)ceil_div(tc, (int64_t)kChunk), 256, 0, s, a, tkeys, tvals, tc,
+                                 crow);
 }
 
 // Compaction of the holey rows into the output CSR plus row sums.

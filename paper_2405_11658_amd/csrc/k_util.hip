@@ -50,6 +50,18 @@ void chunk_start_rows(const int64_t *off, int64_t nrows, int64_t nnz, int32_t *o
   hipLaunchKernelGGL(k_chunk_start_rows, flat_grid(nrows), 256, 0, s, off, nrows, nnz, out);
 }
 
+// The same by a binary search per chunk: cheaper when there are many more
+// rows than chunks.
+__global__ void k_chunk_start_rows_search(const int64_t *off, int64_t nrows, int64_t nnz, int32_t *out) {
+  const int64_t nchunks = ceil_div(nnz, kChunk);
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q <= nchunks; q += (int64_t)gridDim.x * blockDim.x)
+    out[q] = (int32_t)(q == nchunks ? (nrows > 0 ? nrows - 1 : 0) : upper_bound_i64(off, 0, nrows, q * kChunk) - 1);
+}
+void chunk_start_rows_search(const int64_t *off, int64_t nrows, int64_t nnz, int32_t *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_chunk_start_rows_search, flat_grid(ceil_div(nnz, kChunk) + 1), 256, 0, s, off, nrows, nnz,
+                     out);
+}
+
 // Row sums over CSR chunks: each block owns kChunk consecutive positions,
 // accumulates per-row partial sums in LDS and adds them to K once per row.
 __global__ __launch_bounds__(256) void k_row_sums(const int64_t *off, const float *w, int64_t nnz,

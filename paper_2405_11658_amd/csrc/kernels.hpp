@@ -40,6 +40,7 @@ void fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_
 void iota_i32(int32_t *p, int64_t n, hipStream_t s);
 // out[b] = row owning position b*kChunk (b < nchunks); out[nchunks] = nrows-1.
 void chunk_start_rows(const int64_t *off, int64_t nrows, int64_t nnz, int32_t *out, hipStream_t s);
+void chunk_start_rows_search(const int64_t *off, int64_t nrows, int64_t nnz, int32_t *out, hipStream_t s);
 // K[r] = sum of w over row r (FP64); K must be zeroed.
 void row_sums(const int64_t *off, const float *w, int64_t nrows, int64_t nnz, const int32_t *crow,
               double *K, hipStream_t s);
@@ -251,7 +252,8 @@ void agg_toff(const AggArgs &a, hipStream_t s);
 void agg_items(const AggArgs &a, int64_t M, hipStream_t s);  // needs mcrow, toff; zeroes nothing
 void agg_caps(const AggArgs &a, hipStream_t s);
 void agg_part_insert(const AggArgs &a, int *tkeys, double *tvals, hipStream_t s);
-void agg_part_emit(const AggArgs &a, const int *tkeys, const double *tvals, int64_t tc, hipStream_t s);
+void agg_part_emit(const AggArgs &a, const int *tkeys, const double *tvals, int64_t tc, const int32_t *crow,
+                   hipStream_t s);
 void agg_compact(const AggArgs &a, int64_t nnz_out, hipStream_t s);
 
 // ---- k_modularity.hip --------------------------------------------------------
