@@ -117,6 +117,7 @@ constexpr int kDefaultAsyncWaves = 2048;  // wavefronts of the asynchronous swee
 constexpr int kMaxAsyncWaves = 65536;
 constexpr int64_t kVertsPerWave = 1024;  // level-0 vertices with edges per sweeping wavefront, at least
 constexpr int64_t kVertsPerWaveUpper = 256;  // the same for the aggregated levels
+constexpr int kStallIters = 3;  // see the iteration loop of run_core
 
 // Wavefronts of an asynchronous sweep over a level with n vertices that have
 // edges: at most `cap`, and few enough that the vertices in flight stay a
@@ -124,6 +125,9 @@ constexpr int64_t kVertsPerWaveUpper = 256;  // the same for the aggregated leve
 // degenerates into a synchronous update that oscillates and loses modularity).
 // The first level decides most of the final modularity; the aggregated ones
 // tolerate four times as many vertices in flight.
+// Larger per-wavefront LDS tables when the level's average degree is high.
+bool wide_tables(int64_t nnz, int64_t with_edges) { return with_edges > 0 && nnz / with_edges > 128; }
+
 int level_waves(int cap, int64_t n, int pass) {
   int64_t w = n / (pass == 0 ? kVertsPerWave : kVertsPerWaveUpper);
   w = std::max<int64_t>(1, std::min<int64_t>(w, cap));
@@ -642,6 +646,8 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     ma.alist = alist; ma.alen = alen;
     int li = 0;
     int64_t moves_total = 0;
+    unsigned long long min_moves = ~0ull;
+    int stall = 0;
     tm.mark(CAT_OTHER);
     for (int it = 0; it < p.max_iter; ++it) {
       x.zero(counts, NS * kNB);
@@ -678,7 +684,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
       }
       if (async) {
         x.zero(&sc->anext, 1);
-        move_async(ma, level_waves(NW, alen, pass), x.s);
+        move_async(ma, level_waves(NW, alen, pass), wide_tables(g.nnz, alen), x.s);
       }
       if (gi) tiled_sum(gi, nl, tiles, &sc->gain, x.s);
       x.launched("move iteration");
@@ -692,6 +698,19 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
       moves_total += (int64_t)r.moves;
       li = it + 1;
       if (r.gain <= Tp) break;
+      // Asynchronous mode, aggregated levels: vertices moved against a state
+      // that concurrently processed neighbours are changing can trade places
+      // indefinitely, each move scored as a gain; the tolerance test then
+      // never passes.  Stop when the number of moves has not reached a new
+      // minimum for kStallIters iterations in a row.
+      if (async && pass > 0) {
+        if (r.moves < min_moves) {
+          min_moves = r.moves;
+          stall = 0;
+        } else if (++stall >= kStallIters) {
+          break;
+        }
+      }
     }
     tm.mark(CAT_MOVE);
     if (st && pass < LEIDEN_MAX_PASSES) {
@@ -741,7 +760,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     }
     if (async) {
       x.zero(&sc->anext, 1);
-      refine_async(ra, level_waves(NW, alen, pass), x.s);
+      refine_async(ra, level_waves(NW, alen, pass), wide_tables(g.nnz, alen), x.s);
     }
     x.launched("refine sweep");
     const int rounds = 1;

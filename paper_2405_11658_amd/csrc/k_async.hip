@@ -23,8 +23,10 @@
 
 namespace lk {
 
-constexpr int kAsyncWaves = 4;        // wavefronts per workgroup
-constexpr int kAsyncLds = 512;        // LDS table slots per wavefront (degree <= 256)
+// Two shapes: 4 wavefronts per workgroup with 512 LDS table slots each
+// (degree <= 256 in LDS), or 2 with 2048 slots (degree <= 1024 in LDS) for
+// levels whose vertices have high average degree.
+constexpr int kAsyncWaves = 4;
 
 __device__ __forceinline__ int ld_int(const int32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -62,10 +64,11 @@ struct WaveTable {
   bool global;
 };
 
-__device__ __forceinline__ WaveTable wave_table(int *lk, double *lv, int *gk, double *gv, int64_t deg) {
+__device__ __forceinline__ WaveTable wave_table(int *lk, double *lv, int *gk, double *gv, int64_t deg,
+                                                int ldscap) {
   WaveTable t;
   const uint32_t cap = table_cap(deg);
-  t.global = cap > (uint32_t)kAsyncLds;
+  t.global = cap > (uint32_t)ldscap;
   t.keys = t.global ? gk : lk;
   t.vals = t.global ? gv : lv;
   t.mask = cap - 1;
@@ -109,11 +112,12 @@ __device__ __forceinline__ int64_t grab(unsigned long long *next) {
   return (int64_t)__shfl(base, 0);
 }
 
+template <int WPB, int LDSCAP>
 __global__ __launch_bounds__(256) void k_move_async(MoveArgs a) {
-  __shared__ int skeys[kAsyncWaves][kAsyncLds];
-  __shared__ double svals[kAsyncWaves][kAsyncLds];
+  __shared__ int skeys[WPB][LDSCAP];
+  __shared__ double svals[WPB][LDSCAP];
   const int wv = threadIdx.x / kWave;
-  const int64_t gw = (int64_t)blockIdx.x * kAsyncWaves + wv;
+  const int64_t gw = (int64_t)blockIdx.x * WPB + wv;
   int *gk = a.akeys + gw * kHubDeg * 2;
   double *gv = a.avals + gw * kHubDeg * 2;
   double gsum = 0.0;
@@ -148,7 +152,7 @@ __global__ __launch_bounds__(256) void k_move_async(MoveArgs a) {
       const int64_t e0 = __shfl(e0v, k), e1 = __shfl(e1v, k);
       const int d = __shfl(dv, k);
       const double Ki = __shfl(kv, k);
-      WaveTable t = wave_table(skeys[wv], svals[wv], gk, gv, e1 - e0);
+      WaveTable t = wave_table(skeys[wv], svals[wv], gk, gv, e1 - e0, LDSCAP);
       for (int64_t e = e0 + lane(); e < e1; e += kWave) {
         const int j = a.idx[e];
         if (j != i) table_add(t.keys, t.vals, t.mask, ld_int(&a.C[j]), (double)a.w[e]);
@@ -179,18 +183,27 @@ __global__ __launch_bounds__(256) void k_move_async(MoveArgs a) {
   }
 }
 
-// `waves` below kAsyncWaves: one workgroup of that many wavefronts
-void move_async(const MoveArgs &a, int waves, hipStream_t s) {
+// `waves` is rounded down to whole workgroups (at least one, possibly
+// smaller); wide = the 2-wavefront, 2048-slot shape.
+template <class Args, class K4, class K2>
+static void launch_async(K4 k4, K2 k2, const Args &a, int waves, bool wide, hipStream_t s) {
   if (a.n <= 0 || waves <= 0) return;
-  const int per = waves < kAsyncWaves ? waves : kAsyncWaves;
-  hipLaunchKernelGGL(k_move_async, waves / per, per * kWave, 0, s, a);
+  const int wpb = wide ? 2 : kAsyncWaves;
+  const int per = waves < wpb ? waves : wpb;
+  if (wide) hipLaunchKernelGGL(k2, waves / per, per * kWave, 0, s, a);
+  else hipLaunchKernelGGL(k4, waves / per, per * kWave, 0, s, a);
 }
 
+void move_async(const MoveArgs &a, int waves, bool wide, hipStream_t s) {
+  launch_async(k_move_async<4, 512>, k_move_async<2, 2048>, a, waves, wide, s);
+}
+
+template <int WPB, int LDSCAP>
 __global__ __launch_bounds__(256) void k_refine_async(RefineArgs a) {
-  __shared__ int skeys[kAsyncWaves][kAsyncLds];
-  __shared__ double svals[kAsyncWaves][kAsyncLds];
+  __shared__ int skeys[WPB][LDSCAP];
+  __shared__ double svals[WPB][LDSCAP];
   const int wv = threadIdx.x / kWave;
-  const int64_t gw = (int64_t)blockIdx.x * kAsyncWaves + wv;
+  const int64_t gw = (int64_t)blockIdx.x * WPB + wv;
   int *gk = a.akeys + gw * kHubDeg * 2;
   double *gv = a.avals + gw * kHubDeg * 2;
   for (;;) {
@@ -225,7 +238,7 @@ __global__ __launch_bounds__(256) void k_refine_async(RefineArgs a) {
       const double Ki = __shfl(kv, k);
       const int cb = __shfl(cbv, k);
       const int64_t e0 = __shfl(e0v, k), e1 = __shfl(e1v, k);
-      WaveTable t = wave_table(skeys[wv], svals[wv], gk, gv, e1 - e0);
+      WaveTable t = wave_table(skeys[wv], svals[wv], gk, gv, e1 - e0, LDSCAP);
       for (int64_t e = e0 + lane(); e < e1; e += kWave) {
         const int j = a.idx[e];
         if (j != i && a.CB[j] == cb) table_add(t.keys, t.vals, t.mask, ld_int(&a.C[j]), (double)a.w[e]);
@@ -249,10 +262,8 @@ __global__ __launch_bounds__(256) void k_refine_async(RefineArgs a) {
   }
 }
 
-void refine_async(const RefineArgs &a, int waves, hipStream_t s) {
-  if (a.n <= 0 || waves <= 0) return;
-  const int per = waves < kAsyncWaves ? waves : kAsyncWaves;
-  hipLaunchKernelGGL(k_refine_async, waves / per, per * kWave, 0, s, a);
+void refine_async(const RefineArgs &a, int waves, bool wide, hipStream_t s) {
+  launch_async(k_refine_async<4, 512>, k_refine_async<2, 2048>, a, waves, wide, s);
 }
 
 __global__ void k_edge_flags(const int64_t *off, int64_t n, int32_t *flags) {

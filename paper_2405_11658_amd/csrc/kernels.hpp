@@ -204,13 +204,14 @@ void refine_accept(const RefineArgs &a, const int64_t *region_h, hipStream_t s);
 
 // ---- k_async.hip ---------------------------------------------------------------
 constexpr int kAsyncChunk = 64;  // vertex ids taken per grab of the asynchronous sweeps
-// `waves` wavefronts (a multiple of 4) sweep the ids; vertices of degree
-// <= kHubDeg only.  Tables: 2*kHubDeg slots per wavefront in akeys/avals.
-void move_async(const MoveArgs &a, int waves, hipStream_t s);
+// `waves` wavefronts sweep the list; vertices of degree <= kHubDeg only.
+// Tables: LDS, else 2*kHubDeg slots per wavefront in akeys/avals; `wide`
+// selects larger LDS tables (for levels of high average degree).
+void move_async(const MoveArgs &a, int waves, bool wide, hipStream_t s);
 // list of vertices with edges in ascending order: flags then scan then scatter
 void edge_flags(const int64_t *off, int64_t n, int32_t *flags, hipStream_t s);
 void edge_list(const int64_t *off, int64_t n, const int32_t *pos, int32_t *list, hipStream_t s);
-void refine_async(const RefineArgs &a, int waves, hipStream_t s);
+void refine_async(const RefineArgs &a, int waves, bool wide, hipStream_t s);
 // hub frontier of slice a.s (a.hbeg..a.hend of the hub plan) for the hub-only sliced phase
 void move_hub_frontier(const MoveArgs &a, hipStream_t s);
 
