@@ -41,7 +41,7 @@ enum Slot {
   A_pcnt_item, A_pcnt, A_tcap, A_tstart, A_tkeys, A_tvals, A_pcrow,
   // hubs
   H_v, H_cnt, H_ch, H_tab, H_sg, H_chub, H_shub, H_tk, H_tv, H_own, H_pg, H_pc, H_soff,
-  H_fill, H_bnd, L_act, W_keys, W_vals, W_list,
+  H_fill, H_bnd, H_flag, L_act, W_keys, W_vals, W_list,
   // primitives
   T_tmp,
   // batch
@@ -458,6 +458,8 @@ HubHost hub_plan(Ctx &x, const Level &g, int S, const Layout &B) {
   x.zero(H.p.vals, ntab);
   H.p.own = x.get<double>(H_own, nh);
   x.zero(H.p.own, nh);
+  H.p.flag = x.get<int32_t>(H_flag, nh);
+  x.zero(H.p.flag, nh);
   H.p.pg = x.get<double>(H_pg, H.gs[S]);
   H.p.pc = x.get<int32_t>(H_pc, H.gs[S]);
   x.launched("hub tables");

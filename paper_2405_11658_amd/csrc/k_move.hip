@@ -322,6 +322,7 @@ __global__ __launch_bounds__(256) void k_hub_final(MoveArgs a) {
     a.prop[i] = (bc == kNoComm) ? -1 : bc;
     a.gp[i] = bg;
     a.hp.own[h] = 0.0;
+    a.hp.flag[h] = 0;
   }
 }
 
@@ -551,6 +552,8 @@ void move_apply(const MoveArgs &a, const int64_t *region_h, hipStream_t s) {
   for (int b = 0; b < kNB; ++b) move_apply_bucket(a, region_h, b, s);
 }
 
+void move_hub_apply(const MoveArgs &a, hipStream_t s);
+
 void move_apply_bucket(const MoveArgs &a, const int64_t *region_h, int b, hipStream_t s) {
   const int64_t cap = region_h[a.s * kNB + b + 1] - region_h[a.s * kNB + b];
   if (cap <= 0) return;
@@ -560,8 +563,72 @@ void move_apply_bucket(const MoveArgs &a, const int64_t *region_h, int b, hipStr
     case 2: hipLaunchKernelGGL(k_apply_small<32>, grid_for(cap, 8), 256, 0, s, a, b); break;
     case 3: hipLaunchKernelGGL((k_apply_team<64, 256>), grid_for(cap, 4), 256, 0, s, a, b); break;
     case 4: hipLaunchKernelGGL((k_apply_team<256, 256>), grid_for(cap, 1, 2048), 256, 0, s, a, b); break;
-    case 5: hipLaunchKernelGGL((k_apply_team<512, 512>), grid_for(cap, 1, 1024), 512, 0, s, a, b); break;
+    case 5: move_hub_apply(a, s); break;
   }
+}
+
+// ---- apply for hubs, chunk-parallel --------------------------------------------
+// The same rule as the other buckets, with the hub's edge chunks spread over
+// workgroups: (1) a chunk that finds a same-slice neighbour proposing the
+// exact reverse move with priority flags the hub blocked; (2) one thread per
+// hub moves it or leaves it unprocessed; (3) the chunks of moved hubs mark
+// their neighbours unprocessed.
+__global__ __launch_bounds__(256) void k_hub_rev(MoveArgs a) {
+  const int64_t q = a.qbeg + blockIdx.x;
+  const int h = a.hp.chub[q];
+  const int i = a.hp.hubv[h];
+  if (!a.act[i]) return;
+  const int p = a.prop[i];
+  if (p < 0) return;
+  const int fi = a.from[i];
+  const double g = a.gp[i];
+  const int64_t e0 = a.off[i] + (q - a.hp.hch[h]) * kHubEC;
+  const int64_t e1 = min(e0 + (int64_t)kHubEC, a.off[i + 1]);
+  bool blocked = false;
+  for (int64_t e = e0 + threadIdx.x; e < e1 && !blocked; e += blockDim.x) {
+    const int j = a.idx[e];
+    if (j != i && reverse_wins(a, j, i, fi, p, g)) blocked = true;
+  }
+  if (blocked) a.hp.flag[h] = 1;
+}
+
+__global__ __launch_bounds__(256) void k_hub_move(MoveArgs a) {
+  double gsum = 0.0;
+  long long mv = 0;
+  const int64_t h = a.hbeg + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (h < a.hend) {
+    const int i = a.hp.hubv[h];
+    const int p = a.act[i] ? a.prop[i] : -1;
+    if (p >= 0) {
+      if (a.hp.flag[h] == 1) {
+        a.U[i] = 1;
+      } else {
+        do_move(a, i, a.from[i], p, a.gp[i], gsum, mv);
+        a.hp.flag[h] = 2;
+      }
+    }
+  }
+  flush_gain(a, gsum, mv);
+}
+
+__global__ __launch_bounds__(256) void k_hub_mark(MoveArgs a) {
+  const int64_t q = a.qbeg + blockIdx.x;
+  const int h = a.hp.chub[q];
+  if (a.hp.flag[h] != 2) return;
+  const int i = a.hp.hubv[h];
+  const int64_t e0 = a.off[i] + (q - a.hp.hch[h]) * kHubEC;
+  const int64_t e1 = min(e0 + (int64_t)kHubEC, a.off[i + 1]);
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const int j = a.idx[e];
+    if (j != i) a.U[j] = 1;
+  }
+}
+
+void move_hub_apply(const MoveArgs &a, hipStream_t s) {
+  if (a.qend <= a.qbeg) return;
+  hipLaunchKernelGGL(k_hub_rev, (int)(a.qend - a.qbeg), 256, 0, s, a);
+  hipLaunchKernelGGL(k_hub_move, (int)ceil_div(a.hend - a.hbeg, (int64_t)256), 256, 0, s, a);
+  hipLaunchKernelGGL(k_hub_mark, (int)(a.qend - a.qbeg), 256, 0, s, a);
 }
 
 // ---- fixed-order gain total (synchronous mode) ------------------------------------

@@ -92,6 +92,7 @@ struct HubPlan {
   double *own;     // [nhub] weight to the hub's own community (zero between uses)
   double *pg;      // per-segment best gain
   int32_t *pc;     // per-segment best community
+  int32_t *flag;   // [nhub] apply state: 1 blocked, 2 moved (reset by the final reduction)
 };
 
 struct MoveArgs {
