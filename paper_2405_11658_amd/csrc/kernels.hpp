@@ -78,7 +78,7 @@ size_t seg_sort_i32_f32(void *temp, size_t tbytes, const int32_t *kin, int32_t *
 // slice, each split into edge chunks (one gather workgroup each) and owning
 // a global open-addressing table split into scoring segments.
 constexpr int64_t kHubDeg = 2048;  // degree above which a vertex is a hub
-constexpr int kHubEC = 2048;       // edges per gather workgroup
+constexpr int kHubEC = 512;        // edges per gather workgroup
 constexpr int kHubSeg = 4096;      // table slots per scoring workgroup
 struct HubPlan {
   int32_t *hubv;   // [nhub] hub ids, slice-major
