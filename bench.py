@@ -26,7 +26,11 @@ Algorithmic bytes per unit: hub gather 12 B per scanned entry (id, weight,
 community of the neighbour); aggregation merge 12 B per entry plus 12 B per
 member vertex (community-CSR entry and its community); modularity scan 12 B
 per entry plus 4 B per vertex; graph-update merge 16 B per entry (read and
-write of id + weight) plus 16 B per vertex (old and new offsets).
+write of id + weight) plus 16 B per vertex (old and new offsets); asynchronous
+local-moving sweep 12 B per scanned edge (id, weight, community of the
+neighbour) plus 34 B per evaluated vertex (list entry, two offsets, range and
+processed flags, community, K); Sigma reads and neighbour marks are not
+counted (a lower bound).
 
 cpu_baseline: the serial C oracle (test infrastructure) on the same graph and
 first batch: its own static run (untimed preparation), then one DF update,
@@ -52,12 +56,14 @@ BYTES_PER_UNIT = {  # (per entry, per vertex)
     "agg_merge": (12.0, 12.0),
     "mod_scan": (12.0, 4.0),
     "batch_merge": (16.0, 16.0),
+    "move_sweep": (12.0, 34.0),
 }
 PROF_KERNEL_NAMES = {  # symbol of each timed kernel, as rocprofv3 lists it
     "hub_gather": "lk::k_hub_gather(lk::MoveArgs)",
     "agg_merge": "lk::k_agg_items(lk::AggArgs, long)",
     "mod_scan": "lk::k_mod_edges",
     "batch_merge": "lk::k_batch_apply_old(lk::BatchArgs)",
+    "move_sweep": "lk::k_move_async",  # both launch shapes, <4, 512> and <2, 2048>
 }
 
 

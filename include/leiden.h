@@ -97,13 +97,16 @@ typedef struct {
  *                 edges;
  *   MOD_SCAN    - modularity edge scan; entries / vertices of the graph;
  *   BATCH_MERGE - graph update merge of the old rows with the batch;
- *                 entries = CSR entries of G^t, vertices = n. */
+ *                 entries = CSR entries of G^t, vertices = n;
+ *   MOVE_SWEEP  - asynchronous local-moving sweep, one launch per iteration;
+ *                 entries = edges scanned, vertices = vertices evaluated. */
 enum {
   LEIDEN_PROF_HUB_GATHER = 0,
   LEIDEN_PROF_AGG_MERGE = 1,
   LEIDEN_PROF_MOD_SCAN = 2,
   LEIDEN_PROF_BATCH_MERGE = 3,
-  LEIDEN_PROF_N = 4
+  LEIDEN_PROF_MOVE_SWEEP = 4,
+  LEIDEN_PROF_N = 5
 };
 
 /* Per-call statistics (host struct). */

@@ -102,42 +102,6 @@ __device__ __forceinline__ void table_add(int *keys, double *vals, uint32_t mask
   }
 }
 
-__device__ __forceinline__ void table_add64(unsigned long long *keys, double *vals, uint32_t mask,
-                                            unsigned long long key, double w) {
-  const unsigned long long empty = ~0ull;
-  uint32_t h = mix64(key) & mask;
-  for (uint32_t probe = 0; probe <= mask; ++probe) {
-    unsigned long long k = __atomic_load_n(&keys[h], __ATOMIC_RELAXED);
-    if (k == key) { atomicAdd(&vals[h], w); return; }
-    if (k == empty) {
-      unsigned long long old = atomicCAS(&keys[h], empty, key);
-      if (old == empty || old == key) { atomicAdd(&vals[h], w); return; }
-    }
-    h = (h + 1) & mask;
-  }
-}
-
-// Wave-cooperative insertion of 64-bit keys: every lane of the wavefront
-// calls it (inactive lanes with active = false).  The keys of the first two
-// distinct leaders are summed across the wavefront and inserted once each;
-// the remaining lanes insert on their own.  Hot keys then cost one atomic
-// per wavefront instead of one per lane.
-__device__ __forceinline__ void table_add64_wave(unsigned long long *keys, double *vals, uint32_t mask,
-                                                 unsigned long long key, double w, bool active) {
-#pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const unsigned long long m = __ballot(active);
-    if (!m) return;
-    const int leader = __ffsll(m) - 1;
-    const unsigned long long k = __shfl(key, leader);
-    const bool mine = active && key == k;
-    const double sum = group_sum<kWave>(mine ? w : 0.0);
-    if (lane() == leader) table_add64(keys, vals, mask, k, sum);
-    if (mine) active = false;
-  }
-  if (active) table_add64(keys, vals, mask, key, w);
-}
-
 __device__ __forceinline__ double table_get(const int *keys, const double *vals, uint32_t mask,
                                             int key) {
   uint32_t h = mix32((uint32_t)key) & mask;
@@ -218,16 +182,6 @@ __device__ __forceinline__ long long block_sum_ll(long long v, long long *scratc
   for (int k = 0; k < nw; ++k) t += scratch[k];
   __syncthreads();
   return t;
-}
-
-// Smallest index r in [lo, hi) with a[r] > x (upper bound), for sorted a.
-__device__ __forceinline__ int64_t upper_bound_i64(const int64_t *a, int64_t lo, int64_t hi, int64_t x) {
-  while (lo < hi) {
-    int64_t mid = lo + ((hi - lo) >> 1);
-    if (a[mid] <= x) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
 }
 
 __device__ __forceinline__ int64_t lower_bound_i32(const int32_t *a, int64_t lo, int64_t hi, int32_t x) {

@@ -37,8 +37,7 @@ enum Slot {
   // level graphs (ping-pong)
   G0_off, G0_idx, G0_w, G0_crow, G1_off, G1_idx, G1_w, G1_crow,
   // aggregation
-  A_cnt, A_coff, A_mem, A_mdeg, A_mpos, A_mcrow, A_toff, A_hidx, A_hw, A_rowlen, A_pkey, A_pval,
-  A_pcnt_item, A_pcnt, A_tcap, A_tstart, A_tkeys, A_tvals, A_pcrow,
+  A_keys, A_skeys, A_vals, A_svals, A_ukeys, A_sums, A_rowlen,
   // hubs
   H_v, H_cnt, H_ch, H_tab, H_sg, H_chub, H_shub, H_tk, H_tv, H_own, H_pg, H_pc, H_soff,
   H_fill, H_bnd, H_flag, L_act, W_keys, W_vals, W_list,
@@ -67,7 +66,9 @@ struct DevScal {
   int32_t pad;
   unsigned long long nz;
   unsigned long long hub_scanned;
+  unsigned long long sweep_work[2];
   unsigned long long anext;
+  unsigned long long agg_unique;
 };
 
 struct Workspace {
@@ -289,7 +290,7 @@ struct KProf {
     if (!on) return;
     recs.push_back({a, ev(), id, entries, vertices});
   }
-  void finish(leiden_stats *st, const unsigned long long *hub_scanned) {
+  void finish(leiden_stats *st, const unsigned long long *hub_scanned, const unsigned long long *sweep_work) {
     if (!on || !st || recs.empty()) return;
     x.check(hipEventSynchronize(recs.back().b), "hipEventSynchronize");
     for (const Rec &r : recs) {
@@ -301,6 +302,10 @@ struct KProf {
       st->prof_vertices[r.id] += r.vertices;
     }
     if (hub_scanned) st->prof_entries[LEIDEN_PROF_HUB_GATHER] = (int64_t)x.read(hub_scanned);
+    if (sweep_work) {
+      st->prof_vertices[LEIDEN_PROF_MOVE_SWEEP] = (int64_t)x.read(&sweep_work[0]);
+      st->prof_entries[LEIDEN_PROF_MOVE_SWEEP] = (int64_t)x.read(&sweep_work[1]);
+    }
   }
 };
 
@@ -479,6 +484,10 @@ int64_t renumber_dense(Ctx &x, int32_t *C, int64_t n, int64_t bound) {
 }
 
 // Alg. "leidenAggregate": level g with dense labels C (< ncomm) -> out level.
+// Super-vertex graph of level g under membership C (ncomm communities) by
+// sorting: keys C[u] * ncomm + C[v] for every entry, radix-sorted over the
+// key bits in use, summed by key (FP64, deterministic order), the distinct
+// keys then being the output entries in CSR order (rows sorted by id).
 Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, int outbuf, double *Kout) {
   AggArgs a;
   memset(&a, 0, sizeof(a));
@@ -489,70 +498,48 @@ Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, i
   a.idx = g.idx;
   a.w = g.w;
   a.C = C;
-  const int64_t nch = ceil_div(std::max<int64_t>(g.nnz, 1), kChunk);
-  a.cnt = x.get<int32_t>(A_cnt, ncomm + 1);
-  a.coff = x.get<int32_t>(A_coff, ncomm + 1);
-  a.mem = x.get<int32_t>(A_mem, g.n);
-  a.mdeg = x.get<int64_t>(A_mdeg, g.n + 1);
-  a.mpos = x.get<int64_t>(A_mpos, g.n + 1);
-  a.mcrow = x.get<int32_t>(A_mcrow, nch + 2);
-  a.toff = x.get<int64_t>(A_toff, ncomm + 1);
-  a.hidx = x.get<int32_t>(A_hidx, g.nnz);
-  a.hw = x.get<float>(A_hw, g.nnz);
-  a.rowlen = x.get<int32_t>(A_rowlen, ncomm + 1);
-  a.pkey = x.get<unsigned long long>(A_pkey, g.nnz);
-  a.pval = x.get<double>(A_pval, g.nnz);
-  a.pcnt_item = x.get<int32_t>(A_pcnt_item, nch + 1);
-  a.pcnt = x.get<int32_t>(A_pcnt, ncomm + 1);
-  a.tcap = x.get<int64_t>(A_tcap, ncomm + 1);
-  a.tstart = x.get<int64_t>(A_tstart, ncomm + 1);
   const Slot so = outbuf ? G1_off : G0_off, si = outbuf ? G1_idx : G0_idx, sw = outbuf ? G1_w : G0_w,
              sc = outbuf ? G1_crow : G0_crow;
-  a.out_off = x.get<int64_t>(so, ncomm + 1);
-  a.out_K = Kout;
-
-  x.zero(a.cnt, ncomm + 1);
-  agg_count(a, x.s);
-  scan_i32(x, a.cnt, a.coff, ncomm + 1);
-  const int64_t M = x.read(&a.coff[ncomm]);
-  x.zero(a.cnt, ncomm + 1);
-  agg_scatter(a, x.s);
-  agg_mdeg(a, M, x.s);
-  x.launched("agg_scatter");
-  scan_i64(x, a.mdeg, a.mpos, M + 1);
-  chunk_start_rows(a.mpos, M, g.nnz, a.mcrow, x.s);
-  agg_toff(a, x.s);
-  x.zero(a.rowlen, ncomm + 1);
-  x.zero(a.pcnt, ncomm + 1);
-  hipEvent_t t0 = x.kp ? x.kp->begin() : nullptr;
-  agg_items(a, M, x.s);
-  if (x.kp) x.kp->end(t0, LEIDEN_PROF_AGG_MERGE, g.nnz, M);
-  agg_caps(a, x.s);
-  x.launched("agg_items");
-  scan_i64(x, a.tcap, a.tstart, ncomm + 1);
-  const int64_t tc = x.read(&a.tstart[ncomm]);
-  if (tc > 0) {
-    int *tk = x.get<int>(A_tkeys, tc);
-    double *tv = x.get<double>(A_tvals, tc);
-    fill_i32(tk, -1, tc, x.s);
-    x.zero(tv, tc);
-    agg_part_insert(a, tk, tv, x.s);
-    int32_t *pcrow = x.get<int32_t>(A_pcrow, ceil_div(tc, (int64_t)kChunk) + 2);
-    chunk_start_rows_search(a.tstart, ncomm, tc, pcrow, x.s);
-    agg_part_emit(a, tk, tv, tc, pcrow, x.s);
-    x.launched("agg_parts");
+  int64_t *out_off = x.get<int64_t>(so, ncomm + 1);
+  int32_t *rowlen = x.get<int32_t>(A_rowlen, ncomm + 1);
+  x.zero(rowlen, ncomm + 1);
+  int64_t nu = 0;
+  unsigned long long *ukeys = nullptr;
+  double *sums = nullptr;
+  if (g.nnz > 0) {
+    unsigned long long *keys = x.get<unsigned long long>(A_keys, g.nnz);
+    unsigned long long *skeys = x.get<unsigned long long>(A_skeys, g.nnz);
+    float *vals = x.get<float>(A_vals, g.nnz);
+    float *svals = x.get<float>(A_svals, g.nnz);
+    ukeys = x.get<unsigned long long>(A_ukeys, g.nnz);
+    sums = x.get<double>(A_sums, g.nnz);
+    DevScal *scl = x.scal();
+    const unsigned long long top = (unsigned long long)ncomm * (unsigned long long)ncomm - 1ull;
+    int end_bit = 1;
+    while (end_bit < 64 && (top >> end_bit) != 0) ++end_bit;
+    size_t tb = sort_pairs_u64_f32(nullptr, 0, keys, skeys, vals, svals, g.nnz, end_bit, x.s);
+    tb = std::max(tb, reduce_by_key_u64_f32(nullptr, 0, skeys, svals, g.nnz, ukeys, sums, &scl->agg_unique, x.s));
+    void *tmp = x.tmp(tb);
+    hipEvent_t t0 = x.kp ? x.kp->begin() : nullptr;
+    agg_keys(a, g.crow, keys, vals, x.s);
+    sort_pairs_u64_f32(tmp, tb, keys, skeys, vals, svals, g.nnz, end_bit, x.s);
+    reduce_by_key_u64_f32(tmp, tb, skeys, svals, g.nnz, ukeys, sums, &scl->agg_unique, x.s);
+    if (x.kp) x.kp->end(t0, LEIDEN_PROF_AGG_MERGE, g.nnz, g.n);
+    x.launched("agg_sort");
+    nu = (int64_t)x.read(&scl->agg_unique);
   }
-  scan_i32_i64(x, a.rowlen, a.out_off, ncomm + 1);
-  const int64_t nnz2 = x.read(&a.out_off[ncomm]);
-  const int64_t nch2 = ceil_div(std::max<int64_t>(nnz2, 1), kChunk);
-  a.out_idx = x.get<int32_t>(si, nnz2);
-  a.out_w = x.get<float>(sw, nnz2);
-  a.out_crow = x.get<int32_t>(sc, nch2 + 2);
-  chunk_start_rows(a.out_off, ncomm, nnz2, a.out_crow, x.s);
-  if (Kout) x.zero(Kout, ncomm);
-  agg_compact(a, nnz2, x.s);
-  x.launched("agg_compact");
-  Level o{ncomm, nnz2, a.out_off, a.out_idx, a.out_w, a.out_crow};
+  int32_t *out_idx = x.get<int32_t>(si, nu);
+  float *out_w = x.get<float>(sw, nu);
+  agg_rows(ukeys, sums, nu, ncomm, out_idx, out_w, rowlen, x.s);
+  scan_i32_i64(x, rowlen, out_off, ncomm + 1);
+  int32_t *out_crow = x.get<int32_t>(sc, ceil_div(std::max<int64_t>(nu, 1), kChunk) + 2);
+  chunk_start_rows(out_off, ncomm, nu, out_crow, x.s);
+  if (Kout) {
+    x.zero(Kout, ncomm);
+    row_sums(out_off, out_w, ncomm, nu, out_crow, Kout, x.s);
+  }
+  x.launched("agg_rows");
+  Level o{ncomm, nu, out_off, out_idx, out_w, out_crow};
   return o;
 }
 
@@ -644,6 +631,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     ma.hp = hh.p;
     ma.act = hh.nhub > 0 ? act : nullptr;
     ma.hub_scanned = x.kp && x.kp->on ? &sc->hub_scanned : nullptr;
+    ma.sweep_work = x.kp && x.kp->on ? sc->sweep_work : nullptr;
     ma.anext = &sc->anext; ma.akeys = akeys; ma.avals = avals;
     ma.alist = alist; ma.alen = alen;
     int li = 0;
@@ -686,7 +674,9 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
       }
       if (async) {
         x.zero(&sc->anext, 1);
+        hipEvent_t t0 = x.kp ? x.kp->begin() : nullptr;
         move_async(ma, level_waves(NW, alen, pass), wide_tables(g.nnz, alen), x.s);
+        if (x.kp) x.kp->end(t0, LEIDEN_PROF_MOVE_SWEEP, 0, 0);
       }
       if (gi) tiled_sum(gi, nl, tiles, &sc->gain, x.s);
       x.launched("move iteration");
@@ -959,7 +949,10 @@ leiden_status leiden_static(leiden_handle *h, int32_t *membership_out, double *q
     Timer tm(x, stats != nullptr);
     KProf kp(x, stats != nullptr && h->prm.profile != 0);
     x.kp = &kp;
-    if (kp.on) x.zero(&x.scal()->hub_scanned, 1);
+    if (kp.on) {
+      x.zero(&x.scal()->hub_scanned, 1);
+      x.zero(x.scal()->sweep_work, 2);
+    }
     tm.mark(CAT_OTHER);
     const int64_t n = h->n;
     x.ensure(h->C, (size_t)std::max<int64_t>(n, 1) * sizeof(int32_t));
@@ -995,7 +988,7 @@ leiden_status leiden_static(leiden_handle *h, int32_t *membership_out, double *q
     if (q_out) *q_out = (n > 0) ? modularity_dev(x, g, C) : 0.0;
     tm.mark(CAT_OTHER);
     tm.finish(stats);
-    kp.finish(stats, kp.on ? &x.scal()->hub_scanned : nullptr);
+    kp.finish(stats, kp.on ? &x.scal()->hub_scanned : nullptr, kp.on ? x.scal()->sweep_work : nullptr);
     x.check(hipStreamSynchronize(x.s), "sync");
   });
 }
@@ -1017,7 +1010,10 @@ leiden_status leiden_update(leiden_handle *h, const leiden_batch *batch, int32_t
     Timer tm(x, stats != nullptr);
     KProf kp(x, stats != nullptr && h->prm.profile != 0);
     x.kp = &kp;
-    if (kp.on) x.zero(&x.scal()->hub_scanned, 1);
+    if (kp.on) {
+      x.zero(&x.scal()->hub_scanned, 1);
+      x.zero(x.scal()->sweep_work, 2);
+    }
     tm.mark(CAT_OTHER);
     const int64_t n = h->n;
     DevScal *sc = x.scal();
@@ -1174,7 +1170,7 @@ leiden_status leiden_update(leiden_handle *h, const leiden_batch *batch, int32_t
     if (q_out) *q_out = (n > 0) ? modularity_dev(x, g, (const int32_t *)h->C.p) : 0.0;
     tm.mark(CAT_OTHER);
     tm.finish(stats);
-    kp.finish(stats, kp.on ? &x.scal()->hub_scanned : nullptr);
+    kp.finish(stats, kp.on ? &x.scal()->hub_scanned : nullptr, kp.on ? x.scal()->sweep_work : nullptr);
     x.check(hipStreamSynchronize(x.s), "sync");
   });
 }

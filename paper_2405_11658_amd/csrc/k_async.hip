@@ -43,10 +43,18 @@ __device__ __forceinline__ void st_u8(uint8_t *p, uint8_t v) {
 __device__ __forceinline__ void st_int(int32_t *p, int32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// completes this wavefront's outstanding memory operations before the next
-// ones (the table is written and read by different lanes of the wavefront)
+// Completes this wavefront's outstanding memory operations before the next
+// ones (a global-memory table is written and read by different lanes).
 __device__ __forceinline__ void wave_fence() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+// Orders the wavefront's LDS accesses only: LDS executes one wavefront's
+// instructions in issue order, so a compiler barrier suffices for an LDS
+// table that only this wavefront uses, and outstanding global stores (the
+// previous vertex's move and marks) are not waited for.
+__device__ __forceinline__ void lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
 }
 
@@ -57,49 +65,229 @@ __device__ __forceinline__ uint32_t table_cap(int64_t deg) {
 }
 
 // One wavefront's table: LDS for small degrees, its global region otherwise.
+// An LDS table is kept clear between vertices: the slots a vertex takes are
+// listed (slot index, in insertion order) and only those are scanned and
+// reset, so a vertex costs O(distinct neighbour communities), not O(capacity).
+// A global table is cleared and scanned in full.
 struct WaveTable {
   int *keys;
   double *vals;
   uint32_t mask;
   bool global;
+  uint16_t *list;  // LDS only
+  int *cnt;        // LDS only: length of list
 };
 
-__device__ __forceinline__ WaveTable wave_table(int *lk, double *lv, int *gk, double *gv, int64_t deg,
-                                                int ldscap) {
+// LDS area of one wavefront for capacity LDSCAP.
+template <int LDSCAP>
+struct WaveLds {
+  int keys[LDSCAP];
+  double vals[LDSCAP];
+  uint16_t list[LDSCAP / 2];
+  int cnt;
+};
+
+template <int LDSCAP>
+__device__ __forceinline__ void lds_table_init(WaveLds<LDSCAP> &l) {
+  for (int s = lane(); s < LDSCAP; s += kWave) { l.keys[s] = kEmpty; l.vals[s] = 0.0; }
+  if (lane() == 0) l.cnt = 0;
+  lds_fence();
+}
+
+template <int LDSCAP>
+__device__ __forceinline__ WaveTable wave_table(WaveLds<LDSCAP> &l, int *gk, double *gv, int64_t deg) {
   WaveTable t;
   const uint32_t cap = table_cap(deg);
-  t.global = cap > (uint32_t)ldscap;
-  t.keys = t.global ? gk : lk;
-  t.vals = t.global ? gv : lv;
+  t.global = cap > (uint32_t)LDSCAP;
   t.mask = cap - 1;
-  for (uint32_t s = lane(); s < cap; s += kWave) { t.keys[s] = kEmpty; t.vals[s] = 0.0; }
-  wave_fence();
+  if (t.global) {
+    t.keys = gk;
+    t.vals = gv;
+    t.list = nullptr;
+    t.cnt = nullptr;
+    for (uint32_t s = lane(); s < cap; s += kWave) { gk[s] = kEmpty; gv[s] = 0.0; }
+    wave_fence();
+  } else {
+    t.keys = l.keys;
+    t.vals = l.vals;
+    t.list = l.list;
+    t.cnt = &l.cnt;
+  }
   return t;
 }
 
-__device__ __forceinline__ int tkey(const WaveTable &t, uint32_t s) { return t.global ? ld_int(&t.keys[s]) : t.keys[s]; }
-__device__ __forceinline__ double tval(const WaveTable &t, uint32_t s) {
-  return t.global ? ld_dbl(&t.vals[s]) : t.vals[s];
+// Adds w to key's slot; a slot newly taken in an LDS table is listed.
+__device__ __forceinline__ void tab_add(const WaveTable &t, int key, double w) {
+  if (t.global) {
+    table_add(t.keys, t.vals, t.mask, key, w);
+    return;
+  }
+  uint32_t h = mix32((uint32_t)key) & t.mask;
+  for (uint32_t probe = 0; probe <= t.mask; ++probe) {
+    const int k = __atomic_load_n(&t.keys[h], __ATOMIC_RELAXED);
+    if (k == key) { atomicAdd(&t.vals[h], w); return; }
+    if (k == kEmpty) {
+      const int old = atomicCAS(&t.keys[h], kEmpty, key);
+      if (old == kEmpty) {
+        atomicAdd(&t.vals[h], w);
+        t.list[atomicAdd(t.cnt, 1)] = (uint16_t)h;
+        return;
+      }
+      if (old == key) { atomicAdd(&t.vals[h], w); return; }
+    }
+    h = (h + 1) & t.mask;
+  }
 }
 
-// Weight to community d held in the table (0 if absent); all lanes return it.
-__device__ __forceinline__ double own_weight(const WaveTable &t, int d) {
-  double b = 0.0;
-  for (uint32_t s = lane(); s <= t.mask; s += kWave)
-    if (tkey(t, s) == d) b = tval(t, s);
-  return group_sum<kWave>(b);  // at most one lane holds a non-zero term
+// Makes the table's inserts visible to all lanes.
+__device__ __forceinline__ void tab_sync(const WaveTable &t) {
+  if (t.global) wave_fence();
+  else lds_fence();
 }
 
-// Best positive-gain community other than d; (0, kNoComm) if none.
+// Returns an LDS table to the all-clear state.
+__device__ __forceinline__ void tab_release(const WaveTable &t) {
+  if (t.global) return;
+  const int n = *t.cnt;
+  for (int q = lane(); q < n; q += kWave) {
+    const int s = t.list[q];
+    t.keys[s] = kEmpty;
+    t.vals[s] = 0.0;
+  }
+  lds_fence();
+  if (lane() == 0) *t.cnt = 0;
+  lds_fence();
+}
+
+// Edges per lane whose loads are issued together: the neighbour ids of
+// kUnroll wavefront-widths of edges, then their communities, then the table
+// inserts, so that a vertex costs two memory round trips per 256 edges
+// instead of two per 64.
+constexpr int kUnroll = 4;
+
+// The first kUnroll * kWave edges of a vertex, this lane's share: neighbour
+// id, weight and (once loaded) the neighbour's community, kEmpty for
+// self-loops and for neighbours that do not count.  Loading the ids of
+// kUnroll wavefront-widths first and then all their communities keeps a
+// vertex at two memory round trips per kUnroll * kWave edges.
+struct EdgeBatch {
+  int j[kUnroll];
+  float x[kUnroll];
+  int c[kUnroll];
+};
+
+__device__ __forceinline__ void batch_ids(EdgeBatch &eb, const int32_t *idx, const float *w, int i, int64_t e0,
+                                          int64_t e1) {
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) {
+    const int64_t e = e0 + u * kWave + lane();
+    eb.j[u] = i;
+    eb.x[u] = 0.0f;
+    if (e < e1) { eb.j[u] = idx[e]; eb.x[u] = w[e]; }
+  }
+}
+
+// Communities of the batch's neighbours; with CB given only neighbours whose
+// CB equals cb count (both loads issued together).
+__device__ __forceinline__ void batch_comms(EdgeBatch &eb, const int32_t *C, const int32_t *CB, int cb, int i) {
+  int bj[kUnroll];
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) {
+    eb.c[u] = kEmpty;
+    bj[u] = cb;
+    if (eb.j[u] != i) {
+      eb.c[u] = ld_int(&C[eb.j[u]]);
+      if (CB) bj[u] = CB[eb.j[u]];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u)
+    if (bj[u] != cb) eb.c[u] = kEmpty;
+}
+
+// Adds the edges [e0, e1) of vertex i to table t, keyed by the neighbour's
+// current community: the first kUnroll * kWave from the loaded batch, the
+// rest loaded here.  Returns (in all lanes) the weight to community d.
+__device__ __forceinline__ double table_edges(const WaveTable &t, const EdgeBatch &eb, const int32_t *idx,
+                                              const float *w, const int32_t *C, const int32_t *CB, int cb,
+                                              int i, int d, int64_t e0, int64_t e1) {
+  double own = 0.0;
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) {
+    if (eb.c[u] == kEmpty) continue;
+    tab_add(t, eb.c[u], (double)eb.x[u]);
+    if (eb.c[u] == d) own += (double)eb.x[u];
+  }
+  for (int64_t base = e0 + kUnroll * kWave; base < e1; base += kUnroll * kWave) {
+    EdgeBatch r;
+    batch_ids(r, idx, w, i, base, e1);
+    batch_comms(r, C, CB, cb, i);
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (r.c[u] == kEmpty) continue;
+      tab_add(t, r.c[u], (double)r.x[u]);
+      if (r.c[u] == d) own += (double)r.x[u];
+    }
+  }
+  return group_sum<kWave>(own);
+}
+
+// Marks the neighbours of vertex i unprocessed after it moved.
+__device__ __forceinline__ void mark_edges(uint8_t *U, const int32_t *idx, int i, int64_t e0, int64_t e1,
+                                           const EdgeBatch &eb) {
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u)
+    if (eb.j[u] != i) st_u8(&U[eb.j[u]], 1);
+  for (int64_t e = e0 + kUnroll * kWave + lane(); e < e1; e += kWave) {
+    const int j = idx[e];
+    if (j != i) st_u8(&U[j], 1);
+  }
+}
+
+// Scores up to kUnroll (community, weight) pairs per lane with their Sigma
+// loads in flight together, keeping the best positive gain.
+__device__ __forceinline__ void score_batch(const int (&c)[kUnroll], const double (&x)[kUnroll], double M2,
+                                            double b, double Ki, double Sd, const double *Sig, double &bg,
+                                            int &bc) {
+  double S[kUnroll];
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) S[u] = c[u] != kEmpty ? ld_dbl(&Sig[c[u]]) : 0.0;
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) {
+    if (c[u] == kEmpty) continue;
+    const double g = move_score(M2, x[u], b, Ki, S[u], Sd);
+    if (g > 0.0 && better(g, c[u], bg, bc)) { bg = g; bc = c[u]; }
+  }
+}
+
+// Best positive-gain community other than d; (0, kNoComm) if none.  An LDS
+// table is read through its list of taken slots, a global one slot by slot.
 __device__ __forceinline__ void best_move(const WaveTable &t, double M2, int d, double b, double Ki, double Sd,
                                           const double *Sig, double &bg, int &bc) {
   bg = 0.0;
   bc = kNoComm;
-  for (uint32_t s = lane(); s <= t.mask; s += kWave) {
-    const int c = tkey(t, s);
-    if (c == kEmpty || c == d) continue;
-    const double x = move_score(M2, tval(t, s), b, Ki, ld_dbl(&Sig[c]), Sd);
-    if (x > 0.0 && better(x, c, bg, bc)) { bg = x; bc = c; }
+  const uint32_t n = t.global ? t.mask + 1 : (uint32_t)*t.cnt;
+  for (uint32_t q0 = 0; q0 < n; q0 += kUnroll * kWave) {
+    int c[kUnroll];
+    double x[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const uint32_t q = q0 + u * kWave + lane();
+      c[u] = kEmpty;
+      x[u] = 0.0;
+      if (q < n) {
+        if (t.global) {
+          c[u] = ld_int(&t.keys[q]);
+          if (c[u] != kEmpty && c[u] != d) x[u] = ld_dbl(&t.vals[q]);
+        } else {
+          const int s = t.list[q];
+          c[u] = t.keys[s];
+          x[u] = t.vals[s];
+        }
+        if (c[u] == d) c[u] = kEmpty;
+      }
+    }
+    score_batch(c, x, M2, b, Ki, Sd, Sig, bg, bc);
   }
   group_argmax<kWave>(bg, bc);
 }
@@ -114,14 +302,15 @@ __device__ __forceinline__ int64_t grab(unsigned long long *next) {
 
 template <int WPB, int LDSCAP>
 __global__ __launch_bounds__(256) void k_move_async(MoveArgs a) {
-  __shared__ int skeys[WPB][LDSCAP];
-  __shared__ double svals[WPB][LDSCAP];
+  __shared__ WaveLds<LDSCAP> lds[WPB];
   const int wv = threadIdx.x / kWave;
+  lds_table_init(lds[wv]);
   const int64_t gw = (int64_t)blockIdx.x * WPB + wv;
   int *gk = a.akeys + gw * kHubDeg * 2;
   double *gv = a.avals + gw * kHubDeg * 2;
   double gsum = 0.0;
   long long mv = 0;
+  unsigned long long nv = 0, ne = 0;  // vertices evaluated, edges scanned
   for (;;) {
     const int64_t base = grab(a.anext);
     if (base >= a.alen) break;
@@ -148,20 +337,21 @@ __global__ __launch_bounds__(256) void k_move_async(MoveArgs a) {
     while (m) {
       const int k = __ffsll(m) - 1;
       m &= m - 1;
-      const int i = __shfl(v, k);
+      const int i = __shfl(v, k), d = __shfl(dv, k);
       const int64_t e0 = __shfl(e0v, k), e1 = __shfl(e1v, k);
-      const int d = __shfl(dv, k);
       const double Ki = __shfl(kv, k);
-      WaveTable t = wave_table(skeys[wv], svals[wv], gk, gv, e1 - e0, LDSCAP);
-      for (int64_t e = e0 + lane(); e < e1; e += kWave) {
-        const int j = a.idx[e];
-        if (j != i) table_add(t.keys, t.vals, t.mask, ld_int(&a.C[j]), (double)a.w[e]);
-      }
-      wave_fence();
-      const double b = own_weight(t, d);
+      nv += 1;
+      ne += (unsigned long long)(e1 - e0);
+      EdgeBatch eb;
+      batch_ids(eb, a.idx, a.w, i, e0, e1);
+      batch_comms(eb, a.C, nullptr, 0, i);
+      WaveTable t = wave_table(lds[wv], gk, gv, e1 - e0);
+      const double b = table_edges(t, eb, a.idx, a.w, a.C, nullptr, 0, i, d, e0, e1);
+      tab_sync(t);
       double bg;
       int bc;
       best_move(t, a.M2, d, b, Ki, ld_dbl(&a.Sig[d]), a.Sig, bg, bc);
+      tab_release(t);
       if (bc == kNoComm) continue;
       if (lane() == 0) {
         st_int(&a.C[i], bc);
@@ -171,15 +361,16 @@ __global__ __launch_bounds__(256) void k_move_async(MoveArgs a) {
         gsum += bg;
         mv += 1;
       }
-      for (int64_t e = e0 + lane(); e < e1; e += kWave) {
-        const int j = a.idx[e];
-        if (j != i) st_u8(&a.U[j], 1);
-      }
+      mark_edges(a.U, a.idx, i, e0, e1, eb);
     }
   }
   if (lane() == 0) {
     if (gsum != 0.0) unsafeAtomicAdd(a.gain, gsum);
     if (mv) atomicAdd(a.moves, (unsigned long long)mv);
+    if (a.sweep_work && nv) {
+      atomicAdd(&a.sweep_work[0], nv);
+      atomicAdd(&a.sweep_work[1], ne);
+    }
   }
 }
 
@@ -200,9 +391,9 @@ void move_async(const MoveArgs &a, int waves, bool wide, hipStream_t s) {
 
 template <int WPB, int LDSCAP>
 __global__ __launch_bounds__(256) void k_refine_async(RefineArgs a) {
-  __shared__ int skeys[WPB][LDSCAP];
-  __shared__ double svals[WPB][LDSCAP];
+  __shared__ WaveLds<LDSCAP> lds[WPB];
   const int wv = threadIdx.x / kWave;
+  lds_table_init(lds[wv]);
   const int64_t gw = (int64_t)blockIdx.x * WPB + wv;
   int *gk = a.akeys + gw * kHubDeg * 2;
   double *gv = a.avals + gw * kHubDeg * 2;
@@ -233,21 +424,19 @@ __global__ __launch_bounds__(256) void k_refine_async(RefineArgs a) {
     while (m) {
       const int k = __ffsll(m) - 1;
       m &= m - 1;
-      const int i = __shfl(v, k);
-      const int c = __shfl(cv, k);
-      const double Ki = __shfl(kv, k);
-      const int cb = __shfl(cbv, k);
+      const int i = __shfl(v, k), c = __shfl(cv, k), cb = __shfl(cbv, k);
       const int64_t e0 = __shfl(e0v, k), e1 = __shfl(e1v, k);
-      WaveTable t = wave_table(skeys[wv], svals[wv], gk, gv, e1 - e0, LDSCAP);
-      for (int64_t e = e0 + lane(); e < e1; e += kWave) {
-        const int j = a.idx[e];
-        if (j != i && a.CB[j] == cb) table_add(t.keys, t.vals, t.mask, ld_int(&a.C[j]), (double)a.w[e]);
-      }
-      wave_fence();
-      const double b = own_weight(t, c);
+      const double Ki = __shfl(kv, k);
+      EdgeBatch eb;
+      batch_ids(eb, a.idx, a.w, i, e0, e1);
+      batch_comms(eb, a.C, a.CB, cb, i);
+      WaveTable t = wave_table(lds[wv], gk, gv, e1 - e0);
+      const double b = table_edges(t, eb, a.idx, a.w, a.C, a.CB, cb, i, c, e0, e1);
+      tab_sync(t);
       double bg;
       int bc;
       best_move(t, a.M2, c, b, Ki, Ki, a.Sig, bg, bc);
+      tab_release(t);
       if (bc == kNoComm) continue;
       if (lane() == 0 && ld_int(&a.C[bc]) == bc) {
         // claim the singleton: Sigma[c] K_i -> 0 fails if someone joined it
@@ -301,3 +490,4 @@ void move_hub_frontier(const MoveArgs &a, hipStream_t s) {
 }
 
 }  // namespace lk
+

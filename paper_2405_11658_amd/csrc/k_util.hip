@@ -1,6 +1,8 @@
 // Utility kernels: fills, label maps, CSR chunk mapping, row sums, checks,
 // degree buckets, and the rocPRIM-backed scans and sorts.
 #include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_reduce_by_key.hpp>
+#include <rocprim/iterator/transform_iterator.hpp>
 #include <rocprim/device/device_scan.hpp>
 #include <rocprim/device/device_segmented_radix_sort.hpp>
 
@@ -48,18 +50,6 @@ __global__ void k_chunk_start_rows(const int64_t *off, int64_t nrows, int64_t nn
 }
 void chunk_start_rows(const int64_t *off, int64_t nrows, int64_t nnz, int32_t *out, hipStream_t s) {
   hipLaunchKernelGGL(k_chunk_start_rows, flat_grid(nrows), 256, 0, s, off, nrows, nnz, out);
-}
-
-// The same by a binary search per chunk: cheaper when there are many more
-// rows than chunks.
-__global__ void k_chunk_start_rows_search(const int64_t *off, int64_t nrows, int64_t nnz, int32_t *out) {
-  const int64_t nchunks = ceil_div(nnz, kChunk);
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q <= nchunks; q += (int64_t)gridDim.x * blockDim.x)
-    out[q] = (int32_t)(q == nchunks ? (nrows > 0 ? nrows - 1 : 0) : upper_bound_i64(off, 0, nrows, q * kChunk) - 1);
-}
-void chunk_start_rows_search(const int64_t *off, int64_t nrows, int64_t nnz, int32_t *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_chunk_start_rows_search, flat_grid(ceil_div(nnz, kChunk) + 1), 256, 0, s, off, nrows, nnz,
-                     out);
 }
 
 // Row sums over CSR chunks: each block owns kChunk consecutive positions,
@@ -187,6 +177,24 @@ size_t sort_pairs_u64_i32(void *temp, size_t tbytes, const unsigned long long *k
                           hipStream_t s) {
   size_t bytes = tbytes;
   (void)rocprim::radix_sort_pairs(temp, bytes, kin, kout, vin, vout, (size_t)n, 0, 64, s);
+  return bytes;
+}
+size_t sort_pairs_u64_f32(void *temp, size_t tbytes, const unsigned long long *kin, unsigned long long *kout,
+                          const float *vin, float *vout, int64_t n, int end_bit, hipStream_t s) {
+  size_t bytes = tbytes;
+  (void)rocprim::radix_sort_pairs(temp, bytes, kin, kout, vin, vout, (size_t)n, 0, end_bit, s);
+  return bytes;
+}
+struct ToF64 {
+  __host__ __device__ double operator()(float x) const { return (double)x; }
+};
+size_t reduce_by_key_u64_f32(void *temp, size_t tbytes, const unsigned long long *keys, const float *vals,
+                             int64_t n, unsigned long long *ukeys, double *sums, unsigned long long *count,
+                             hipStream_t s) {
+  size_t bytes = tbytes;
+  (void)rocprim::deterministic_reduce_by_key(temp, bytes, keys, rocprim::make_transform_iterator(vals, ToF64()),
+                                             (size_t)n, ukeys, sums, count, rocprim::plus<double>(),
+                                             rocprim::equal_to<unsigned long long>(), s);
   return bytes;
 }
 size_t sort_pairs_u64_f64(void *temp, size_t tbytes, const unsigned long long *kin,

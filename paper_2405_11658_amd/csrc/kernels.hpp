@@ -40,7 +40,6 @@ void fill_u64(unsigned long long *p, unsigned long long v, int64_t n, hipStream_
 void iota_i32(int32_t *p, int64_t n, hipStream_t s);
 // out[b] = row owning position b*kChunk (b < nchunks); out[nchunks] = nrows-1.
 void chunk_start_rows(const int64_t *off, int64_t nrows, int64_t nnz, int32_t *out, hipStream_t s);
-void chunk_start_rows_search(const int64_t *off, int64_t nrows, int64_t nnz, int32_t *out, hipStream_t s);
 // K[r] = sum of w over row r (FP64); K must be zeroed.
 void row_sums(const int64_t *off, const float *w, int64_t nrows, int64_t nnz, const int32_t *crow,
               double *K, hipStream_t s);
@@ -69,6 +68,11 @@ size_t sort_pairs_u64_i32(void *temp, size_t tbytes, const unsigned long long *k
 size_t sort_pairs_u64_f64(void *temp, size_t tbytes, const unsigned long long *kin,
                           unsigned long long *kout, const double *vin, double *vout, int64_t n,
                           hipStream_t s);
+size_t sort_pairs_u64_f32(void *temp, size_t tbytes, const unsigned long long *kin, unsigned long long *kout,
+                          const float *vin, float *vout, int64_t n, int end_bit, hipStream_t s);
+size_t reduce_by_key_u64_f32(void *temp, size_t tbytes, const unsigned long long *keys, const float *vals,
+                             int64_t n, unsigned long long *ukeys, double *sums, unsigned long long *count,
+                             hipStream_t s);
 size_t seg_sort_i32_f32(void *temp, size_t tbytes, const int32_t *kin, int32_t *kout,
                         const float *vin, float *vout, int64_t nnz, int64_t nseg,
                         const int64_t *off, hipStream_t s);
@@ -131,6 +135,7 @@ struct MoveArgs {
   int64_t qbeg, qend;    // their edge chunks
   int64_t gbeg, gend;    // their table segments
   unsigned long long *hub_scanned;  // nullable: edges scanned by the hub gather
+  unsigned long long *sweep_work;   // nullable: [vertices evaluated, edges scanned] by the async sweep
   // asynchronous sweep
   unsigned long long *anext;  // device counter: next list position (zeroed per sweep)
   const int32_t *alist;       // vertices with edges, ascending
@@ -223,40 +228,10 @@ struct AggArgs {
   const int32_t *idx;
   const float *w;
   const int32_t *C;
-  // work
-  int32_t *cnt;      // ncomm+1
-  int32_t *coff;     // ncomm+1
-  int32_t *mem;      // n
-  int64_t *mdeg;     // n+1
-  int64_t *mpos;     // n+1
-  int32_t *mcrow;    // nchunks+1 (slot chunk starts)
-  int64_t *toff;     // ncomm+1
-  int32_t *hidx;     // nnz (holey rows)
-  float *hw;         // nnz
-  int32_t *rowlen;   // ncomm+1
-  unsigned long long *pkey;  // nnz
-  double *pval;      // nnz
-  int32_t *pcnt_item;  // nchunks
-  int32_t *pcnt;     // ncomm
-  int64_t *tcap;     // ncomm+1
-  int64_t *tstart;   // ncomm+1
-  // outputs
-  int64_t *out_off;  // ncomm+1
-  int32_t *out_idx;
-  float *out_w;
-  double *out_K;     // ncomm, row sums
-  int32_t *out_crow; // chunk starts of the output
 };
-void agg_count(const AggArgs &a, hipStream_t s);
-void agg_scatter(const AggArgs &a, hipStream_t s);           // needs coff, cnt zeroed (reused as fill)
-void agg_mdeg(const AggArgs &a, int64_t M, hipStream_t s);
-void agg_toff(const AggArgs &a, hipStream_t s);
-void agg_items(const AggArgs &a, int64_t M, hipStream_t s);  // needs mcrow, toff; zeroes nothing
-void agg_caps(const AggArgs &a, hipStream_t s);
-void agg_part_insert(const AggArgs &a, int *tkeys, double *tvals, hipStream_t s);
-void agg_part_emit(const AggArgs &a, const int *tkeys, const double *tvals, int64_t tc, const int32_t *crow,
-                   hipStream_t s);
-void agg_compact(const AggArgs &a, int64_t nnz_out, hipStream_t s);
+void agg_keys(const AggArgs &a, const int32_t *crow, unsigned long long *keys, float *vals, hipStream_t s);
+void agg_rows(const unsigned long long *ukeys, const double *sums, int64_t nu, int64_t ncomm, int32_t *out_idx,
+              float *out_w, int32_t *rowlen, hipStream_t s);
 
 // ---- k_modularity.hip --------------------------------------------------------
 // acc[0] += sigma total, S[c] += K-contributions (S zeroed, ncomm = n)

@@ -157,7 +157,9 @@ def test_default_mode_quality_vs_oracle_async():
     order) on id-permuted planted-partition graphs (no id locality to favour
     either order): static runs, and DF updates started from the same installed
     state on both sides.  The mean gap Q_gpu - Q_oracle must be >= -1e-3 and
-    every instance within 5e-3; every community connected.  (The two orders
+    no instance may fall more than 5e-3 below the oracle (modularity is
+    maximised: a result above the oracle's is not a parity failure); every
+    community connected.  (The two orders
     are different heuristics: relabelling the vertices alone moves the
     oracle's result by about 2.5e-3 on these graphs.)"""
     gaps = []
@@ -184,7 +186,7 @@ def test_default_mode_quality_vs_oracle_async():
     gaps = np.array(gaps)
     say("Q_gpu - Q_oracle_async:", np.round(gaps, 5).tolist(), "mean", round(float(gaps.mean()), 5))
     assert gaps.mean() >= -1e-3
-    assert np.abs(gaps).max() <= 5e-3
+    assert gaps.min() >= -5e-3
 
 
 def test_empty_batch_and_errors():
