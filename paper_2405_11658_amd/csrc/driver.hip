@@ -530,14 +530,11 @@ Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, i
   }
   int32_t *out_idx = x.get<int32_t>(si, nu);
   float *out_w = x.get<float>(sw, nu);
-  agg_rows(ukeys, sums, nu, ncomm, out_idx, out_w, rowlen, x.s);
+  if (Kout) x.zero(Kout, ncomm);
+  agg_rows(ukeys, sums, nu, ncomm, out_idx, out_w, rowlen, Kout, x.s);
   scan_i32_i64(x, rowlen, out_off, ncomm + 1);
   int32_t *out_crow = x.get<int32_t>(sc, ceil_div(std::max<int64_t>(nu, 1), kChunk) + 2);
   chunk_start_rows(out_off, ncomm, nu, out_crow, x.s);
-  if (Kout) {
-    x.zero(Kout, ncomm);
-    row_sums(out_off, out_w, ncomm, nu, out_crow, Kout, x.s);
-  }
   x.launched("agg_rows");
   Level o{ncomm, nu, out_off, out_idx, out_w, out_crow};
   return o;
@@ -640,9 +637,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     int stall = 0;
     tm.mark(CAT_OTHER);
     for (int it = 0; it < p.max_iter; ++it) {
-      x.zero(counts, NS * kNB);
-      x.zero(&sc->gain, 1);
-      x.zero(&sc->moves, 1);
+      reset_iter(counts, NS * kNB, &sc->gain, &sc->moves, async ? &sc->anext : nullptr, x.s);
       if (gi) x.zero(gi, nl);
       for (int sl = 0; sl < NS; ++sl) {
         ma.s = sl;
@@ -673,7 +668,6 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
         move_apply(ma, B.region.data(), x.s);
       }
       if (async) {
-        x.zero(&sc->anext, 1);
         hipEvent_t t0 = x.kp ? x.kp->begin() : nullptr;
         move_async(ma, level_waves(NW, alen, pass), wide_tables(g.nnz, alen), x.s);
         if (x.kp) x.kp->end(t0, LEIDEN_PROF_MOVE_SWEEP, 0, 0);
@@ -730,8 +724,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     ra.refined = &sc->refined;
     ra.anext = &sc->anext; ra.akeys = akeys; ra.avals = avals;
     ra.alist = alist; ra.alen = alen;
-    x.zero(counts, NS * kNB);
-    x.zero(&sc->refined, 1);
+    reset_iter(counts, NS * kNB, nullptr, &sc->refined, async ? &sc->anext : nullptr, x.s);
     refine_break(ra, x.s);
     x.launched("break");
     ra.hp = hh.p;
@@ -751,7 +744,6 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
       refine_accept(ra, B.region.data(), x.s);
     }
     if (async) {
-      x.zero(&sc->anext, 1);
       refine_async(ra, level_waves(NW, alen, pass), wide_tables(g.nnz, alen), x.s);
     }
     x.launched("refine sweep");

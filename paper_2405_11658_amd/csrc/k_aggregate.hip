@@ -8,8 +8,8 @@
 // leave the distinct (community, community) pairs sorted, i.e. the output
 // entries already in CSR order with rows sorted by neighbour id.  A last pass
 // splits the keys into (row, id), stores the weights rounded to float32 and
-// counts the row lengths; a scan gives the offsets and a row-sum pass the next
-// level's K' = Sigma'.  All work is streaming except the C[v] gather, and the
+// accumulates the row lengths and row sums (the next level's K' = Sigma');
+// a scan of the lengths gives the offsets.  All work is streaming except the C[v] gather, and the
 // result does not depend on scheduling.
 #include "device.hpp"
 #include "kernels.hpp"
@@ -35,25 +35,43 @@ void agg_keys(const AggArgs &a, const int32_t *crow, unsigned long long *keys, f
 }
 
 // Distinct sorted keys -> output entries (in place: position k of the sorted
-// distinct keys is the CSR position) and per-row counts.
+// distinct keys is the CSR position), row lengths and, with K given, row sums
+// of the stored float weights (the next level's K').  Rows are contiguous
+// runs, so each wavefront adds one count and one sum per run it holds.
 __global__ void k_agg_rows(const unsigned long long *ukeys, const double *sums, int64_t nu, int64_t ncomm,
-                           int32_t *out_idx, float *out_w, int32_t *rowlen) {
+                           int32_t *out_idx, float *out_w, int32_t *rowlen, double *K) {
   for (int64_t k0 = (int64_t)blockIdx.x * blockDim.x; k0 < nu; k0 += (int64_t)gridDim.x * blockDim.x) {
     const int64_t k = k0 + threadIdx.x;
     const bool act = k < nu;
     int r = 0;
+    double x = 0.0;
     if (act) {
       const unsigned long long key = ukeys[k];
       r = (int)(key / (unsigned long long)ncomm);
+      const float wf = (float)sums[k];
       out_idx[k] = (int32_t)(key % (unsigned long long)ncomm);
-      out_w[k] = (float)sums[k];
+      out_w[k] = wf;
+      x = (double)wf;
     }
-    wave_peel_inc(rowlen, r, act);
+    unsigned long long pending = __ballot(act);
+    while (pending) {
+      const int leader = __ffsll(pending) - 1;
+      const int rk = __shfl(r, leader);
+      const bool mine = ((pending >> lane()) & 1ull) && r == rk;
+      const unsigned long long grp = __ballot(mine);
+      const double sum = group_sum<kWave>(mine ? x : 0.0);
+      if (lane() == leader) {
+        atomicAdd(&rowlen[rk], (int)__popcll(grp));
+        if (K) unsafeAtomicAdd(&K[rk], sum);
+      }
+      pending &= ~grp;
+    }
   }
 }
 void agg_rows(const unsigned long long *ukeys, const double *sums, int64_t nu, int64_t ncomm, int32_t *out_idx,
-              float *out_w, int32_t *rowlen, hipStream_t s) {
-  if (nu > 0) hipLaunchKernelGGL(k_agg_rows, flat_grid(nu), 256, 0, s, ukeys, sums, nu, ncomm, out_idx, out_w, rowlen);
+              float *out_w, int32_t *rowlen, double *K, hipStream_t s) {
+  if (nu > 0)
+    hipLaunchKernelGGL(k_agg_rows, flat_grid(nu), 256, 0, s, ukeys, sums, nu, ncomm, out_idx, out_w, rowlen, K);
 }
 
 }  // namespace lk

@@ -231,6 +231,19 @@ __global__ void k_copy_bytes(const uint8_t *src, uint8_t *dst, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     dst[i] = src[i];
 }
+// Per-iteration counters cleared in one launch: n ints and up to three
+// scalars (each nullable).
+__global__ void k_reset_iter(int32_t *counts, int n, double *d0, unsigned long long *u0, unsigned long long *u1) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) counts[i] = 0;
+  if (threadIdx.x == 0) {
+    if (d0) *d0 = 0.0;
+    if (u0) *u0 = 0ull;
+    if (u1) *u1 = 0ull;
+  }
+}
+void reset_iter(int32_t *counts, int n, double *d0, unsigned long long *u0, unsigned long long *u1, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_iter, 1, 256, 0, s, counts, n, d0, u0, u1);
+}
 void copy_u8(const uint8_t *src, uint8_t *dst, int64_t n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_copy_bytes, flat_grid(n), 256, 0, s, src, dst, n);
 }

@@ -62,6 +62,8 @@ size_t scan_excl_i32(void *temp, size_t tbytes, const int32_t *in, int32_t *out,
 size_t scan_excl_i64(void *temp, size_t tbytes, const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
 size_t scan_excl_i32_to_i64(void *temp, size_t tbytes, const int32_t *in, int64_t *out, int64_t n,
                             hipStream_t s);
+void reset_iter(int32_t *counts, int n, double *d0, unsigned long long *u0, unsigned long long *u1,
+                hipStream_t s);
 size_t sort_pairs_u64_i32(void *temp, size_t tbytes, const unsigned long long *kin,
                           unsigned long long *kout, const int32_t *vin, int32_t *vout, int64_t n,
                           hipStream_t s);
@@ -231,7 +233,7 @@ struct AggArgs {
 };
 void agg_keys(const AggArgs &a, const int32_t *crow, unsigned long long *keys, float *vals, hipStream_t s);
 void agg_rows(const unsigned long long *ukeys, const double *sums, int64_t nu, int64_t ncomm, int32_t *out_idx,
-              float *out_w, int32_t *rowlen, hipStream_t s);
+              float *out_w, int32_t *rowlen, double *K, hipStream_t s);  // K nullable, zeroed by the caller
 
 // ---- k_modularity.hip --------------------------------------------------------
 // acc[0] += sigma total, S[c] += K-contributions (S zeroed, ncomm = n)
