@@ -102,6 +102,29 @@ __device__ __forceinline__ void table_add(int *keys, double *vals, uint32_t mask
   }
 }
 
+// Workgroup-level merge of (key, value) additions before they reach global
+// memory: the block inserts into an LDS table (capacity above the number of
+// distinct keys it inserts) and then issues one atomic per distinct key, so a
+// key shared by many items (a giant community) costs one global atomic per
+// workgroup instead of one per item.  Called by the whole block.
+template <int SLOTS>
+__device__ __forceinline__ void block_merge_clear(int *tk, double *tv) {
+  for (int s = threadIdx.x; s < SLOTS; s += blockDim.x) { tk[s] = kEmpty; tv[s] = 0.0; }
+  __syncthreads();
+}
+template <int SLOTS>
+__device__ __forceinline__ void block_merge_flush(int *tk, double *tv, double *out) {
+  __syncthreads();
+  for (int s = threadIdx.x; s < SLOTS; s += blockDim.x) {
+    if (tk[s] != kEmpty) {
+      unsafeAtomicAdd(&out[tk[s]], tv[s]);
+      tk[s] = kEmpty;
+      tv[s] = 0.0;
+    }
+  }
+  __syncthreads();
+}
+
 __device__ __forceinline__ double table_get(const int *keys, const double *vals, uint32_t mask,
                                             int key) {
   uint32_t h = mix32((uint32_t)key) & mask;

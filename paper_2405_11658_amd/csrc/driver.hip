@@ -158,14 +158,16 @@ struct Ctx {
   void ensure(DBuf &b, size_t bytes) {
     if (bytes == 0) bytes = 16;
     if (b.cap >= bytes) return;
+    // grow by at least a quarter, so that sizes creeping up from call to call
+    // (a graph growing by batches) do not reallocate every time
+    size_t want = std::max(bytes, (size_t)(b.cap + b.cap / 4));
+    want = (want + 255) & ~(size_t)255;
     if (b.p) {
       check(hipStreamSynchronize(s), "hipStreamSynchronize");
       check(hipFree(b.p), "hipFree");
       b.p = nullptr;
       b.cap = 0;
     }
-    size_t want = std::max(bytes, (size_t)(b.cap + b.cap / 4));
-    want = (want + 255) & ~(size_t)255;
     hipError_t e = hipMalloc(&b.p, want);
     if (e != hipSuccess) {
       (void)hipGetLastError();

@@ -1,8 +1,9 @@
 // Modularity, Eq. 1: Q = sum_c [sigma_c / 2m - (Sigma_c / 2m)^2], with sigma_c the
 // weight of stored entries inside c and Sigma_c the total weight of c.  One
 // chunked pass over the CSR accumulates the internal weight and the per-row
-// sums scattered to communities (FP64); a second pass over communities sums
-// Sigma_c and (Sigma_c / 2m)^2.
+// sums, merged by community within the chunk before they are added to
+// Sigma (FP64); a second pass over communities sums Sigma_c and
+// (Sigma_c / 2m)^2.
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -13,13 +14,15 @@ __global__ __launch_bounds__(256) void k_mod_edges(const int64_t *off, const int
                                                    double *acc, double *S) {
   __shared__ int rowof[kChunk];
   __shared__ double ksum[kChunk];
+  __shared__ int tk[2 * kChunk];
+  __shared__ double tv[2 * kChunk];
   __shared__ int sh[16];
   __shared__ double sd[16];
   const int64_t q0 = (int64_t)blockIdx.x * kChunk;
   const int len = (int)min((int64_t)kChunk, nnz - q0);
   chunk_rows<kChunk>(off, q0, len, crow[blockIdx.x], crow[blockIdx.x + 1], rowof, sh);
   for (int t = threadIdx.x; t < kChunk; t += blockDim.x) ksum[t] = 0.0;
-  __syncthreads();
+  block_merge_clear<2 * kChunk>(tk, tv);
   double sig = 0.0;
   for (int t = threadIdx.x; t < len; t += blockDim.x) {
     const int r = rowof[t];
@@ -32,12 +35,12 @@ __global__ __launch_bounds__(256) void k_mod_edges(const int64_t *off, const int
   }
   sig = block_sum(sig, sd);
   if (threadIdx.x == 0 && sig != 0.0) unsafeAtomicAdd(&acc[0], sig);
-  for (int t0 = 0; t0 < kChunk; t0 += blockDim.x) {
-    const int t = t0 + threadIdx.x;
-    const bool st = t < len && (t == 0 || rowof[t] != rowof[t - 1]);
-    const int c = st ? C[rowof[t]] : 0;
-    wave_peel_add_f64(S, c, st ? ksum[t] : 0.0, st);
-  }
+  // row sums -> Sigma of the row's community, merged per chunk (at most
+  // kChunk distinct communities in the 2 * kChunk-slot table)
+  for (int t = threadIdx.x; t < len; t += blockDim.x)
+    if ((t == 0 || rowof[t] != rowof[t - 1]) && ksum[t] != 0.0)
+      table_add(tk, tv, 2 * kChunk - 1, C[rowof[t]], ksum[t]);
+  block_merge_flush<2 * kChunk>(tk, tv, S);
 }
 
 void modularity_edges(const int64_t *off, const int32_t *idx, const float *w, const int32_t *crow,

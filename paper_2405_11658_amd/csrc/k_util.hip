@@ -81,17 +81,22 @@ void row_sums(const int64_t *off, const float *w, int64_t nrows, int64_t nnz, co
   if (nnz > 0) hipLaunchKernelGGL(k_row_sums, (int)ceil_div(nnz, kChunk), 256, 0, s, off, w, nnz, crow, K);
 }
 
-__global__ void k_scatter_add(const double *v, const int32_t *C, int64_t n, double *out) {
-  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n; i0 += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = i0 + threadIdx.x;
-    const bool act = i < n;
-    const int c = act ? C[i] : 0;
-    const double x = act ? v[i] : 0.0;
-    wave_peel_add_f64(out, c, x, act && x != 0.0);
+// out[C[i]] += v[i] (zero values skipped), merged per workgroup by key.
+constexpr int kScatterItems = 1024;
+__global__ __launch_bounds__(256) void k_scatter_add(const double *v, const int32_t *C, int64_t n, double *out) {
+  __shared__ int tk[2 * kScatterItems];
+  __shared__ double tv[2 * kScatterItems];
+  block_merge_clear<2 * kScatterItems>(tk, tv);
+  for (int64_t i0 = (int64_t)blockIdx.x * kScatterItems; i0 < n; i0 += (int64_t)gridDim.x * kScatterItems) {
+    for (int t = threadIdx.x; t < kScatterItems; t += blockDim.x) {
+      const int64_t i = i0 + t;
+      if (i < n && v[i] != 0.0) table_add(tk, tv, 2 * kScatterItems - 1, C[i], v[i]);
+    }
+    block_merge_flush<2 * kScatterItems>(tk, tv, out);
   }
 }
 void scatter_add(const double *v, const int32_t *C, int64_t n, double *out, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_scatter_add, flat_grid(n), 256, 0, s, v, C, n, out);
+  if (n > 0) hipLaunchKernelGGL(k_scatter_add, (int)std::min<int64_t>(ceil_div(n, kScatterItems), 2048), 256, 0, s, v, C, n, out);
 }
 
 __global__ void k_gather_map(int32_t *C, const int32_t *map, int64_t n) {
