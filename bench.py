@@ -19,6 +19,9 @@ modularity of the result (Eq. 1).  `value` is |E^t| / (wall time per step)
 over the timed steps; latencies p50/p99 come from HIP events inside the
 library and exclude the graph update, which the paper does not time
 (Sec. 5.1.4).  Static Leiden on the same graph is timed for the comparison.
+Modularity: the mean over the last five updates against the mean of
+--static-reps static runs on the final graph (both are asynchronous heuristics
+whose results vary from run to run by about 1e-3).
 
 roofline: the timed kernel (leiden_params.profile) with the largest share of
 the timed steps; achieved = algorithmic bytes / event-timed duration.
@@ -198,9 +201,17 @@ def main() -> int:
     entries = float(np.mean(ents))
     value = entries / (ms_per_step / 1e3)
 
-    # static Leiden on the final graph: modularity reference for the updates
-    _, q_static_final, st = L.leiden_static(h)
-    log(f"static on final graph: {st['ms_total']:.2f} ms Q={q_static_final:.6f}")
+    # static Leiden on the final graph: modularity reference for the updates.
+    # Both sides are asynchronous heuristics whose modularity varies from run
+    # to run by about 1e-3, so the comparison is of means: the last five
+    # updates against several static runs on the final graph.
+    q_static_final = []
+    for r in range(max(1, args.static_reps)):
+        _, q, st = L.leiden_static(h)
+        q_static_final.append(q)
+        log(f"static on final graph #{r}: {st['ms_total']:.2f} ms Q={q:.6f}")
+    q_upd_tail = float(np.mean(qs[-5:]))
+    q_stat_mean = float(np.mean(q_static_final))
 
     # roofline of the timed kernel with the largest total time
     dom = max(prof, key=lambda k: prof[k]["ms"])
@@ -270,8 +281,9 @@ def main() -> int:
         "updates_per_s": ratio(B * 1e3, pct(lat, 50)),
         "static_ms": {"p50": round(pct(static_ms_timed, 50), 3), "reps": len(static_ms_timed)},
         "speedup_vs_static": ratio(pct(static_ms_timed, 50), pct(lat, 50)),
-        "modularity": {"update_last": qs[-1], "static_final_graph": q_static_final,
-                       "dq_update_vs_static": qs[-1] - q_static_final,
+        "modularity": {"update_last": qs[-1], "update_last5_mean": q_upd_tail,
+                       "static_final_graph": q_static_final, "static_final_mean": q_stat_mean,
+                       "dq_update_vs_static": q_upd_tail - q_stat_mean,
                        "update_first": q_first, "oracle_update_first": q_oracle_first,
                        "dq_vs_oracle": (q_first - q_oracle_first) if q_oracle_first is not None else None,
                        "static_initial": q_static0},
