@@ -1,6 +1,7 @@
-"""GPU parity at the benchmark's full size: RMAT scale 22, edge factor 16
-(4,194,304 vertices, ~128M directed entries), in the configuration bench.py
-times (default asynchronous mode, DF updates of 1e-4 |E|).
+"""GPU parity at full size: RMAT scale 22, edge factor 16 (4,194,304
+vertices, ~128M directed entries) in the configuration bench.py times
+(default asynchronous mode, DF updates of 1e-4 |E|), and the road-like
+4096 x 4096 grid (16.8M vertices) with DF updates of 1e-5 and 1e-3 |E|.
 
 Everything the oracle can compute at this size in seconds is compared in
 full: modularity of the returned membership (relative 1e-9), the stored K,
@@ -42,9 +43,9 @@ def _state_checks(h, g, C, q):
     return C
 
 
-def test_rmat22_full_size():
-    g = gen.rmat(22, 16, seed=1)
-    say("rmat22 n", g.n, "entries", g.nnz)
+def _full_size(g, updates):
+    """Static run, aggregation of its membership, then the given (mode, fraction)
+    updates one after another, each checked against the oracle."""
     h = L.leiden_create(g.off, g.idx, g.w)
     C, q, st = L.leiden_static(h)
     say("static Q", q, "passes", st["passes"], "ms", round(st["ms_total"], 1))
@@ -59,12 +60,13 @@ def test_rmat22_full_size():
     assert np.array_equal(gi, ref.idx) and np.array_equal(gw, ref.w)
 
     cur = g
-    for k, mode in enumerate(("df", "ds")):
+    for k, (mode, frac) in enumerate(updates):
         _, K0, S0, m20 = L.leiden_get_state(h)
         C0 = to_np(L.leiden_get_state(h)[0])
-        b = gen.random_batch(cur, gen.batch_count(cur.nnz, 1e-4), seed=300 + k)
+        b = gen.random_batch(cur, gen.batch_count(cur.nnz, frac), seed=300 + k)
         say("update", mode, "batch", b.size)
         C, q, st, tr = L.leiden_update(h, dev_batch(b), mode, trace=True)
+        say(mode, "update ms", round(st["ms_total"], 1))
         gt, _ = oracle.apply_batch(og(cur), ob(b))
         off, idx, w = L.leiden_get_graph(h)
         assert np.array_equal(to_np(off), gt.off)
@@ -76,3 +78,18 @@ def test_rmat22_full_size():
         say(mode, "affected", int(dV.sum()), "changed", int(dC.sum()), "Q", q)
         cur = gen.CSR(gt.n, gt.off, gt.idx, gt.w)
         _state_checks(h, cur, C, q)
+
+
+def test_rmat22_full_size():
+    g = gen.rmat(22, 16, seed=1)
+    say("rmat22 n", g.n, "entries", g.nnz)
+    _full_size(g, [("df", 1e-4), ("ds", 1e-4)])
+
+
+def test_grid4096_full_size():
+    """Road-like graph: 4096 x 4096 grid, 5 % random diagonals, 2 % of the
+    edges dropped (16.8M vertices, ~69M entries, degree <= 8); DF updates of
+    1e-5 and 1e-3 |E|."""
+    g = gen.grid2d(4096, 0.05, 0.02, seed=1)
+    say("grid4096 n", g.n, "entries", g.nnz)
+    _full_size(g, [("df", 1e-5), ("df", 1e-3)])
