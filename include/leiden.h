@@ -243,9 +243,10 @@ leiden_status leiden_modularity(int64_t n, const int64_t *offsets, const int32_t
 /* Alg. "leidenAggregate" for a given membership with dense labels in
  * [0, ncomm): super-vertex CSR with, for each pair of communities, the FP64
  * sum of the weights rounded to float32.  out_offsets: ncomm+1 int64;
- * out_indices / out_weights: capacity nnz.  Rows are compacted; the order of
- * entries inside a row is unspecified.  *nnz_out (host) receives the number
- * of entries.  Stateless. */
+ * out_indices / out_weights: capacity nnz.  Rows are compacted and sorted by
+ * neighbour id; the sums are taken in a fixed order, so the result does not
+ * depend on scheduling.  *nnz_out (host) receives the number of entries.
+ * Stateless. */
 leiden_status leiden_aggregate(int64_t n, const int64_t *offsets, const int32_t *indices,
                                const float *weights, const int32_t *membership, int64_t ncomm,
                                int64_t *out_offsets, int32_t *out_indices, float *out_weights,

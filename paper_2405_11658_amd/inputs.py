@@ -196,6 +196,69 @@ def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c:
     return _symmetric_csr(nn, u, v)
 
 
+def rmat_device(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c: float = 0.19,
+                seed: int = 1, device: str = "cuda"):
+    """The R-MAT graph of ``rmat`` (same model, symmetrised, self-loops and
+    duplicates removed, unit weights, ids relabelled by a random permutation)
+    drawn and assembled on a torch device, for sizes whose host assembly would
+    take minutes (scale 26: ~1.9e9 directed entries).  Random numbers come from
+    a ``torch.Generator`` seeded with ``seed``, so the graph differs from
+    ``rmat``'s at the same seed.  Returns (n, off int64, idx int32, w float32)
+    as device tensors, rows sorted by neighbour id.
+
+    Assembly: the unique undirected keys a*n+b (a < b) are sorted once (the
+    rows' forward halves) and their mirrors b*n+a once more (backward halves);
+    every entry's CSR position is its row offset plus its rank inside its own
+    half of the row plus the number of entries of the other half of the row
+    that precede it, found by binary search in the other sorted half."""
+    import torch
+    dev = torch.device(device)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    N = 1 << scale
+    m = edge_factor * N
+    ab, abc = a + b, a + b + c
+    perm = torch.randperm(N, generator=gen, device=dev)
+    chunk = 1 << 26
+    keys = []
+    for s0 in range(0, m, chunk):
+        k = min(chunk, m - s0)
+        u = torch.zeros(k, dtype=torch.int64, device=dev)
+        v = torch.zeros(k, dtype=torch.int64, device=dev)
+        for _ in range(scale):
+            r = torch.rand(k, generator=gen, device=dev)
+            u = (u << 1) | (r >= ab).to(torch.int64)
+            v = (v << 1) | (((r >= a) & (r < ab)) | (r >= abc)).to(torch.int64)
+        u = perm[u]
+        v = perm[v]
+        keep = u != v
+        u, v = u[keep], v[keep]
+        keys.append(torch.minimum(u, v) * N + torch.maximum(u, v))
+        del u, v, r, keep
+    key1 = torch.unique(torch.cat(keys))          # sorted, a < b
+    del keys, perm
+    key2, _ = torch.sort((key1 % N) * N + key1 // N)
+    bounds = torch.arange(N + 1, dtype=torch.int64, device=dev) * N
+    h1 = torch.searchsorted(key1, bounds)
+    h2 = torch.searchsorted(key2, bounds)
+    deg = (h1[1:] - h1[:-1]) + (h2[1:] - h2[:-1])
+    off = torch.zeros(N + 1, dtype=torch.int64, device=dev)
+    off[1:] = torch.cumsum(deg, 0)
+    nnz = int(off[-1].item())
+    idx = torch.empty(nnz, dtype=torch.int32, device=dev)
+    for mine, other, hm, ho in ((key1, key2, h1, h2), (key2, key1, h2, h1)):
+        for s0 in range(0, mine.numel(), chunk):
+            k = mine[s0:s0 + chunk]
+            src = k // N
+            rank = torch.arange(s0, s0 + k.numel(), dtype=torch.int64, device=dev) - hm[src]
+            before = torch.searchsorted(other, k) - ho[src]
+            idx[off[src] + rank + before] = (k % N).to(torch.int32)
+            del k, src, rank, before
+    del key1, key2, h1, h2, bounds, deg
+    w = torch.ones(nnz, dtype=torch.float32, device=dev)
+    return N, off, idx, w
+
+
 def grid2d(side: int = 4096, p_diag: float = 0.05, p_drop: float = 0.02, seed: int = 1) -> CSR:
     """Road-like graph: side x side 4-neighbour grid, each of the 2*(side-1)^2
     diagonals added with p_diag, then every edge dropped with p_drop."""

@@ -322,7 +322,7 @@ def leiden_modularity(off, idx, w, membership) -> float:
 
 
 def leiden_aggregate(off, idx, w, membership, ncomm: int):
-    """Super-vertex CSR (rows compacted, entry order inside a row unspecified)."""
+    """Super-vertex CSR (rows compacted and sorted by neighbour id)."""
     lib = load()
     off = _dev(off, torch.int64)
     idx = _dev(idx, torch.int32)

@@ -8,8 +8,11 @@ full: modularity of the returned membership (relative 1e-9), the stored K,
 Sigma and 2m (exact, unit weights), the aggregated super-vertex CSR for the
 returned membership (exact after sorting each row), the graph after a batch
 (exact) and the DF and DS affected / in-range / changed flags (exact)."""
+import os
+
 import numpy as np
 import pytest
+import torch
 
 import oracle
 from paper_2405_11658_amd import inputs as gen
@@ -93,3 +96,101 @@ def test_grid4096_full_size():
     g = gen.grid2d(4096, 0.05, 0.02, seed=1)
     say("grid4096 n", g.n, "entries", g.nnz)
     _full_size(g, [("df", 1e-5), ("df", 1e-3)])
+
+
+@pytest.mark.skipif(os.environ.get("LEIDEN_RMAT26") != "1",
+                    reason="RMAT scale 26 (~1.9e9 entries, ~150 GB of HBM, ~60 GB of host memory, "
+                           "minutes): run with LEIDEN_RMAT26=1")
+def test_rmat26_full_size():
+    """Web/social-like RMAT scale 26, edge factor 16 (67M vertices, ~1.9e9
+    directed entries, hubs above 1e5), generated on the device.  Checked: the
+    aggregated CSR for a hashed membership of 65536 labels (computed before the
+    handle's own work buffers grow) by properties that hold at any size
+    (rows sorted, symmetry, row sums equal to the label totals, total weight,
+    modularity unchanged by aggregation) and 64 sampled rows recomputed from
+    the definition; the modularity of the static and DF results against the
+    oracle (relative 1e-9), K = degree, Sigma = its sum by community and 2m
+    (exact, unit weights); the graph after a DF batch of 1e-4 |E| (exact) and
+    the DF marks (exact)."""
+    n, off, idx, w = gen.rmat_device(26, 16, seed=1)
+    nnz = idx.numel()
+    say("rmat26 n", n, "entries", nnz)
+    h = L.leiden_create(off, idx, w)
+    g = gen.CSR(n, off.cpu().numpy(), idx.cpu().numpy(), w.cpu().numpy())
+    deg = np.diff(g.off).astype(np.float64)
+    say("graph on host")
+
+    ncomm = 65536
+    Ch = ((np.arange(n, dtype=np.uint64) * np.uint64(2654435761)) % np.uint64(ncomm)).astype(np.int32)
+    Ch_dev = torch.from_numpy(Ch).cuda()
+    aoff, aidx, aw = L.leiden_aggregate(off, idx, w, Ch_dev, ncomm)
+    del off, idx, w
+    torch.cuda.empty_cache()
+    na = aidx.numel()
+    say("aggregate: labels", ncomm, "entries", na)
+    rows = torch.repeat_interleave(torch.arange(ncomm, device="cuda"), aoff[1:] - aoff[:-1])
+    key = rows * ncomm + aidx.to(torch.int64)
+    assert bool((key[1:] > key[:-1]).all())              # rows sorted, no repeats
+    tkey, order = torch.sort(aidx.to(torch.int64) * ncomm + rows)
+    assert torch.equal(tkey, key) and torch.equal(aw[order], aw)   # symmetric
+    rsum = torch.zeros(ncomm, dtype=torch.float64, device="cuda").index_add_(0, rows, aw.to(torch.float64))
+    rsum = rsum.cpu().numpy()
+    lab = np.bincount(Ch, weights=deg, minlength=ncomm)
+    assert np.all(np.abs(rsum - lab) <= 1e-6 * lab + 1e-9)
+    assert abs(float(rsum.sum()) - float(nnz)) <= 1e-6 * nnz
+    qa = L.leiden_modularity(aoff, aidx, aw, torch.arange(ncomm, dtype=torch.int32, device="cuda"))
+    qh = oracle.modularity(og(g), Ch)
+    assert abs(qa - qh) <= 1e-6 * max(abs(qh), 1e-12), (qa, qh)
+    aoff_h, aidx_h, aw_h = aoff.cpu().numpy(), aidx.cpu().numpy(), aw.cpu().numpy()
+    del rows, key, tkey, order, aoff, aidx, aw, Ch_dev
+    torch.cuda.empty_cache()
+    members = np.argsort(Ch, kind="stable")
+    mstart = np.searchsorted(Ch[members], np.arange(ncomm + 1))
+    rng = np.random.default_rng(7)
+    for c in rng.choice(ncomm, 64, replace=False):
+        mem = members[mstart[c]:mstart[c + 1]]
+        lens = g.off[mem + 1] - g.off[mem]
+        ents = np.repeat(g.off[mem] - (np.cumsum(lens) - lens), lens) + np.arange(int(lens.sum()))
+        ids, inv = np.unique(Ch[g.idx[ents]], return_inverse=True)
+        sums = np.bincount(inv, weights=g.w[ents].astype(np.float64)).astype(np.float32)
+        lo, hi = aoff_h[c], aoff_h[c + 1]
+        assert np.array_equal(aidx_h[lo:hi], ids.astype(np.int32)) and np.array_equal(aw_h[lo:hi], sums)
+    del members, aoff_h, aidx_h, aw_h
+    say("aggregate checked")
+
+    C, q, st = L.leiden_static(h)
+    say("static Q", q, "passes", st["passes"], "ms", round(st["ms_total"], 1))
+    Cn = to_np(C)
+    qo = oracle.modularity(og(g), Cn)
+    assert abs(q - qo) <= 1e-9 * abs(qo), (q, qo)
+    _, K, S, m2 = L.leiden_get_state(h)
+    assert np.array_equal(to_np(K), deg)
+    assert np.array_equal(to_np(S), np.bincount(Cn, weights=deg, minlength=n))
+    assert m2 == float(nnz)
+    say("static checked")
+
+    b = gen.random_batch(g, gen.batch_count(nnz, 1e-4), seed=300)
+    say("df batch", b.size)
+    _, K0, S0, m20 = L.leiden_get_state(h)
+    C2, q2, st2, tr = L.leiden_update(h, dev_batch(b), "df", trace=True)
+    say("df update ms", round(st2["ms_total"], 1), "Q", q2)
+    gt, _ = oracle.apply_batch(og(g), ob(b))
+    del g
+    off2, idx2, w2 = L.leiden_get_graph(h)
+    assert np.array_equal(to_np(off2), gt.off)
+    assert np.array_equal(to_np(idx2), gt.idx) and np.array_equal(to_np(w2), gt.w)
+    del off2, idx2, w2
+    say("graph update checked")
+    dV, in_rng, dC = oracle.mark("df", gt, ob(b), Cn, to_np(K0), to_np(S0), m20)
+    assert np.array_equal(to_np(tr["affected"]), dV)
+    assert np.array_equal(to_np(tr["in_range"]), in_rng)
+    assert np.array_equal(to_np(tr["changed"]), dC)
+    C2n = to_np(C2)
+    qo2 = oracle.modularity(gt, C2n)
+    assert abs(q2 - qo2) <= 1e-9 * abs(qo2), (q2, qo2)
+    deg2 = np.diff(gt.off).astype(np.float64)
+    _, K2, S2, m22 = L.leiden_get_state(h)
+    assert np.array_equal(to_np(K2), deg2)
+    assert np.array_equal(to_np(S2), np.bincount(C2n, weights=deg2, minlength=n))
+    assert m22 == float(gt.off[-1])
+    say("df checked: affected", int(dV.sum()), "changed", int(dC.sum()))
