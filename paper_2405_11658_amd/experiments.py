@@ -12,7 +12,11 @@ method runs in the library's kernels).
   the first 90 % are loaded, and the rest arrive as consecutive insertion
   batches, each applied with each front-end.
 
-Run ``python -m paper_2405_11658_amd.experiments sweep|stream [options]``;
+* ``served``: a scaled form of the served batched workload (many resident
+  graphs, uneven batches), run as plain per-graph calls, through
+  ``leiden_update_many`` and through the server.
+
+Run ``python -m paper_2405_11658_amd.experiments sweep|stream|serve [options]``;
 each prints one JSON object per measurement.
 """
 from __future__ import annotations
@@ -105,6 +109,126 @@ def temporal_stream(scale: int = 20, edge_factor: int = 16, batches: int = 100, 
     print(json.dumps({"kind": "stream_static", "ms": st["ms_total"], "q": q}), file=out, flush=True)
 
 
+def served(graphs: int = 64, nmin: float = 1e3, nmax: float = 1e6, requests: int = 256, slots: int = 8,
+           seed: int = 1, out=sys.stdout):
+    """A scaled form of the served batched workload: `graphs` resident dynamic
+    graphs with vertex counts log-uniform in [nmin, nmax] (half R-MAT with edge
+    factor 8, half planted partitions of 64-vertex blocks), and `requests` DF
+    update requests, each on a uniformly chosen graph with a batch of
+    log-uniform 1e2..1e6 updates (80 % insertions) capped at 5 % of that
+    graph's edges; the requests of one graph apply in order.  The same
+    requests run three ways on the GPU, each from the same installed
+    memberships: one update after another on one stream (plain per-graph
+    calls); leiden_update_many over waves of distinct graphs; the server with
+    `slots` workers, all requests queued at once (continuous batching).  One
+    JSON line per form: updates per second of wall time, request latency
+    p50/p99 and the mean final modularity."""
+    L = _leiden()
+    import torch
+    rng = np.random.default_rng(seed)
+    gs = []
+    for k in range(graphs):
+        n = int(round(np.exp(rng.uniform(np.log(nmin), np.log(nmax)))))
+        if k % 2 == 0:
+            scale = max(1, int(np.ceil(np.log2(n))))
+            gs.append(gen.rmat(scale, 8, seed=seed + k, n=n))
+        else:
+            n = max(128, n // 64 * 64)
+            gs.append(gen.planted_partition(n, n // 64, 0.1, 2.0 / n, seed=seed + k, permute=True))
+    owner = rng.integers(0, graphs, requests)
+    per = np.bincount(owner, minlength=graphs)
+    streams = {}
+    for k in range(graphs):
+        if per[k] == 0:
+            continue
+        und = gs[k].nnz // 2
+        size = int(round(np.exp(rng.uniform(np.log(1e2), np.log(1e6)))))
+        size = max(1, min(size, und // 20 // max(1, per[k])))
+        streams[k] = [L.make_batch(b.del_u, b.del_v, b.ins_u, b.ins_v, b.ins_w)
+                      for b in gen.batch_stream(gs[k], size, int(per[k]), seed=seed + 100 + k)]
+    order = []
+    nxt = np.zeros(graphs, np.int64)
+    for r in range(requests):
+        k = int(owner[r])
+        order.append((k, streams[k][nxt[k]]))
+        nxt[k] += 1
+    total_updates = sum(int(b[0].numel() + b[2].numel()) for _, b in order)
+    entries = sum(g.nnz for g in gs)
+    print(json.dumps({"kind": "serve_setup", "graphs": graphs, "requests": requests, "entries": int(entries),
+                      "updates": total_updates}), file=out, flush=True)
+
+    base = []
+    for g in gs:
+        h = L.leiden_create(g.off, g.idx, g.w)
+        C, _, _ = L.leiden_static(h, want_q=False)
+        base.append(C.clone())
+        del h
+
+    def fresh():
+        hs = [L.leiden_create(g.off, g.idx, g.w) for g in gs]
+        for h, C in zip(hs, base):
+            L.leiden_set_state(h, C)
+        torch.cuda.synchronize()
+        return hs
+
+    def report(form, wall, lats, hs):
+        qs = [L.leiden_modularity(*L.leiden_get_graph(h), L.leiden_get_state(h)[0]) for h in hs]
+        print(json.dumps({"kind": "serve", "form": form, "wall_s": round(wall, 3),
+                          "updates_per_s": total_updates / wall, "requests_per_s": requests / wall,
+                          "latency_p50_ms": float(np.percentile(lats, 50)),
+                          "latency_p99_ms": float(np.percentile(lats, 99)),
+                          "q_mean": float(np.mean(qs))}), file=out, flush=True)
+
+    # plain per-graph calls, one after another (latency: from the start, as if
+    # all requests were queued at time 0)
+    hs = fresh()
+    t0 = time.perf_counter()
+    lats = []
+    for k, b in order:
+        L.leiden_update(hs[k], b, "df")
+        lats.append((time.perf_counter() - t0) * 1e3)
+    wall = time.perf_counter() - t0
+    report("sequential", wall, lats, hs)
+    del hs
+
+    # waves of distinct graphs through leiden_update_many
+    hs = fresh()
+    t0 = time.perf_counter()
+    lats = []
+    wave, seen = [], set()
+    def flush():
+        if wave:
+            res = L.leiden_update_many([hs[k] for k, _ in wave], [b for _, b in wave], ["df"] * len(wave),
+                                       max_parallel=slots)
+            assert all(r[3] == 0 for r in res)
+            lats.extend([(time.perf_counter() - t0) * 1e3] * len(wave))
+            wave.clear()
+            seen.clear()
+    for k, b in order:
+        if k in seen:
+            flush()
+        wave.append((k, b))
+        seen.add(k)
+    flush()
+    wall = time.perf_counter() - t0
+    report("update_many", wall, lats, hs)
+    del hs
+
+    # the server: every request queued at once
+    hs = fresh()
+    sv = L.Server(slots=slots)
+    t0 = time.perf_counter()
+    ids = [sv.submit(hs[k], b, "df") for k, b in order]
+    lats = []
+    for rid in ids:
+        st, _, _, _, lat, _ = sv.wait(rid)
+        assert st == 0
+        lats.append(lat)
+    wall = time.perf_counter() - t0
+    sv.close()
+    report("server", wall, lats, hs)
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -118,12 +242,19 @@ def main(argv=None) -> int:
     t.add_argument("--edge-factor", type=int, default=16)
     t.add_argument("--batches", type=int, default=100)
     t.add_argument("--frac", type=float, default=1e-4)
+    v = sub.add_parser("serve")
+    v.add_argument("--graphs", type=int, default=64)
+    v.add_argument("--nmax", type=float, default=1e6)
+    v.add_argument("--requests", type=int, default=256)
+    v.add_argument("--slots", type=int, default=8)
     a = ap.parse_args(argv)
     t0 = time.time()
     if a.cmd == "sweep":
         batch_sweep(a.scale, a.edge_factor, tuple(a.fracs), a.reps)
-    else:
+    elif a.cmd == "stream":
         temporal_stream(a.scale, a.edge_factor, a.batches, a.frac)
+    else:
+        served(a.graphs, 1e3, a.nmax, a.requests, a.slots)
     print(json.dumps({"kind": "done", "seconds": round(time.time() - t0, 1)}), flush=True)
     return 0
 
