@@ -1,0 +1,33 @@
+"""Host tests of the seeded input generators (no GPU): the R-MAT graph
+assembled with torch (used for the RMAT-26 run, there on the device) is run
+on the CPU at small scales and must be a valid undirected CSR with the same
+statistics as the numpy generator's."""
+import numpy as np
+import pytest
+
+from paper_2405_11658_amd import inputs as gen
+
+
+@pytest.mark.parametrize("scale", [6, 10, 13])
+def test_rmat_device_on_cpu_is_a_valid_csr(scale):
+    n, off, idx, w = gen.rmat_device(scale, 16, seed=3, device="cpu")
+    off, idx, w = off.numpy(), idx.numpy(), w.numpy()
+    assert n == 1 << scale and off[0] == 0 and off[-1] == len(idx) == len(w)
+    deg = np.diff(off)
+    rows = np.repeat(np.arange(n, dtype=np.int64), deg)
+    key = rows * n + idx
+    assert (np.diff(key) > 0).all()                       # rows sorted, no repeated entries
+    assert (rows != idx).all()                            # no self-loops
+    assert np.array_equal(np.sort(idx.astype(np.int64) * n + rows), key)   # symmetric
+    assert (w == 1.0).all()
+    ref = gen.rmat(scale, 16, seed=3)
+    assert abs(len(idx) - ref.nnz) <= 0.05 * ref.nnz      # same model: entry counts agree closely
+    assert abs(deg.max() - np.diff(ref.off).max()) <= 0.35 * np.diff(ref.off).max()
+
+
+def test_rmat_device_is_seeded():
+    a = gen.rmat_device(9, 8, seed=5, device="cpu")
+    b = gen.rmat_device(9, 8, seed=5, device="cpu")
+    c = gen.rmat_device(9, 8, seed=6, device="cpu")
+    assert all(np.array_equal(x.numpy(), y.numpy()) for x, y in zip(a[1:], b[1:]))
+    assert not np.array_equal(a[2].numpy(), c[2].numpy())
