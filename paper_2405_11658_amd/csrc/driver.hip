@@ -37,7 +37,7 @@ enum Slot {
   // level graphs (ping-pong)
   G0_off, G0_idx, G0_w, G0_crow, G1_off, G1_idx, G1_w, G1_crow,
   // aggregation
-  A_keys, A_skeys, A_vals, A_svals, A_ukeys, A_sums, A_rowlen,
+  A_keys, A_skeys, A_vals, A_svals, A_ukeys, A_sums, A_rowlen, A_flag, A_cmap, A_inv, A_cc,
   // hubs
   H_v, H_cnt, H_ch, H_tab, H_sg, H_chub, H_shub, H_tk, H_tv, H_own, H_pg, H_pc, H_soff,
   H_fill, H_bnd, H_flag, L_act, W_keys, W_vals, W_list,
@@ -119,6 +119,7 @@ constexpr int kMaxAsyncWaves = 65536;
 constexpr int64_t kVertsPerWave = 1024;  // level-0 vertices with edges per sweeping wavefront, at least
 constexpr int64_t kVertsPerWaveUpper = 256;  // the same for the aggregated levels
 constexpr int kStallIters = 3;  // see the iteration loop of run_core
+constexpr int64_t kAggRelabelMin = 1 << 20;  // level entries from which aggregation relabels communities
 
 // Wavefronts of an asynchronous sweep over a level with n vertices that have
 // edges: at most `cap`, and few enough that the vertices in flight stay a
@@ -508,6 +509,25 @@ Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, i
   int64_t nu = 0;
   unsigned long long *ukeys = nullptr;
   double *sums = nullptr;
+  // large levels: keys over a dense relabelling of the communities that own
+  // entries (fewer key bits, fewer radix passes)
+  int64_t nk = ncomm;
+  const int32_t *inv = nullptr;
+  if (g.nnz >= kAggRelabelMin) {
+    int32_t *flag = x.get<int32_t>(A_flag, ncomm + 1);
+    int32_t *cmap = x.get<int32_t>(A_cmap, ncomm + 1);
+    int32_t *Cc = x.get<int32_t>(A_cc, g.n);
+    x.zero(flag, ncomm + 1);
+    agg_flag(g.n, g.off, C, flag, x.s);
+    scan_i32(x, flag, cmap, ncomm + 1);
+    nk = x.read(&cmap[ncomm]);
+    int32_t *invp = x.get<int32_t>(A_inv, nk);
+    agg_inv(ncomm, flag, cmap, invp, x.s);
+    agg_relabel(g.n, g.off, C, cmap, Cc, x.s);
+    a.C = Cc;
+    a.ncomm = nk;
+    inv = invp;
+  }
   if (g.nnz > 0) {
     unsigned long long *keys = x.get<unsigned long long>(A_keys, g.nnz);
     unsigned long long *skeys = x.get<unsigned long long>(A_skeys, g.nnz);
@@ -516,7 +536,7 @@ Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, i
     ukeys = x.get<unsigned long long>(A_ukeys, g.nnz);
     sums = x.get<double>(A_sums, g.nnz);
     DevScal *scl = x.scal();
-    const unsigned long long top = (unsigned long long)ncomm * (unsigned long long)ncomm - 1ull;
+    const unsigned long long top = (unsigned long long)nk * (unsigned long long)nk - 1ull;
     int end_bit = 1;
     while (end_bit < 64 && (top >> end_bit) != 0) ++end_bit;
     size_t tb = sort_pairs_u64_f32(nullptr, 0, keys, skeys, vals, svals, g.nnz, end_bit, x.s);
@@ -533,7 +553,7 @@ Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, i
   int32_t *out_idx = x.get<int32_t>(si, nu);
   float *out_w = x.get<float>(sw, nu);
   if (Kout) x.zero(Kout, ncomm);
-  agg_rows(ukeys, sums, nu, ncomm, out_idx, out_w, rowlen, Kout, x.s);
+  agg_rows(ukeys, sums, nu, nk, inv, out_idx, out_w, rowlen, Kout, x.s);
   scan_i32_i64(x, rowlen, out_off, ncomm + 1);
   int32_t *out_crow = x.get<int32_t>(sc, ceil_div(std::max<int64_t>(nu, 1), kChunk) + 2);
   chunk_start_rows(out_off, ncomm, nu, out_crow, x.s);
@@ -670,6 +690,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
         move_apply(ma, B.region.data(), x.s);
       }
       if (async) {
+        // after the hubs: the other vertices then see the hubs' new communities
         hipEvent_t t0 = x.kp ? x.kp->begin() : nullptr;
         move_async(ma, level_waves(NW, alen, pass), wide_tables(g.nnz, alen), x.s);
         if (x.kp) x.kp->end(t0, LEIDEN_PROF_MOVE_SWEEP, 0, 0);

@@ -232,8 +232,12 @@ struct AggArgs {
   const int32_t *C;
 };
 void agg_keys(const AggArgs &a, const int32_t *crow, unsigned long long *keys, float *vals, hipStream_t s);
-void agg_rows(const unsigned long long *ukeys, const double *sums, int64_t nu, int64_t ncomm, int32_t *out_idx,
-              float *out_w, int32_t *rowlen, double *K, hipStream_t s);  // K nullable, zeroed by the caller
+void agg_flag(int64_t n, const int64_t *off, const int32_t *C, int32_t *flag, hipStream_t s);
+void agg_relabel(int64_t n, const int64_t *off, const int32_t *C, const int32_t *cmap, int32_t *Cc, hipStream_t s);
+void agg_inv(int64_t ncomm, const int32_t *flag, const int32_t *cmap, int32_t *inv, hipStream_t s);
+// inv nullable (keys over the original labels); K nullable, zeroed by the caller
+void agg_rows(const unsigned long long *ukeys, const double *sums, int64_t nu, int64_t ncomm, const int32_t *inv,
+              int32_t *out_idx, float *out_w, int32_t *rowlen, double *K, hipStream_t s);
 
 // ---- k_modularity.hip --------------------------------------------------------
 // acc[0] += sigma total, S[c] += K-contributions (S zeroed, ncomm = n)
