@@ -252,8 +252,12 @@ __global__ __launch_bounds__(BLOCK) void k_propose_team(MoveArgs a, int b) {
 // hub's own community into `own`).
 __global__ __launch_bounds__(256) void k_hub_gather(MoveArgs a) {
   constexpr int T = 2 * kHubEC;
+  constexpr int PER = kHubEC / 256;  // edges per thread
+  static_assert(kHubEC % 256 == 0, "edge chunk must be a multiple of the workgroup size");
   __shared__ int keys[T];
   __shared__ double vals[T];
+  __shared__ int used[kHubEC];  // slots taken (at most one per edge)
+  __shared__ int nused;
   const int64_t q = a.qbeg + blockIdx.x;
   const int h = a.hp.chub[q];
   const int i = a.hp.hubv[h];
@@ -262,20 +266,45 @@ __global__ __launch_bounds__(256) void k_hub_gather(MoveArgs a) {
   const int64_t e1 = min(e0 + (int64_t)kHubEC, a.off[i + 1]);
   if (a.hub_scanned && threadIdx.x == 0) atomicAdd(a.hub_scanned, (unsigned long long)(e1 - e0));
   for (int s = threadIdx.x; s < T; s += blockDim.x) { keys[s] = kEmpty; vals[s] = 0.0; }
+  if (threadIdx.x == 0) nused = 0;
+  // this thread's edges: all ids first, then all communities
+  int j[PER], c[PER];
+  float x[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int64_t e = e0 + threadIdx.x + u * 256;
+    j[u] = i;
+    x[u] = 0.0f;
+    if (e < e1) { j[u] = a.idx[e]; x[u] = a.w[e]; }
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) c[u] = j[u] != i ? a.C[j[u]] : kEmpty;
   __syncthreads();
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-    const int j = a.idx[e];
-    if (j != i) table_add(keys, vals, T - 1, a.C[j], (double)a.w[e]);
+#pragma unroll
+  for (int u = 0; u < PER; ++u)
+    if (c[u] != kEmpty) table_add(keys, vals, T - 1, c[u], (double)x[u]);
+  __syncthreads();
+  // list the taken slots, so that the merge into the hub's global table is
+  // spread evenly over the threads
+  for (int s0 = 0; s0 < T; s0 += blockDim.x) {
+    const int s = s0 + threadIdx.x;
+    const bool taken = keys[s] != kEmpty;
+    const unsigned long long m = __ballot(taken);
+    int base = 0;
+    if (lane() == 0 && m) base = atomicAdd(&nused, (int)__popcll(m));
+    base = __shfl(base, 0);
+    if (taken) used[base + (int)__popcll(m & ((1ull << lane()) - 1ull))] = s;
   }
   __syncthreads();
+  const int nu = nused;
   const int d = a.C[i];
   const int64_t t0 = a.hp.htab[h];
   const uint32_t mask = (uint32_t)(a.hp.htab[h + 1] - t0 - 1);
-  for (int s = threadIdx.x; s < T; s += blockDim.x) {
-    const int c = keys[s];
-    if (c == kEmpty) continue;
-    if (c == d) unsafeAtomicAdd(&a.hp.own[h], vals[s]);
-    else table_add(a.hp.keys + t0, a.hp.vals + t0, mask, c, vals[s]);
+  for (int k = threadIdx.x; k < nu; k += blockDim.x) {
+    const int s = used[k];
+    const int cs = keys[s];
+    if (cs == d) unsafeAtomicAdd(&a.hp.own[h], vals[s]);
+    else table_add(a.hp.keys + t0, a.hp.vals + t0, mask, cs, vals[s]);
   }
 }
 

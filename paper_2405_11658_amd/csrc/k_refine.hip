@@ -245,8 +245,12 @@ __global__ void k_rhub_frontier(RefineArgs a) {
 
 __global__ __launch_bounds__(256) void k_rhub_gather(RefineArgs a) {
   constexpr int T = 2 * kHubEC;
+  constexpr int PER = kHubEC / 256;  // edges per thread
+  static_assert(kHubEC % 256 == 0, "edge chunk must be a multiple of the workgroup size");
   __shared__ int keys[T];
   __shared__ double vals[T];
+  __shared__ int used[kHubEC];  // slots taken (at most one per edge)
+  __shared__ int nused;
   const int64_t q = a.qbeg + blockIdx.x;
   const int h = a.hp.chub[q];
   const int i = a.hp.hubv[h];
@@ -255,19 +259,50 @@ __global__ __launch_bounds__(256) void k_rhub_gather(RefineArgs a) {
   const int64_t e1 = min(e0 + (int64_t)kHubEC, a.off[i + 1]);
   const int cbi = a.CB[i];
   for (int s = threadIdx.x; s < T; s += blockDim.x) { keys[s] = kEmpty; vals[s] = 0.0; }
-  __syncthreads();
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-    const int j = a.idx[e];
-    if (j != i && a.CB[j] == cbi) table_add(keys, vals, T - 1, a.C[j], (double)a.w[e]);
+  if (threadIdx.x == 0) nused = 0;
+  // this thread's edges: all ids first, then communities and bounds together
+  int j[PER], c[PER];
+  float x[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int64_t e = e0 + threadIdx.x + u * 256;
+    j[u] = i;
+    x[u] = 0.0f;
+    if (e < e1) { j[u] = a.idx[e]; x[u] = a.w[e]; }
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    c[u] = kEmpty;
+    if (j[u] != i) {
+      const int cj = a.C[j[u]];
+      if (a.CB[j[u]] == cbi) c[u] = cj;
+    }
   }
   __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u)
+    if (c[u] != kEmpty) table_add(keys, vals, T - 1, c[u], (double)x[u]);
+  __syncthreads();
+  // list the taken slots, so that the merge into the hub's global table is
+  // spread evenly over the threads
+  for (int s0 = 0; s0 < T; s0 += blockDim.x) {
+    const int s = s0 + threadIdx.x;
+    const bool taken = keys[s] != kEmpty;
+    const unsigned long long m = __ballot(taken);
+    int base = 0;
+    if (lane() == 0 && m) base = atomicAdd(&nused, (int)__popcll(m));
+    base = __shfl(base, 0);
+    if (taken) used[base + (int)__popcll(m & ((1ull << lane()) - 1ull))] = s;
+  }
+  __syncthreads();
+  const int nu = nused;
   const int64_t t0 = a.hp.htab[h];
   const uint32_t mask = (uint32_t)(a.hp.htab[h + 1] - t0 - 1);
-  for (int s = threadIdx.x; s < T; s += blockDim.x) {
-    const int c = keys[s];
-    if (c == kEmpty) continue;
-    if (c == i) unsafeAtomicAdd(&a.hp.own[h], vals[s]);
-    else table_add(a.hp.keys + t0, a.hp.vals + t0, mask, c, vals[s]);
+  for (int k = threadIdx.x; k < nu; k += blockDim.x) {
+    const int s = used[k];
+    const int cs = keys[s];
+    if (cs == i) unsafeAtomicAdd(&a.hp.own[h], vals[s]);
+    else table_add(a.hp.keys + t0, a.hp.vals + t0, mask, cs, vals[s]);
   }
 }
 
