@@ -3,6 +3,7 @@
 Synchronous mode makes every update deterministic, so a result computed in
 the mix must equal the same update run alone, element by element."""
 import numpy as np
+import torch
 import pytest
 
 from paper_2405_11658_amd import inputs as gen
@@ -50,3 +51,28 @@ def test_server_results_equal_alone(slots, budget):
             assert np.array_equal(to_np(Cs), to_np(C)), (k, r)
             assert abs(qs - q) <= 1e-12 * abs(q)  # modularity sums with atomics: last bits vary
             assert latency >= service > 0.0
+
+
+def test_autotune_keeps_state_and_installs_a_candidate():
+    """autotune() times candidate sweep/hub settings on scratch copies: the
+    handle's graph and membership are unchanged, the chosen setting is one of
+    the candidates and within the modularity tolerance of the best, and the
+    handle then updates normally."""
+    from paper_2405_11658_amd.autotune import autotune
+    g = gen.rmat(14, 8, seed=11)
+    h = L.leiden_create(g.off, g.idx, g.w)
+    L.leiden_static(h)
+    off0, idx0, w0 = [t.clone() for t in L.leiden_get_graph(h)]
+    C0 = L.leiden_get_state(h)[0].clone()
+    bs = gen.batch_stream(g, gen.batch_count(g.nnz, 1e-3), 3, seed=5)
+    warm, sample, _ = [L.make_batch(b.del_u, b.del_v, b.ins_u, b.ins_v, b.ins_w) for b in bs]
+    p, res = autotune(h, warm, sample, waves=(64, 256), slices=(8, 16))
+    say("autotune results", res, "chose", p.async_waves, p.nslices)
+    assert len(res) == 4 and (p.async_waves, p.nslices) in [(r[0], r[1]) for r in res]
+    qbest = max(r[3] for r in res)
+    assert [r for r in res if (r[0], r[1]) == (p.async_waves, p.nslices)][0][3] >= qbest - 5e-4
+    off1, idx1, w1 = L.leiden_get_graph(h)
+    assert torch.equal(off0, off1) and torch.equal(idx0, idx1) and torch.equal(w0, w1)
+    assert torch.equal(C0, L.leiden_get_state(h)[0])
+    _, q, st, _ = L.leiden_update(h, warm, "df")
+    assert q > 0.0
