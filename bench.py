@@ -274,7 +274,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"rmat{args.scale}_ef{args.edge_factor}_{args.mode}_f{args.frac:g}",
                    "n": g.n, "entries": int(g.nnz), "batch_updates": B, "mode": args.mode,
-                   "nslices": 16},
+                   "hub_slices": 64},
         "latency_ms": {"p50": round(pct(lat, 50), 3), "p99": round(pct(lat, 99), 3),
                        "mean": round(float(np.mean(lat)), 3)},
         "latency_with_graph_update_ms": {"p50": round(pct(lat_all, 50), 3), "p99": round(pct(lat_all, 99), 3)},

@@ -65,7 +65,8 @@ typedef enum { LEIDEN_ND = 1, LEIDEN_DS = 2, LEIDEN_DF = 3 } leiden_mode;
  * the vertices in ascending id order and apply each move at once; results
  * depend on timing.
  * Vertices of degree > 2048 are moved before each sweep, synchronously within
- * each of nslices hash-ordered slices.  sync_mode = 1: deterministic test
+ * each of hub_slices hash-ordered slices (0 = 64; more slices move fewer hubs
+ * at once).  sync_mode = 1: deterministic test
  * mode - every vertex is swept in nslices hash-ordered slices (default 16),
  * the slices in order, the vertices of a slice synchronously, the gain summed
  * in a fixed order; results are bit-identical to the CPU oracle's synchronous
@@ -81,9 +82,10 @@ typedef struct {
   int32_t max_passes;
   int32_t sync_mode;
   int32_t refine_variant;
-  int32_t nslices; /* 1 .. 256 */
+  int32_t nslices; /* 1 .. 256, synchronous mode */
   int32_t profile; /* 0 or 1 */
   int32_t async_waves; /* 0 .. 65536, rounded up to a multiple of 4 */
+  int32_t hub_slices;  /* 0 .. 256, asynchronous mode only */
 } leiden_params;
 
 #define LEIDEN_MAX_PASSES 64

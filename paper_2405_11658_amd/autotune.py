@@ -3,7 +3,7 @@ step of the method runs in the library).
 
 ``autotune(h, batch)`` tries candidate settings of the asynchronous sweep's
 wavefront cap (``async_waves``: how many vertices are in flight) and of the
-number of hub slices (``nslices``) on scratch copies of the handle's current
+number of hub slices (``hub_slices``) on scratch copies of the handle's current
 graph and membership: each candidate applies two sample batches one after
 the other (``warm``, which sizes the scratch handle's work buffers, then
 ``batch``, valid after it, as ``inputs.batch_stream`` draws them) with the
@@ -18,7 +18,7 @@ import itertools
 from . import leiden as L
 
 DEFAULT_WAVES = (512, 1024, 2048, 4096)
-DEFAULT_SLICES = (8, 16, 32)
+DEFAULT_SLICES = (16, 32, 64)
 
 
 def _scratch(off, idx, w, C, params):
@@ -29,7 +29,7 @@ def _scratch(off, idx, w, C, params):
 
 def autotune(h: L.Handle, warm, batch, mode: str = "df", waves=DEFAULT_WAVES, slices=DEFAULT_SLICES,
              q_tol: float = 5e-4, base: L.leiden_params | None = None):
-    """Returns (chosen params, list of (async_waves, nslices, ms, q) per candidate)."""
+    """Returns (chosen params, list of (async_waves, hub_slices, ms, q) per candidate)."""
     off, idx, w = L.leiden_get_graph(h)
     C = L.leiden_get_state(h)[0].clone()
     base = base or L.leiden_default_params()
@@ -37,7 +37,7 @@ def autotune(h: L.Handle, warm, batch, mode: str = "df", waves=DEFAULT_WAVES, sl
     for aw, ns in itertools.product(waves, slices):
         p = L.leiden_params.from_buffer_copy(base)
         p.async_waves = aw
-        p.nslices = ns
+        p.hub_slices = ns
         s = _scratch(off, idx, w, C, p)
         L.leiden_update(s, warm, mode, want_q=False)
         _, q, st, _ = L.leiden_update(s, batch, mode)
@@ -48,6 +48,6 @@ def autotune(h: L.Handle, warm, batch, mode: str = "df", waves=DEFAULT_WAVES, sl
     aw, ns, _, _ = min(ok, key=lambda r: r[2])
     chosen = L.leiden_params.from_buffer_copy(base)
     chosen.async_waves = aw
-    chosen.nslices = ns
+    chosen.hub_slices = ns
     L.leiden_set_params(h, chosen)
     return chosen, results

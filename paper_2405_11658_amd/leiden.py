@@ -40,7 +40,8 @@ class leiden_params(ct.Structure):
     _fields_ = [("tau0", ct.c_double), ("tol_drop", ct.c_double), ("agg_tol", ct.c_double),
                 ("max_iter", ct.c_int32), ("max_passes", ct.c_int32),
                 ("sync_mode", ct.c_int32), ("refine_variant", ct.c_int32), ("nslices", ct.c_int32),
-                ("profile", ct.c_int32), ("async_waves", ct.c_int32)]
+                ("profile", ct.c_int32), ("async_waves", ct.c_int32),
+                ("hub_slices", ct.c_int32)]
 
 
 class leiden_stats(ct.Structure):

@@ -67,10 +67,10 @@ def test_autotune_keeps_state_and_installs_a_candidate():
     bs = gen.batch_stream(g, gen.batch_count(g.nnz, 1e-3), 3, seed=5)
     warm, sample, _ = [L.make_batch(b.del_u, b.del_v, b.ins_u, b.ins_v, b.ins_w) for b in bs]
     p, res = autotune(h, warm, sample, waves=(64, 256), slices=(8, 16))
-    say("autotune results", res, "chose", p.async_waves, p.nslices)
-    assert len(res) == 4 and (p.async_waves, p.nslices) in [(r[0], r[1]) for r in res]
+    say("autotune results", res, "chose", p.async_waves, p.hub_slices)
+    assert len(res) == 4 and (p.async_waves, p.hub_slices) in [(r[0], r[1]) for r in res]
     qbest = max(r[3] for r in res)
-    assert [r for r in res if (r[0], r[1]) == (p.async_waves, p.nslices)][0][3] >= qbest - 5e-4
+    assert [r for r in res if (r[0], r[1]) == (p.async_waves, p.hub_slices)][0][3] >= qbest - 5e-4
     off1, idx1, w1 = L.leiden_get_graph(h)
     assert torch.equal(off0, off1) and torch.equal(idx0, idx1) and torch.equal(w0, w1)
     assert torch.equal(C0, L.leiden_get_state(h)[0])
