@@ -194,3 +194,31 @@ def test_rmat26_full_size():
     assert np.array_equal(to_np(S2), np.bincount(C2n, weights=deg2, minlength=n))
     assert m22 == float(gt.off[-1])
     say("df checked: affected", int(dV.sum()), "changed", int(dC.sum()))
+
+
+@pytest.mark.skipif(os.environ.get("LEIDEN_QUALITY") != "1",
+                    reason="five serial oracle DF updates on RMAT-22 (~90 s of host time): run with LEIDEN_QUALITY=1")
+def test_rmat22_df_quality_vs_oracle_from_same_state():
+    """The default asynchronous DF update against the serial oracle's DF
+    update, both started from the oracle's static membership, on five
+    batches of 1e-4 |E|: the mean modularity gap must be within 1e-3 and no
+    batch more than 2e-3 below (the two are different orders of the same
+    heuristic; the gate is on their modularity)."""
+    g = gen.rmat(22, 16, seed=1)
+    ost, _ = oracle.static(og(g), oracle.make_params())
+    say("oracle static Q", oracle.modularity(og(g), ost.C))
+    C0 = torch.from_numpy(np.ascontiguousarray(ost.C)).cuda()
+    gaps = []
+    for k in range(5):
+        b = gen.random_batch(g, gen.batch_count(g.nnz, 1e-4), seed=700 + k)
+        h = L.leiden_create(g.off, g.idx, g.w)
+        L.leiden_set_state(h, C0)
+        _, q, _, _ = L.leiden_update(h, dev_batch(b), "df")
+        del h
+        o2, _, _, _ = oracle.update(ost, ob(b), "df", oracle.make_params())
+        qo = oracle.modularity(o2.g, o2.C)
+        gaps.append(q - qo)
+        say("batch", k, "Q", q, "oracle", qo, "gap", q - qo)
+    gaps = np.array(gaps)
+    assert gaps.mean() >= -1e-3, gaps
+    assert gaps.min() >= -2e-3, gaps
