@@ -655,6 +655,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     ma.gain = gi ? nullptr : &sc->gain; ma.moves = &sc->moves;
     ma.hp = hh.p;
     ma.act = hh.nhub > 0 ? act : nullptr;
+    ma.hub_front = async ? 1 : 0;
     ma.hub_scanned = x.kp && x.kp->on ? &sc->hub_scanned : nullptr;
     ma.sweep_work = x.kp && x.kp->on ? sc->sweep_work : nullptr;
     ma.anext = &sc->anext; ma.akeys = akeys; ma.avals = avals;
@@ -677,7 +678,6 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
         if (async) {
           // hubs: synchronous among the hubs of the slice; the rest below
           if (ma.hend == ma.hbeg) continue;
-          move_hub_frontier(ma, x.s);
           hipEvent_t t0 = x.kp ? x.kp->begin() : nullptr;
           move_hub_gather(ma, x.s);
           if (x.kp) x.kp->end(t0, LEIDEN_PROF_HUB_GATHER, 0, 0);

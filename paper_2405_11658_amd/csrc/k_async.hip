@@ -470,24 +470,5 @@ void edge_list(const int64_t *off, int64_t n, const int32_t *pos, int32_t *list,
   if (n > 0) hipLaunchKernelGGL(k_edge_list, flat_grid(n), 256, 0, s, off, n, pos, list);
 }
 
-// Hubs of slice a.s enter the frontier: processed flag cleared, proposal
-// reset, in-range ones listed in bucket kNB-1 of the slice and flagged act.
-__global__ void k_hub_frontier(MoveArgs a) {
-  int32_t *cnt = a.counts + a.s * kNB + (kNB - 1);
-  int32_t *list = a.lists + a.region[a.s * kNB + (kNB - 1)];
-  for (int64_t h = a.hbeg + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < a.hend;
-       h += (int64_t)gridDim.x * blockDim.x) {
-    const int i = a.hp.hubv[h];
-    a.prop[i] = -1;
-    const bool go = a.U[i] && a.rng[i];
-    a.U[i] = 0;
-    a.act[i] = go;
-    if (go) list[atomicAdd(cnt, 1)] = i;
-  }
-}
-void move_hub_frontier(const MoveArgs &a, hipStream_t s) {
-  if (a.hend > a.hbeg) hipLaunchKernelGGL(k_hub_frontier, flat_grid(a.hend - a.hbeg), 256, 0, s, a);
-}
-
 }  // namespace lk
 

@@ -261,7 +261,20 @@ __global__ __launch_bounds__(256) void k_hub_gather(MoveArgs a) {
   const int64_t q = a.qbeg + blockIdx.x;
   const int h = a.hp.chub[q];
   const int i = a.hp.hubv[h];
-  if (!a.act[i]) return;
+  if (a.hub_front) {
+    // The hub enters the frontier of its slice: every chunk takes the same
+    // decision from the processed flag, which k_hub_rev clears; the first
+    // chunk records it and resets the proposal.
+    const bool go = a.U[i] && a.rng[i];
+    if (q == a.hp.hch[h] && threadIdx.x == 0) {
+      a.prop[i] = -1;
+      a.act[i] = go;
+      if (go) a.lists[a.region[a.s * kNB + (kNB - 1)] + atomicAdd(a.counts + a.s * kNB + (kNB - 1), 1)] = i;
+    }
+    if (!go) return;
+  } else if (!a.act[i]) {
+    return;
+  }
   const int64_t e0 = a.off[i] + (q - a.hp.hch[h]) * kHubEC;
   const int64_t e1 = min(e0 + (int64_t)kHubEC, a.off[i + 1]);
   if (a.hub_scanned && threadIdx.x == 0) atomicAdd(a.hub_scanned, (unsigned long long)(e1 - e0));
@@ -599,13 +612,15 @@ void move_apply_bucket(const MoveArgs &a, const int64_t *region_h, int b, hipStr
 // ---- apply for hubs, chunk-parallel --------------------------------------------
 // The same rule as the other buckets, with the hub's edge chunks spread over
 // workgroups: (1) a chunk that finds a same-slice neighbour proposing the
-// exact reverse move with priority flags the hub blocked; (2) one thread per
-// hub moves it or leaves it unprocessed; (3) the chunks of moved hubs mark
-// their neighbours unprocessed.
+// exact reverse move with priority flags the hub blocked; (2) every chunk of
+// an unblocked hub marks its neighbours unprocessed and the first one moves
+// the hub, while the first chunk of a blocked hub leaves it unprocessed.
 __global__ __launch_bounds__(256) void k_hub_rev(MoveArgs a) {
   const int64_t q = a.qbeg + blockIdx.x;
   const int h = a.hp.chub[q];
   const int i = a.hp.hubv[h];
+  // the frontier read in the gather is complete: clear the processed flag
+  if (a.hub_front && q == a.hp.hch[h] && threadIdx.x == 0) a.U[i] = 0;
   if (!a.act[i]) return;
   const int p = a.prop[i];
   if (p < 0) return;
@@ -621,30 +636,25 @@ __global__ __launch_bounds__(256) void k_hub_rev(MoveArgs a) {
   if (blocked) a.hp.flag[h] = 1;
 }
 
-__global__ __launch_bounds__(256) void k_hub_move(MoveArgs a) {
-  double gsum = 0.0;
-  long long mv = 0;
-  const int64_t h = a.hbeg + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (h < a.hend) {
-    const int i = a.hp.hubv[h];
-    const int p = a.act[i] ? a.prop[i] : -1;
-    if (p >= 0) {
-      if (a.hp.flag[h] == 1) {
-        a.U[i] = 1;
-      } else {
-        do_move(a, i, a.from[i], p, a.gp[i], gsum, mv);
-        a.hp.flag[h] = 2;
-      }
-    }
-  }
-  flush_gain(a, gsum, mv);
-}
-
 __global__ __launch_bounds__(256) void k_hub_mark(MoveArgs a) {
   const int64_t q = a.qbeg + blockIdx.x;
   const int h = a.hp.chub[q];
-  if (a.hp.flag[h] != 2) return;
   const int i = a.hp.hubv[h];
+  if (!a.act[i]) return;
+  const int p = a.prop[i];
+  if (p < 0) return;
+  const bool lead = q == a.hp.hch[h] && threadIdx.x == 0;
+  if (a.hp.flag[h] == 1) {
+    if (lead) a.U[i] = 1;
+    return;
+  }
+  if (lead) {
+    double gsum = 0.0;
+    long long mv = 0;
+    do_move(a, i, a.from[i], p, a.gp[i], gsum, mv);
+    if (gsum != 0.0 && a.gain) unsafeAtomicAdd(a.gain, gsum);
+    atomicAdd(a.moves, 1ull);
+  }
   const int64_t e0 = a.off[i] + (q - a.hp.hch[h]) * kHubEC;
   const int64_t e1 = min(e0 + (int64_t)kHubEC, a.off[i + 1]);
   for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
@@ -656,7 +666,6 @@ __global__ __launch_bounds__(256) void k_hub_mark(MoveArgs a) {
 void move_hub_apply(const MoveArgs &a, hipStream_t s) {
   if (a.qend <= a.qbeg) return;
   hipLaunchKernelGGL(k_hub_rev, (int)(a.qend - a.qbeg), 256, 0, s, a);
-  hipLaunchKernelGGL(k_hub_move, (int)ceil_div(a.hend - a.hbeg, (int64_t)256), 256, 0, s, a);
   hipLaunchKernelGGL(k_hub_mark, (int)(a.qend - a.qbeg), 256, 0, s, a);
 }
 

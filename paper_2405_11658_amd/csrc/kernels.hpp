@@ -98,7 +98,7 @@ struct HubPlan {
   double *own;     // [nhub] weight to the hub's own community (zero between uses)
   double *pg;      // per-segment best gain
   int32_t *pc;     // per-segment best community
-  int32_t *flag;   // [nhub] apply state: 1 blocked, 2 moved (reset by the final reduction)
+  int32_t *flag;   // [nhub] 1 when the hub's move is blocked (reset by the final reduction)
 };
 
 struct MoveArgs {
@@ -133,6 +133,7 @@ struct MoveArgs {
   // multi-workgroup hub path
   HubPlan hp;
   uint8_t *act;          // hub is in the frontier of its slice (written by the frontier)
+  int hub_front;         // the hub gather writes act itself (asynchronous mode)
   int64_t hbeg, hend;    // hubs of the current slice
   int64_t qbeg, qend;    // their edge chunks
   int64_t gbeg, gend;    // their table segments
@@ -221,7 +222,6 @@ void edge_flags(const int64_t *off, int64_t n, int32_t *flags, hipStream_t s);
 void edge_list(const int64_t *off, int64_t n, const int32_t *pos, int32_t *list, hipStream_t s);
 void refine_async(const RefineArgs &a, int waves, bool wide, hipStream_t s);
 // hub frontier of slice a.s (a.hbeg..a.hend of the hub plan) for the hub-only sliced phase
-void move_hub_frontier(const MoveArgs &a, hipStream_t s);
 
 // ---- k_aggregate.hip -----------------------------------------------------------
 struct AggArgs {
