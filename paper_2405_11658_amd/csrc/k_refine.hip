@@ -234,15 +234,9 @@ static int rgrid(int64_t cap, int per_block, int maxb = 4096) {
 // then a global table per hub; segments scored and cleared; a final
 // wavefront reduces).  Candidates: hubs of the slice in a changed bound that
 // are isolated at the start of the slice; only neighbours in the same bound
-// count; the own community is the vertex itself.
-__global__ void k_rhub_frontier(RefineArgs a) {
-  for (int64_t h = a.hbeg + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < a.hend;
-       h += (int64_t)gridDim.x * blockDim.x) {
-    const int i = a.hp.hubv[h];
-    a.act[i] = a.dC[a.CB[i]] && a.C[i] == i && a.S[i] == 1;
-  }
-}
-
+// count; the own community is the vertex itself.  Each gather chunk tests
+// candidacy itself (nothing it reads changes during the launch) and the
+// hub's first chunk records it for the later launches.
 __global__ __launch_bounds__(256) void k_rhub_gather(RefineArgs a) {
   constexpr int T = 2 * kHubEC;
   constexpr int PER = kHubEC / 256;  // edges per thread
@@ -254,7 +248,9 @@ __global__ __launch_bounds__(256) void k_rhub_gather(RefineArgs a) {
   const int64_t q = a.qbeg + blockIdx.x;
   const int h = a.hp.chub[q];
   const int i = a.hp.hubv[h];
-  if (!a.act[i]) return;
+  const bool go = a.dC[a.CB[i]] && a.C[i] == i && a.S[i] == 1;
+  if (q == a.hp.hch[h] && threadIdx.x == 0) a.act[i] = go;
+  if (!go) return;
   const int64_t e0 = a.off[i] + (q - a.hp.hch[h]) * kHubEC;
   const int64_t e1 = min(e0 + (int64_t)kHubEC, a.off[i + 1]);
   const int cbi = a.CB[i];
@@ -348,12 +344,9 @@ __global__ __launch_bounds__(256) void k_rhub_final(RefineArgs a) {
 }
 
 static void refine_hubs(const RefineArgs &a, hipStream_t s) {
-  if (a.hend <= a.hbeg) return;
-  hipLaunchKernelGGL(k_rhub_frontier, flat_grid(a.hend - a.hbeg), 256, 0, s, a);
-  if (a.qend > a.qbeg) {
-    hipLaunchKernelGGL(k_rhub_gather, (int)(a.qend - a.qbeg), 256, 0, s, a);
-    hipLaunchKernelGGL(k_rhub_score, (int)(a.gend - a.gbeg), 256, 0, s, a);
-  }
+  if (a.hend <= a.hbeg || a.qend <= a.qbeg) return;  // every hub has edge chunks
+  hipLaunchKernelGGL(k_rhub_gather, (int)(a.qend - a.qbeg), 256, 0, s, a);
+  hipLaunchKernelGGL(k_rhub_score, (int)(a.gend - a.gbeg), 256, 0, s, a);
   hipLaunchKernelGGL(k_rhub_final, (int)ceil_div(a.hend - a.hbeg, (int64_t)4), 256, 0, s, a);
 }
 

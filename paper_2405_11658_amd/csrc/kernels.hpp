@@ -132,7 +132,7 @@ struct MoveArgs {
   unsigned long long *moves;  // device scalar
   // multi-workgroup hub path
   HubPlan hp;
-  uint8_t *act;          // hub is in the frontier of its slice (written by the frontier)
+  uint8_t *act;          // hub is in the frontier of its slice
   int hub_front;         // the hub gather writes act itself (asynchronous mode)
   int64_t hbeg, hend;    // hubs of the current slice
   int64_t qbeg, qend;    // their edge chunks
