@@ -632,3 +632,82 @@ def test_zero_gain_move_is_not_taken():
     C2 = C.copy(); C2[3] = 2
     assert q4_exact(g, C2) == q4_exact(g, C)      # the only candidate has zero gain
     assert oracle.best_move(g, C, K, Sig, float(K.sum()), 3)[0] == -1
+
+
+def test_threshold_drops_between_passes():
+    """Alg. leiden divides the iteration tolerance by TOLERANCE_DROP after every
+    pass (Sec. 4.6: tau0 = 0.01, drop 10).  Hand-worked case: three K4 blocks
+    A = {0..3}, B = {4..7}, C = {8..11} with 4 edges A-B and 3 edges B-C, and a
+    separate edge (12, 13) of weight 15, so m = 40, D_A = 16, D_B = 19, D_C = 15.
+    Starting from the blocks with nothing affected and nothing changed, pass 0
+    moves nothing and aggregation keeps the blocks.  On the aggregated level
+    the only positive move is A joining B, with
+        dQ = e_AB/m - D_A D_B / (2 m^2) = 4/40 - 304/3200 = 0.005,
+    which lies between tau0/10 = 0.001 and tau0 = 0.01: with the dropped
+    threshold pass 1 takes a second (empty) iteration, so l_1 = 2 and the
+    loop goes on to a third pass, which converges at once (l_2 = 1).  Had the
+    threshold not dropped, pass 1 would stop after one iteration and end the
+    run after two passes."""
+    m, DA, DB, DC = 40, 16, 19, 15
+    dq = Fraction(4, m) - Fraction(DA * DB, 2 * m * m)
+    assert dq == Fraction(1, 200)
+    assert Fraction(1, 1000) < dq < Fraction(1, 100)
+    # every other merge on the aggregated levels loses modularity
+    assert Fraction(3, m) - Fraction(DB * DC, 2 * m * m) < 0
+    assert Fraction(3, m) - Fraction((DA + DB) * DC, 2 * m * m) < 0
+    u, v, w = [], [], []
+    for blk in (0, 4, 8):
+        for a, b in itertools.combinations(range(blk, blk + 4), 2):
+            u.append(a); v.append(b); w.append(1.0)
+    for k in range(4):
+        u.append(k); v.append(4 + k); w.append(1.0)
+    for k in range(3):
+        u.append(4 + k); v.append(8 + k); w.append(1.0)
+    u.append(12); v.append(13); w.append(15.0)
+    g = as_og(gen.from_edges(14, u, v, w))
+    K = np.array([g.w[g.off[k]:g.off[k + 1]].astype(np.float64).sum() for k in range(14)])
+    C0 = np.array([0] * 4 + [1] * 4 + [2] * 4 + [3] * 2, np.int32)
+    Sig = np.zeros(14); np.add.at(Sig, C0, K)
+    assert Sig[:3].tolist() == [DA, DB, DC] and K.sum() == 2 * m
+    none = np.zeros(14, np.uint8)
+    ones = np.ones(14, np.uint8)
+    for sync in (False, True):
+        prm = oracle.make_params(sync=sync, nslices=1)
+        C, st = oracle.core(g, C0, K, Sig, float(K.sum()), none, ones, none, False, prm)
+        assert st["passes"] == 3, st
+        assert st["move_iters"] == [1, 2, 1], st
+        assert same_partition(C, [0] * 8 + [1] * 4 + [2] * 2)
+
+
+def test_move_phase_respects_affected_range():
+    """Alg. deltaScreening hands the move phase a range (inAffectedRange): a
+    vertex outside it is never moved in the first pass, even after a moving
+    neighbour marks it unprocessed (Alg. leidenMove skips it).  Hand-worked
+    case: triangles {0,1,2} and {3,4,5} joined by the edge (2,3), with 2 and
+    3 placed in each other's community, C = [0,0,1,0,1,1], and only vertex 2
+    affected and in range.  Vertex 2 gains g = 14*3 - 3*((3+7)-7) = 33 > 0 by
+    joining community 0 and marks 3 unprocessed; vertex 3 would then gain
+    14*(2-1) - 3*((3+4)-10) = 23 > 0 by joining community 1, but it is out of
+    range.  So exactly one move is made and 3 keeps its label."""
+    g = as_og(gen.from_edges(6, [0, 0, 1, 3, 3, 4, 2], [1, 2, 2, 4, 5, 5, 3]))
+    C = np.array([0, 0, 1, 0, 1, 1], np.int32)
+    K = np.diff(g.off).astype(np.float64)
+    Sig = np.zeros(6); np.add.at(Sig, C, K)
+    M2 = float(K.sum())
+    assert (M2, Sig[0], Sig[1]) == (14.0, 7.0, 7.0)
+    assert oracle.best_move(g, C, K, Sig, M2, 2) == (0, 33.0)
+    after = C.copy(); after[2] = 0
+    Sig2 = np.zeros(6); np.add.at(Sig2, after, K)
+    assert oracle.best_move(g, after, K, Sig2, M2, 3) == (1, 23.0)   # would move if in range
+    rng = np.array([0, 0, 1, 0, 0, 0], np.uint8)
+    for sync in (False, True):
+        l, C2, Sig3, dC, U, nm, gain = oracle.move_phase(g, C, K, Sig, M2, np.zeros(6, np.uint8), rng.copy(),
+                                                         rng, True, sync=sync, nslices=1)
+        assert nm == 1 and gain == 33.0
+        assert C2.tolist() == [0, 0, 0, 0, 1, 1]
+        assert dC.tolist() == [1, 1, 0, 0, 0, 0]
+    # the same inside the pass loop: the first pass makes that one move only
+    for sync in (False, True):
+        _, st = oracle.core(g, C, K, Sig, M2, rng, rng, np.zeros(6, np.uint8), True,
+                            oracle.make_params(sync=sync, nslices=1))
+        assert st["moves_pass0"] == 1 and st["affected"] == 1, st
