@@ -19,18 +19,26 @@
  * (K, Sigma, 2m) and modularity are float64 (Sec. 5.1.2).
  *
  * Memory.  Unless a parameter says "host", every pointer is a device pointer
- * (hipMalloc'd memory of the current device).  The caller owns all input and
+ * (device memory of the current device).  The caller owns all input and
  * output buffers; they must stay valid until the work enqueued on `stream`
- * completes.  A handle owns its graph, state and scratch; leiden_destroy frees
- * them.  `stream` is a hipStream_t passed as void* (NULL = default stream).
+ * completes.  A handle owns its graph, state and scratch, obtained from the
+ * allocator given to leiden_create (else from HIP's stream-ordered allocator);
+ * leiden_destroy releases them.  `stream` is a hipStream_t passed as void*
+ * (NULL = default stream).
  *
  * Ordering.  Calls are stream-ordered; calls that return host values (q_out,
- * stats, counts) synchronise the stream before returning.
+ * stats, counts) synchronise the stream before returning.  A call on a handle
+ * enqueued on another stream than the handle's previous call first waits (on
+ * the device) for the previous call's work.  No call waits for the whole
+ * device: memory is released in stream order.
  *
  * Errors.  Every entry point returns a leiden_status; no exception crosses the
  * ABI.  On LEIDEN_EINVAL the handle is unchanged (inputs are validated before
- * any mutation).  leiden_last_error() gives a message for the last failure on
- * a handle.
+ * any mutation).  A LEIDEN_ENOMEM or LEIDEN_EHIP from leiden_update after the
+ * batch was validated leaves the handle holding G^t without a community state:
+ * its next leiden_update returns LEIDEN_ESTATE until leiden_static or
+ * leiden_set_state installs a membership again.  leiden_last_error() gives a
+ * message for the last failure on a handle.
  *
  * Concurrency.  A handle is used by one host thread at a time; distinct
  * handles are independent.
@@ -38,6 +46,7 @@
 #ifndef LEIDEN_H
 #define LEIDEN_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -84,7 +93,7 @@ typedef struct {
   int32_t refine_variant;
   int32_t nslices; /* 1 .. 256, synchronous mode */
   int32_t profile; /* 0 or 1 */
-  int32_t async_waves; /* 0 .. 65536, rounded up to a multiple of 4 */
+  int32_t async_waves; /* 0 .. 65536; 1 = one wavefront: the serial sweep */
   int32_t hub_slices;  /* 0 .. 256, asynchronous mode only */
 } leiden_params;
 
@@ -171,15 +180,36 @@ typedef struct {
 
 typedef struct leiden_handle leiden_handle;
 
+/* Device-memory provider of a handle (for example a framework's caching
+ * allocator).  alloc returns `bytes` of device memory usable by work enqueued
+ * on `stream` (a hipStream_t as void*), or NULL when it cannot; the library
+ * then fails the call with LEIDEN_ENOMEM.  release returns memory that alloc
+ * gave out (same size); it is called without waiting for the device, with
+ * the stream that last used the memory, after that use was enqueued: the
+ * provider must not hand the memory to other work before the work enqueued
+ * on that stream so far has completed.  Both may be called from the library's
+ * worker threads (leiden_update_many, leiden_server_*), never concurrently
+ * for one handle. */
+typedef struct {
+  void *(*alloc)(void *ctx, size_t bytes, void *stream);
+  void (*release)(void *ctx, void *ptr, size_t bytes, void *stream);
+  void *ctx;
+} leiden_allocator;
+
 void leiden_default_params(leiden_params *p /* host */);
 
 /* Create a handle holding a copy of the graph (rows are sorted by the
  * library; duplicate entries in a row are LEIDEN_EINVAL).  params may be NULL
- * for the defaults.  *out (host) receives the handle. */
+ * for the defaults.  alloc (host struct, copied; may be NULL) provides every
+ * device allocation of the handle for its whole life; NULL uses HIP's
+ * stream-ordered allocator (hipMallocAsync / hipFreeAsync).  *out (host)
+ * receives the handle. */
 leiden_status leiden_create(int64_t n, int64_t nnz, const int64_t *offsets, const int32_t *indices,
-                            const float *weights, const leiden_params *params, void *stream,
-                            leiden_handle **out);
+                            const float *weights, const leiden_params *params, const leiden_allocator *alloc,
+                            void *stream, leiden_handle **out);
 
+/* Releases the handle's memory in stream order after its last enqueued work
+ * (no wait for the device); the handle pointer is invalid afterwards. */
 leiden_status leiden_destroy(leiden_handle *h);
 
 leiden_status leiden_set_params(leiden_handle *h, const leiden_params *params /* host */);
@@ -199,6 +229,23 @@ leiden_status leiden_update(leiden_handle *h, const leiden_batch *batch, int32_t
                             int32_t *membership_out, double *q_out, leiden_stats *stats,
                             const leiden_trace *trace, void *stream);
 
+/* Marking only (Alg. "naiveDynamic", "deltaScreening", "dynamicFrontier",
+ * and changedCommunities of Alg. "leiden"): the flags leiden_update would
+ * compute for this batch - affected (deltaV), in_range (inAffectedRange) and
+ * changed (keyed by the previous community id), each n bytes, nullable - from
+ * G^t (the handle's graph with the batch applied), the stored C^{t-1},
+ * K^{t-1}, Sigma^{t-1} and 2m.  The batch is validated as for leiden_update.
+ * Pure: the handle's graph and state are not modified (its scratch is).
+ * Requires a prior leiden_static or leiden_set_state (else LEIDEN_ESTATE). */
+leiden_status leiden_mark_affected(leiden_handle *h, const leiden_batch *batch, int32_t mode,
+                                   uint8_t *affected, uint8_t *in_range, uint8_t *changed, void *stream);
+
+/* Estimate (host, *bytes) of the device memory a leiden_update with n_del
+ * deletions and n_ins insertions may newly allocate on this handle: the
+ * update's working set for the grown graph minus what the handle holds.
+ * Used by the server's admission; an estimate, not a bound. */
+leiden_status leiden_update_bytes(const leiden_handle *h, int64_t n_del, int64_t n_ins, int64_t *bytes /* host */);
+
 /* Batched form of leiden_update for many independent graphs (the update of
  * Sec. 3.5 applied to each).  handles[k] (host array of distinct handles),
  * batches[k], modes[k] and, when non-NULL, membership_out[k] (host array of
@@ -217,7 +264,8 @@ leiden_status leiden_update_many(leiden_handle *const *handles, const leiden_bat
 /* Serving loop over many resident graphs (handles): update requests are
  * queued by leiden_server_submit and run as they are admitted - up to
  * `slots` at a time (1 .. 64), each on a stream and host worker of its own,
- * while the summed device-memory estimate of the running requests stays
+ * while the summed device-memory estimate of the running requests (each the
+ * leiden_update_bytes of its handle and batch, taken at admission) stays
  * within memory_budget bytes (0 = unlimited; a request is always admitted
  * when nothing else runs) and no other request of the same handle runs.  A
  * request that does not fit lets later ones that do go first.  The batch
@@ -235,6 +283,59 @@ leiden_status leiden_server_wait(leiden_server *server, int64_t request_id, leid
                                  double *q_out, leiden_stats *stats, double *latency_ms,
                                  double *service_ms);
 leiden_status leiden_server_destroy(leiden_server *server);
+
+/* Fleet: many small graphs updated together in one persistent launch.
+ *
+ * A fleet holds `count` graphs (each as leiden_create copies it: CSR with
+ * int64 offsets, int32 ids, float32 weights; rows need not be sorted) and
+ * their community state in device memory.  leiden_fleet_run takes a list of
+ * jobs - graph index graphs[k] (each at most once per run) and mode modes[k]:
+ * 0 static Leiden (Alg. "leiden" from singletons), LEIDEN_ND / DS / DF an
+ * update with batches[k] (as for leiden_update; a graph needs a static job or
+ * an earlier update first, else that job's status is LEIDEN_ESTATE) - and
+ * runs all of them in ONE launch: each workgroup takes jobs from a queue and
+ * performs a whole update of one graph (graph update, marking,
+ * changedCommunities, updateWeights, the pass loop, final relabel, Sigma and
+ * Eq. 1).  The launch is replayed from a captured HIP graph.
+ *
+ * Local moving and refinement are the serial asynchronous sweeps of
+ * Alg. "leidenMove" and "leidenRefine" (vertices one at a time in ascending
+ * id order, the workgroup sharing each vertex's edges and table), so every
+ * job's result is determined by its graph and batch alone - equal to the
+ * serial reading of the paper's algorithms, and independent of the launch
+ * variant (leiden_fleet_set_variant: wavefronts per workgroup and LDS table
+ * slots, a speed choice only; leiden_fleet_variant_info describes it).
+ * params: as for leiden_create (sync_mode, nslices, async_waves, hub_slices
+ * and profile are not used; max_passes <= 16).  alloc as for leiden_create.
+ *
+ * Per job, when the arrays are non-NULL: membership_out[k] (device, n of
+ * that graph, dense labels), q_out[k], status_out[k] and stats[k] (host;
+ * passes, move_iters, level_vertices, communities, affected, changed,
+ * moves_pass0, ms_total = the launch's device time).  *ms_out (host,
+ * nullable): device time of the launch.  The return value is the first
+ * non-OK job status (the other jobs still ran); a malformed call (graph index
+ * out of range or repeated, bad mode, NULL batch arrays) is LEIDEN_EINVAL and
+ * runs nothing.  An invalid batch leaves its graph unchanged.  A graph's
+ * buffers grow (stream-ordered) when a batch would exceed their capacity. */
+typedef struct leiden_fleet leiden_fleet;
+leiden_status leiden_fleet_create(int32_t count, const int64_t *n /* host */, const int64_t *nnz /* host */,
+                                  const int64_t *const *offsets, const int32_t *const *indices,
+                                  const float *const *weights /* host arrays of device pointers */,
+                                  const leiden_params *params, const leiden_allocator *alloc, void *stream,
+                                  leiden_fleet **out);
+leiden_status leiden_fleet_run(leiden_fleet *fleet, int32_t count, const int32_t *graphs /* host */,
+                               const int32_t *modes /* host */, const leiden_batch *batches /* host */,
+                               int32_t *const *membership_out, double *q_out, leiden_status *status_out,
+                               leiden_stats *stats, double *ms_out, void *stream);
+leiden_status leiden_fleet_get_graph(leiden_fleet *fleet, int32_t graph, int64_t *offsets, int32_t *indices,
+                                     float *weights, int64_t *nnz /* host */, void *stream);
+leiden_status leiden_fleet_get_state(leiden_fleet *fleet, int32_t graph, int32_t *membership, double *K,
+                                     double *Sigma, double *m2 /* host */, void *stream);
+leiden_status leiden_fleet_set_variant(leiden_fleet *fleet, int32_t variant /* 0 .. 5 */);
+leiden_status leiden_fleet_variant_info(int32_t variant, int32_t *waves /* host */, int32_t *slots /* host */);
+int32_t leiden_fleet_count(const leiden_fleet *fleet);
+const char *leiden_fleet_last_error(const leiden_fleet *fleet);
+leiden_status leiden_fleet_destroy(leiden_fleet *fleet);
 
 /* Eq. 1 in FP64 for any CSR graph and membership (labels in [0, n));
  * q_out (host) is 0 when the graph has no edges.  Stateless. */

@@ -14,10 +14,12 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
 
+#include "host_alloc.hpp"
 #include "kernels.hpp"
 #include "leiden.h"
 
@@ -25,10 +27,7 @@ using namespace lk;
 
 namespace {
 
-struct DBuf {
-  void *p = nullptr;
-  size_t cap = 0;
-};
+
 
 enum Slot {
   // level arrays (size n of level 0)
@@ -74,15 +73,28 @@ struct DevScal {
 struct Workspace {
   DBuf ws[NSLOT];
   DBuf scal;
+  Alloc al;
   void *hpin = nullptr;
   std::string err;
   std::vector<hipEvent_t> events;
   std::vector<hipEvent_t> kevents;
+  // releases every buffer, ordered after the work enqueued on `s`
+  void release(hipStream_t s) {
+    for (auto &b : ws) {
+      al.put(b.p, b.cap, s);
+      b = DBuf{};
+    }
+    al.put(scal.p, scal.cap, s);
+    scal = DBuf{};
+  }
+  // device bytes held
+  size_t held() const {
+    size_t t = scal.cap;
+    for (const auto &b : ws) t += b.cap;
+    return t;
+  }
   ~Workspace() {
-    for (auto &b : ws)
-      if (b.p) (void)hipFree(b.p);
-    if (scal.p) (void)hipFree(scal.p);
-    if (hpin) (void)hipHostFree(hpin);
+    pin_pool().give(hpin);
     for (auto e : events) (void)hipEventDestroy(e);
     for (auto e : kevents) (void)hipEventDestroy(e);
   }
@@ -100,9 +112,18 @@ struct leiden_handle {
   double M2 = 0.0;
   bool has_state = false;
   Workspace w;
+  hipStream_t last = nullptr;  // stream of the latest call
+  bool used = false;           // a call has enqueued work on `last`
+  hipEvent_t order = nullptr;  // orders a call on another stream after `last`
+  void release(hipStream_t s) {
+    for (DBuf *b : {&g_off, &g_idx, &g_w, &g_crow, &t_off, &t_idx, &t_w, &C, &K, &Sig}) {
+      w.al.put(b->p, b->cap, s);
+      *b = DBuf{};
+    }
+    w.release(s);
+  }
   ~leiden_handle() {
-    for (DBuf *b : {&g_off, &g_idx, &g_w, &g_crow, &t_off, &t_idx, &t_w, &C, &K, &Sig})
-      if (b->p) (void)hipFree(b->p);
+    if (order) (void)hipEventDestroy(order);
   }
 };
 
@@ -112,7 +133,6 @@ struct Fail {
   leiden_status st;
 };
 
-constexpr size_t kPinBytes = 65536;
 constexpr int kMaxSlices = 256;
 // hub slices of the asynchronous mode: with 1/64 of the hubs moving at a time a
 // DF update on RMAT-22 stays within about 7e-4 of the serial sweep's
@@ -138,7 +158,7 @@ bool wide_tables(int64_t nnz, int64_t with_edges) { return with_edges > 0 && nnz
 int level_waves(int cap, int64_t n, int pass) {
   int64_t w = n / (pass == 0 ? kVertsPerWave : kVertsPerWaveUpper);
   w = std::max<int64_t>(1, std::min<int64_t>(w, cap));
-  return (int)(w < 4 ? w : (w + 3) / 4 * 4);
+  return (int)(w < 4 ? w : w / 4 * 4);  // whole 4-wavefront workgroups, never above cap
 }
 
 struct KProf;
@@ -168,19 +188,17 @@ struct Ctx {
     // (a graph growing by batches) do not reallocate every time
     size_t want = std::max(bytes, (size_t)(b.cap + b.cap / 4));
     want = (want + 255) & ~(size_t)255;
-    if (b.p) {
-      check(hipStreamSynchronize(s), "hipStreamSynchronize");
-      check(hipFree(b.p), "hipFree");
-      b.p = nullptr;
-      b.cap = 0;
-    }
-    hipError_t e = hipMalloc(&b.p, want);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      b.p = nullptr;
+    // the old contents are not kept; its release is ordered after the work
+    // already enqueued on the stream
+    w->al.put(b.p, b.cap, s);
+    b.p = nullptr;
+    b.cap = 0;
+    void *p = w->al.get(want, s);
+    if (!p) {
       w->err = "device allocation of " + std::to_string(want) + " bytes failed";
       throw Fail{LEIDEN_ENOMEM};
     }
+    b.p = p;
     b.cap = want;
   }
   template <class T>
@@ -196,7 +214,13 @@ struct Ctx {
     return (DevScal *)w->scal.p;
   }
   void *pin() {
-    if (!w->hpin) check(hipHostMalloc(&w->hpin, kPinBytes, hipHostMallocDefault), "hipHostMalloc");
+    if (!w->hpin) {
+      w->hpin = pin_pool().take();
+      if (!w->hpin) {
+        w->err = "pinned host allocation failed";
+        throw Fail{LEIDEN_ENOMEM};
+      }
+    }
     return w->hpin;
   }
   template <class T>
@@ -603,7 +627,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
   double *tiles = x.get<double>(L_tiles, n / 256 + 2);
   uint8_t *act = x.get<uint8_t>(L_act, n);
   const bool async = p.sync_mode == 0;
-  const int NW = async ? (p.async_waves > 0 ? (p.async_waves + 3) / 4 * 4 : kDefaultAsyncWaves) : 0;
+  const int NW = async ? (p.async_waves > 0 ? p.async_waves : kDefaultAsyncWaves) : 0;
   int *akeys = async ? x.get<int>(W_keys, (int64_t)NW * 2 * kHubDeg) : nullptr;
   double *avals = async ? x.get<double>(W_vals, (int64_t)NW * 2 * kHubDeg) : nullptr;
 
@@ -718,7 +742,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
       // indefinitely, each move scored as a gain; the tolerance test then
       // never passes.  Stop when the number of moves has not reached a new
       // minimum for kStallIters iterations in a row.
-      if (async && pass > 0) {
+      if (async && pass > 0 && level_waves(NW, alen, pass) > 1) {
         if (r.moves < min_moves) {
           min_moves = r.moves;
           stall = 0;
@@ -872,6 +896,173 @@ bool valid_params(const leiden_params *p) {
 
 }  // namespace
 
+namespace {
+bool batch_pointers_ok(const leiden_batch *batch) {
+  if (batch->n_del < 0 || batch->n_ins < 0) return false;
+  if (batch->n_del > 0 && (!batch->del_u || !batch->del_v)) return false;
+  if (batch->n_ins > 0 && (!batch->ins_u || !batch->ins_v || !batch->ins_w)) return false;
+  return true;
+}
+
+// Validates the batch against G^{t-1} (the handle's graph) and builds G^t,
+// rows sorted, in the handle's spare CSR (t_off, t_idx, t_w); the handle's
+// graph and state are not modified.  Returns |E^t|; b keeps the sorted
+// directed batch for the marking.
+int64_t stage_batch(Ctx &x, leiden_handle *h, const leiden_batch &batch, BatchArgs &b) {
+  const int64_t n = h->n;
+  DevScal *sc = x.scal();
+  memset(&b, 0, sizeof(b));
+  b.n = n;
+  b.nnz = h->nnz;
+  b.off = (const int64_t *)h->g_off.p;
+  b.idx = (const int32_t *)h->g_idx.p;
+  b.w = (const float *)h->g_w.p;
+  b.nd = batch.n_del;
+  b.ni = batch.n_ins;
+  b.du = batch.del_u; b.dv = batch.del_v;
+  b.iu = batch.ins_u; b.iv = batch.ins_v; b.iw = batch.ins_w;
+  b.E = 2 * (b.nd + b.ni);
+  const int64_t E = b.E;
+  b.keys = x.get<unsigned long long>(B_keys, E);
+  b.vals = x.get<int32_t>(B_vals, E);
+  b.skeys = x.get<unsigned long long>(B_skeys, E);
+  b.svals = x.get<int32_t>(B_svals, E);
+  b.ew = x.get<float>(B_ew, E);
+  b.err = &sc->err;
+  b.bstart = x.get<int64_t>(B_bstart, n);
+  b.bcnt = x.get<int32_t>(B_bcnt, n);
+  b.dcnt = x.get<int32_t>(B_dcnt, n);
+  b.icnt = x.get<int32_t>(B_icnt, n);
+  b.isdel = x.get<int32_t>(B_isdel, E + 1);
+  b.delpre = x.get<int32_t>(B_delpre, E + 1);
+  b.newdeg = x.get<int64_t>(B_newdeg, n + 1);
+  b.crow = (const int32_t *)h->g_crow.p;
+  x.zero(&sc->err, 1);
+  x.zero(b.bcnt, n);
+  x.zero(b.dcnt, n);
+  x.zero(b.icnt, n);
+  batch_build(b, x.s);
+  x.launched("batch_build");
+  if (E > 0) {
+    size_t tb = sort_pairs_u64_i32(nullptr, 0, b.keys, b.skeys, b.vals, b.svals, E, x.s);
+    sort_pairs_u64_i32(x.tmp(tb), tb, b.keys, b.skeys, b.vals, b.svals, E, x.s);
+    x.launched("batch sort");
+  }
+  batch_dups_rows(b, x.s);
+  x.launched("batch_dups");
+  const int32_t err = x.read(&sc->err);
+  if (err) {
+    std::string why;
+    if (err & 1) why += " id out of range;";
+    if (err & 2) why += " self-loop;";
+    if (err & 4) why += " repeated edge;";
+    if (err & 8) why += " deletion of a missing edge;";
+    if (err & 16) why += " insertion of an existing edge;";
+    if (err & 32) why += " non-positive or non-finite weight;";
+    x.invalid("invalid batch:" + why);
+  }
+  x.ensure(h->t_off, (size_t)(n + 1) * sizeof(int64_t));
+  b.newoff = (int64_t *)h->t_off.p;
+  batch_newdeg(b, x.s);
+  scan_i64(x, b.newdeg, b.newoff, n + 1);
+  scan_i32(x, b.isdel, b.delpre, E + 1);
+  const int64_t nnz_new = x.read(&b.newoff[n]);
+  x.ensure(h->t_idx, (size_t)std::max<int64_t>(nnz_new, 1) * sizeof(int32_t));
+  x.ensure(h->t_w, (size_t)std::max<int64_t>(nnz_new, 1) * sizeof(float));
+  b.nidx = (int32_t *)h->t_idx.p;
+  b.nw = (float *)h->t_w.p;
+  hipEvent_t t0 = x.kp ? x.kp->begin() : nullptr;
+  batch_apply_old(b, x.s);
+  if (x.kp) x.kp->end(t0, LEIDEN_PROF_BATCH_MERGE, nnz_new, n);
+  batch_apply_ins(b, x.s);
+  x.launched("batch_apply");
+  return nnz_new;
+}
+
+// Alg. "naiveDynamic" / "deltaScreening" / "dynamicFrontier" and
+// changedCommunities: flags dV (affected), rng (in range) and dC (changed,
+// keyed by C^{t-1}) from the staged batch b, G^t = g and the handle's
+// C^{t-1}, K^{t-1}, Sigma^{t-1}; m is left ready for updateWeights.
+void mark_batch(Ctx &x, leiden_handle *h, int32_t mode, const BatchArgs &b, const Level &g, uint8_t *dV,
+                uint8_t *rng, uint8_t *dC, MarkArgs &m) {
+  const int64_t n = h->n;
+  const int64_t E = b.E;
+  DevScal *sc = x.scal();
+  x.zero(dV, n);
+  x.zero(rng, n);
+  x.zero(dC, n);
+  memset(&m, 0, sizeof(m));
+  m.n = n;
+  m.off = g.off;
+  m.idx = g.idx;
+  m.E = E;
+  m.nd2 = 2 * b.nd;
+  m.skeys = b.skeys;
+  m.svals = b.svals;
+  m.ew = b.ew;
+  m.C = (const int32_t *)h->C.p;
+  m.K = (const double *)h->K.p;
+  m.Sig = (const double *)h->Sig.p;
+  m.M2 = h->M2;
+  m.dV = dV;
+  m.rng = rng;
+  m.dC = dC;
+  if (mode == LEIDEN_ND) {
+    fill_u8(dV, 1, n, x.s);
+    fill_u8(rng, 1, n, x.s);
+    mark_changed(m, x.s);
+  } else if (mode == LEIDEN_DF) {
+    mark_df(m, x.s);
+    fill_u8(rng, 1, n, x.s);
+  } else {
+    m.dE = x.get<uint8_t>(M_dE, n);
+    m.dCm = x.get<uint8_t>(M_dCm, n);
+    m.k2 = x.get<unsigned long long>(M_k2, E);
+    m.k2s = x.get<unsigned long long>(M_k2s, E);
+    m.v2 = x.get<double>(M_v2, E);
+    m.v2s = x.get<double>(M_v2s, E);
+    m.list = x.get<int32_t>(M_list, n);
+    m.count = &sc->list_count;
+    x.zero(m.dE, n);
+    x.zero(m.dCm, n);
+    x.zero(m.count, 1);
+    mark_ds_del(m, x.s);
+    mark_ds_keys(m, x.s);
+    if (E > 0) {
+      size_t tb = sort_pairs_u64_f64(nullptr, 0, m.k2, m.k2s, m.v2, m.v2s, E, x.s);
+      sort_pairs_u64_f64(x.tmp(tb), tb, m.k2, m.k2s, m.v2, m.v2s, E, x.s);
+    }
+    mark_ds_best(m, x.s);
+    mark_ds_expand(m, x.s);
+  }
+  x.launched("marking");
+}
+}  // namespace
+
+namespace {
+// A call on a stream other than the previous call's first waits for the
+// handle's latest work (recorded in h->order at the end of every call), so
+// calls on different streams never overlap on the handle's memory.
+void enter(Ctx &x, leiden_handle *h) {
+  if (!h->order) x.check(hipEventCreateWithFlags(&h->order, hipEventDisableTiming), "hipEventCreate");
+  if (h->used && h->last != x.s) x.check(hipStreamWaitEvent(x.s, h->order, 0), "hipStreamWaitEvent");
+  h->last = x.s;
+}
+void leave(leiden_handle *h, hipStream_t s) {
+  if (h->order && hipEventRecord(h->order, s) == hipSuccess) h->used = true;
+  else (void)hipGetLastError();
+}
+// A call on handle h: ordered after the handle's previous work, guarded.
+leiden_status run_handle(leiden_handle *h, Ctx &x, const std::function<void()> &f) {
+  leiden_status st = run_guarded(h->w, [&] {
+    enter(x, h);
+    f();
+  });
+  leave(h, x.s);
+  return st;
+}
+}  // namespace
+
 // ============================ C ABI =========================================
 extern "C" {
 
@@ -906,11 +1097,12 @@ int64_t leiden_num_vertices(const leiden_handle *h) { return h ? h->n : -1; }
 int64_t leiden_num_entries(const leiden_handle *h) { return h ? h->nnz : -1; }
 
 leiden_status leiden_create(int64_t n, int64_t nnz, const int64_t *offsets, const int32_t *indices,
-                            const float *weights, const leiden_params *params, void *stream,
-                            leiden_handle **out) {
+                            const float *weights, const leiden_params *params, const leiden_allocator *alloc,
+                            void *stream, leiden_handle **out) {
   if (!out || n < 0 || nnz < 0 || n > INT32_MAX - 1 || !offsets || (nnz > 0 && (!indices || !weights)))
     return LEIDEN_EINVAL;
   if (params && !valid_params(params)) return LEIDEN_EINVAL;
+  if (alloc && (!alloc->alloc || !alloc->release)) return LEIDEN_EINVAL;
   *out = nullptr;
   leiden_handle *h = new (std::nothrow) leiden_handle();
   if (!h) return LEIDEN_ENOMEM;
@@ -918,8 +1110,13 @@ leiden_status leiden_create(int64_t n, int64_t nnz, const int64_t *offsets, cons
   h->nnz = nnz;
   if (params) h->prm = *params;
   else leiden_default_params(&h->prm);
+  if (alloc) {
+    h->w.al.a = *alloc;
+    h->w.al.custom = true;
+  }
   Ctx x{&h->w, (hipStream_t)stream};
   leiden_status st = run_guarded(h->w, [&] {
+    enter(x, h);
     x.ensure(h->g_off, (size_t)(n + 1) * sizeof(int64_t));
     x.ensure(h->g_idx, (size_t)std::max<int64_t>(nnz, 1) * sizeof(int32_t));
     x.ensure(h->g_w, (size_t)std::max<int64_t>(nnz, 1) * sizeof(float));
@@ -943,16 +1140,23 @@ leiden_status leiden_create(int64_t n, int64_t nnz, const int64_t *offsets, cons
       x.invalid("graph has an id out of range, a non-positive or non-finite weight, or a repeated entry");
   });
   if (st != LEIDEN_OK) {
+    h->release(x.s);
     delete h;
     return st;
   }
+  leave(h, x.s);
   *out = h;
   return LEIDEN_OK;
 }
 
 leiden_status leiden_destroy(leiden_handle *h) {
   if (!h) return LEIDEN_EINVAL;
-  (void)hipDeviceSynchronize();
+  // no wait for the device: the releases are ordered after the handle's last
+  // work (on the null stream, which first waits for that work)
+  hipStream_t s = nullptr;
+  if (h->used && h->order) (void)hipStreamWaitEvent(s, h->order, 0);
+  h->release(s);
+  (void)hipGetLastError();
   delete h;
   return LEIDEN_OK;
 }
@@ -968,7 +1172,7 @@ leiden_status leiden_static(leiden_handle *h, int32_t *membership_out, double *q
   if (!h) return LEIDEN_EINVAL;
   if (stats) memset(stats, 0, sizeof(*stats));
   Ctx x{&h->w, (hipStream_t)stream};
-  return run_guarded(h->w, [&] {
+  return run_handle(h, x, [&] {
     Timer tm(x, stats != nullptr);
     KProf kp(x, stats != nullptr && h->prm.profile != 0);
     x.kp = &kp;
@@ -1020,16 +1224,15 @@ leiden_status leiden_update(leiden_handle *h, const leiden_batch *batch, int32_t
                             double *q_out, leiden_stats *stats, const leiden_trace *trace, void *stream) {
   if (!h || !batch) return LEIDEN_EINVAL;
   if (mode != LEIDEN_ND && mode != LEIDEN_DS && mode != LEIDEN_DF) return LEIDEN_EINVAL;
-  if (batch->n_del < 0 || batch->n_ins < 0) return LEIDEN_EINVAL;
-  if (batch->n_del > 0 && (!batch->del_u || !batch->del_v)) return LEIDEN_EINVAL;
-  if (batch->n_ins > 0 && (!batch->ins_u || !batch->ins_v || !batch->ins_w)) return LEIDEN_EINVAL;
+  if (!batch_pointers_ok(batch)) return LEIDEN_EINVAL;
   if (!h->has_state) {
     h->w.err = "update before leiden_static or leiden_set_state";
     return LEIDEN_ESTATE;
   }
   if (stats) memset(stats, 0, sizeof(*stats));
   Ctx x{&h->w, (hipStream_t)stream};
-  return run_guarded(h->w, [&] {
+  bool mutated = false;  // the handle holds G^t (set once the new graph is installed)
+  const leiden_status status = run_handle(h, x, [&] {
     Timer tm(x, stats != nullptr);
     KProf kp(x, stats != nullptr && h->prm.profile != 0);
     x.kp = &kp;
@@ -1040,77 +1243,15 @@ leiden_status leiden_update(leiden_handle *h, const leiden_batch *batch, int32_t
     tm.mark(CAT_OTHER);
     const int64_t n = h->n;
     DevScal *sc = x.scal();
-    // ---- validate and apply the batch (G^{t-1} -> G^t) ----
+    // ---- validate the batch and build G^t in the spare CSR ----
     BatchArgs b;
-    memset(&b, 0, sizeof(b));
-    b.n = n;
-    b.nnz = h->nnz;
-    b.off = (const int64_t *)h->g_off.p;
-    b.idx = (const int32_t *)h->g_idx.p;
-    b.w = (const float *)h->g_w.p;
-    b.nd = batch->n_del;
-    b.ni = batch->n_ins;
-    b.du = batch->del_u; b.dv = batch->del_v;
-    b.iu = batch->ins_u; b.iv = batch->ins_v; b.iw = batch->ins_w;
-    b.E = 2 * (b.nd + b.ni);
+    const int64_t nnz_new = stage_batch(x, h, *batch, b);
     const int64_t E = b.E;
-    b.keys = x.get<unsigned long long>(B_keys, E);
-    b.vals = x.get<int32_t>(B_vals, E);
-    b.skeys = x.get<unsigned long long>(B_skeys, E);
-    b.svals = x.get<int32_t>(B_svals, E);
-    b.ew = x.get<float>(B_ew, E);
-    b.err = &sc->err;
-    b.bstart = x.get<int64_t>(B_bstart, n);
-    b.bcnt = x.get<int32_t>(B_bcnt, n);
-    b.dcnt = x.get<int32_t>(B_dcnt, n);
-    b.icnt = x.get<int32_t>(B_icnt, n);
-    b.isdel = x.get<int32_t>(B_isdel, E + 1);
-    b.delpre = x.get<int32_t>(B_delpre, E + 1);
-    b.newdeg = x.get<int64_t>(B_newdeg, n + 1);
-    b.crow = (const int32_t *)h->g_crow.p;
-    x.zero(&sc->err, 1);
-    x.zero(b.bcnt, n);
-    x.zero(b.dcnt, n);
-    x.zero(b.icnt, n);
-    batch_build(b, x.s);
-    x.launched("batch_build");
-    if (E > 0) {
-      size_t tb = sort_pairs_u64_i32(nullptr, 0, b.keys, b.skeys, b.vals, b.svals, E, x.s);
-      sort_pairs_u64_i32(x.tmp(tb), tb, b.keys, b.skeys, b.vals, b.svals, E, x.s);
-      x.launched("batch sort");
-    }
-    batch_dups_rows(b, x.s);
-    x.launched("batch_dups");
-    const int32_t err = x.read(&sc->err);
-    if (err) {
-      std::string why;
-      if (err & 1) why += " id out of range;";
-      if (err & 2) why += " self-loop;";
-      if (err & 4) why += " repeated edge;";
-      if (err & 8) why += " deletion of a missing edge;";
-      if (err & 16) why += " insertion of an existing edge;";
-      if (err & 32) why += " non-positive or non-finite weight;";
-      x.invalid("invalid batch:" + why);
-    }
-    x.ensure(h->t_off, (size_t)(n + 1) * sizeof(int64_t));
-    b.newoff = (int64_t *)h->t_off.p;
-    batch_newdeg(b, x.s);
-    scan_i64(x, b.newdeg, b.newoff, n + 1);
-    scan_i32(x, b.isdel, b.delpre, E + 1);
-    const int64_t nnz_new = x.read(&b.newoff[n]);
-    x.ensure(h->t_idx, (size_t)std::max<int64_t>(nnz_new, 1) * sizeof(int32_t));
-    x.ensure(h->t_w, (size_t)std::max<int64_t>(nnz_new, 1) * sizeof(float));
-    b.nidx = (int32_t *)h->t_idx.p;
-    b.nw = (float *)h->t_w.p;
-    hipEvent_t t0 = x.kp ? x.kp->begin() : nullptr;
-    batch_apply_old(b, x.s);
-    if (x.kp) x.kp->end(t0, LEIDEN_PROF_BATCH_MERGE, nnz_new, n);
-    batch_apply_ins(b, x.s);
-    x.launched("batch_apply");
     std::swap(h->g_off, h->t_off);
     std::swap(h->g_idx, h->t_idx);
     std::swap(h->g_w, h->t_w);
     h->nnz = nnz_new;
+    mutated = true;
     refresh_crow(x, h);
     tm.mark(CAT_APPLY);
 
@@ -1119,60 +1260,14 @@ leiden_status leiden_update(leiden_handle *h, const leiden_batch *batch, int32_t
     uint8_t *dV = x.get<uint8_t>(L_U, n);
     uint8_t *rng = x.get<uint8_t>(L_rng, n);
     uint8_t *dC = x.get<uint8_t>(L_dC, n);
-    x.zero(dV, n);
-    x.zero(rng, n);
-    x.zero(dC, n);
     MarkArgs m;
-    memset(&m, 0, sizeof(m));
-    m.n = n;
-    m.off = g.off;
-    m.idx = g.idx;
-    m.E = E;
-    m.nd2 = 2 * b.nd;
-    m.skeys = b.skeys;
-    m.svals = b.svals;
-    m.ew = b.ew;
-    m.C = (const int32_t *)h->C.p;
-    m.K = (const double *)h->K.p;
-    m.Sig = (const double *)h->Sig.p;
-    m.M2 = h->M2;
-    m.dV = dV;
-    m.rng = rng;
-    m.dC = dC;
-    if (mode == LEIDEN_ND) {
-      fill_u8(dV, 1, n, x.s);
-      fill_u8(rng, 1, n, x.s);
-      mark_changed(m, x.s);
-    } else if (mode == LEIDEN_DF) {
-      mark_df(m, x.s);
-      fill_u8(rng, 1, n, x.s);
-    } else {
-      m.dE = x.get<uint8_t>(M_dE, n);
-      m.dCm = x.get<uint8_t>(M_dCm, n);
-      m.k2 = x.get<unsigned long long>(M_k2, E);
-      m.k2s = x.get<unsigned long long>(M_k2s, E);
-      m.v2 = x.get<double>(M_v2, E);
-      m.v2s = x.get<double>(M_v2s, E);
-      m.list = x.get<int32_t>(M_list, n);
-      m.count = &sc->list_count;
-      x.zero(m.dE, n);
-      x.zero(m.dCm, n);
-      x.zero(m.count, 1);
-      mark_ds_del(m, x.s);
-      mark_ds_keys(m, x.s);
-      if (E > 0) {
-        size_t tb = sort_pairs_u64_f64(nullptr, 0, m.k2, m.k2s, m.v2, m.v2s, E, x.s);
-        sort_pairs_u64_f64(x.tmp(tb), tb, m.k2, m.k2s, m.v2, m.v2s, E, x.s);
-      }
-      mark_ds_best(m, x.s);
-      mark_ds_expand(m, x.s);
-    }
-    x.launched("marking");
+    mark_batch(x, h, mode, b, g, dV, rng, dC, m);
     if (trace) {
       if (trace->affected) x.copy(trace->affected, (const uint8_t *)dV, n);
       if (trace->in_range) x.copy(trace->in_range, (const uint8_t *)rng, n);
       if (trace->changed) x.copy(trace->changed, (const uint8_t *)dC, n);
     }
+    (void)E;
     x.zero(&sc->m2delta, 1);
     update_weights(m, (double *)h->K.p, (double *)h->Sig.p, &sc->m2delta, x.s);
     x.launched("update_weights");
@@ -1196,6 +1291,68 @@ leiden_status leiden_update(leiden_handle *h, const leiden_batch *batch, int32_t
     kp.finish(stats, kp.on ? &x.scal()->hub_scanned : nullptr, kp.on ? x.scal()->sweep_work : nullptr);
     x.check(hipStreamSynchronize(x.s), "sync");
   });
+  if (status != LEIDEN_OK && mutated) {
+    // G^t is installed but C, K, Sigma may be part-way through the update:
+    // the handle keeps the new graph and refuses updates until a membership
+    // is installed again
+    h->has_state = false;
+    h->w.err += " (the handle holds the updated graph without a community state: call leiden_static or "
+                "leiden_set_state before the next update)";
+  }
+  return status;
+}
+
+leiden_status leiden_update_bytes(const leiden_handle *h, int64_t n_del, int64_t n_ins, int64_t *bytes) {
+  if (!h || !bytes || n_del < 0 || n_ins < 0) return LEIDEN_EINVAL;
+  // working set of an update (per vertex: level state, flags, lists, batch
+  // rows, aggregation relabelling; per entry: the graph and its spare copy,
+  // two level graphs, the aggregation keys and sums, hub tables; per directed
+  // batch entry: keys, values and their sorted copies; plus the per-wavefront
+  // tables of the asynchronous sweeps) minus what the handle already holds
+  const int64_t n = h->n;
+  const int64_t nnz = h->nnz + 2 * n_ins;
+  const int64_t E = 2 * (n_del + n_ins);
+  const int64_t async_tables = (int64_t)kDefaultAsyncWaves * 2 * kHubDeg * 12;
+  const int64_t need = 203 * n + 104 * nnz + 68 * E + async_tables;
+  int64_t held = (int64_t)h->w.held();
+  for (const DBuf *b : {&h->g_off, &h->g_idx, &h->g_w, &h->g_crow, &h->t_off, &h->t_idx, &h->t_w, &h->C, &h->K,
+                        &h->Sig})
+    held += (int64_t)b->cap;
+  *bytes = std::max<int64_t>(0, need - held);
+  return LEIDEN_OK;
+}
+
+leiden_status leiden_mark_affected(leiden_handle *h, const leiden_batch *batch, int32_t mode, uint8_t *affected,
+                                   uint8_t *in_range, uint8_t *changed, void *stream) {
+  if (!h || !batch) return LEIDEN_EINVAL;
+  if (mode != LEIDEN_ND && mode != LEIDEN_DS && mode != LEIDEN_DF) return LEIDEN_EINVAL;
+  if (!batch_pointers_ok(batch)) return LEIDEN_EINVAL;
+  if (!h->has_state) {
+    h->w.err = "marking before leiden_static or leiden_set_state";
+    return LEIDEN_ESTATE;
+  }
+  Ctx x{&h->w, (hipStream_t)stream};
+  return run_handle(h, x, [&] {
+    const int64_t n = h->n;
+    BatchArgs b;
+    const int64_t nnz_new = stage_batch(x, h, *batch, b);
+    // G^t lives in the spare CSR; the handle's graph and state are untouched
+    const int64_t nch = ceil_div(std::max<int64_t>(nnz_new, 1), kChunk);
+    int32_t *crow = x.get<int32_t>(Q_crow, nch + 2);
+    chunk_start_rows((const int64_t *)h->t_off.p, n, nnz_new, crow, x.s);
+    x.launched("chunk_start_rows");
+    const Level gt{n, nnz_new, (const int64_t *)h->t_off.p, (const int32_t *)h->t_idx.p,
+                   (const float *)h->t_w.p, crow};
+    uint8_t *dV = x.get<uint8_t>(L_U, n);
+    uint8_t *rng = x.get<uint8_t>(L_rng, n);
+    uint8_t *dC = x.get<uint8_t>(L_dC, n);
+    MarkArgs m;
+    mark_batch(x, h, mode, b, gt, dV, rng, dC, m);
+    if (affected) x.copy(affected, (const uint8_t *)dV, n);
+    if (in_range) x.copy(in_range, (const uint8_t *)rng, n);
+    if (changed) x.copy(changed, (const uint8_t *)dC, n);
+    x.check(hipStreamSynchronize(x.s), "sync");
+  });
 }
 
 leiden_status leiden_modularity(int64_t n, const int64_t *offsets, const int32_t *indices, const float *weights,
@@ -1203,7 +1360,7 @@ leiden_status leiden_modularity(int64_t n, const int64_t *offsets, const int32_t
   if (n < 0 || !q_out || (n > 0 && (!offsets || !membership))) return LEIDEN_EINVAL;
   Workspace w;
   Ctx x{&w, (hipStream_t)stream};
-  return run_guarded(w, [&] {
+  const leiden_status st = run_guarded(w, [&] {
     if (n == 0) { *q_out = 0.0; return; }
     const int64_t nnz = x.read(offsets + n);
     if (nnz > 0 && (!indices || !weights)) x.invalid("null edge arrays");
@@ -1217,6 +1374,8 @@ leiden_status leiden_modularity(int64_t n, const int64_t *offsets, const int32_t
     Level g{n, nnz, offsets, indices, weights, crow};
     *q_out = modularity_dev(x, g, membership);
   });
+  w.release(x.s);
+  return st;
 }
 
 leiden_status leiden_aggregate(int64_t n, const int64_t *offsets, const int32_t *indices, const float *weights,
@@ -1225,7 +1384,7 @@ leiden_status leiden_aggregate(int64_t n, const int64_t *offsets, const int32_t 
   if (n < 0 || ncomm < 0 || !nnz_out || !out_offsets || (n > 0 && (!offsets || !membership))) return LEIDEN_EINVAL;
   Workspace w;
   Ctx x{&w, (hipStream_t)stream};
-  return run_guarded(w, [&] {
+  const leiden_status st = run_guarded(w, [&] {
     const int64_t nnz = (n > 0) ? x.read(offsets + n) : 0;
     DevScal *sc = x.scal();
     x.zero(&sc->err, 1);
@@ -1245,13 +1404,15 @@ leiden_status leiden_aggregate(int64_t n, const int64_t *offsets, const int32_t 
     *nnz_out = o.nnz;
     x.check(hipStreamSynchronize(x.s), "sync");
   });
+  w.release(x.s);
+  return st;
 }
 
 leiden_status leiden_get_graph(leiden_handle *h, int64_t *offsets, int32_t *indices, float *weights,
                                int64_t *nnz, void *stream) {
   if (!h) return LEIDEN_EINVAL;
   Ctx x{&h->w, (hipStream_t)stream};
-  return run_guarded(h->w, [&] {
+  return run_handle(h, x, [&] {
     if (nnz) *nnz = h->nnz;
     if (offsets) x.copy(offsets, (const int64_t *)h->g_off.p, h->n + 1);
     if (indices) x.copy(indices, (const int32_t *)h->g_idx.p, h->nnz);
@@ -1265,7 +1426,7 @@ leiden_status leiden_get_state(leiden_handle *h, int32_t *membership, double *K,
   if (!h) return LEIDEN_EINVAL;
   if (!h->has_state) return LEIDEN_ESTATE;
   Ctx x{&h->w, (hipStream_t)stream};
-  return run_guarded(h->w, [&] {
+  return run_handle(h, x, [&] {
     if (membership) x.copy(membership, (const int32_t *)h->C.p, h->n);
     if (K) x.copy(K, (const double *)h->K.p, h->n);
     if (Sigma) x.copy(Sigma, (const double *)h->Sig.p, h->n);
@@ -1277,7 +1438,7 @@ leiden_status leiden_get_state(leiden_handle *h, int32_t *membership, double *K,
 leiden_status leiden_set_state(leiden_handle *h, const int32_t *membership, void *stream) {
   if (!h || (h->n > 0 && !membership)) return LEIDEN_EINVAL;
   Ctx x{&h->w, (hipStream_t)stream};
-  return run_guarded(h->w, [&] {
+  return run_handle(h, x, [&] {
     const int64_t n = h->n;
     DevScal *sc = x.scal();
     x.zero(&sc->err, 1);

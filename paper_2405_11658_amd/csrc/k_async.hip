@@ -314,32 +314,36 @@ __global__ __launch_bounds__(256) void k_move_async(MoveArgs a) {
   for (;;) {
     const int64_t base = grab(a.anext);
     if (base >= a.alen) break;
-    // each lane fetches the state of one vertex of the chunk; unprocessed
-    // candidates are claimed (marked processed) at once and then handled one
-    // after another by the whole wavefront
+    // each lane fetches the state of one vertex of the chunk; the chunk's
+    // unprocessed vertices are then handled one after another by the whole
+    // wavefront, in list order.  A vertex is marked processed at its turn, and
+    // after a move the flags of the chunk's later vertices are read again, so
+    // that one wavefront alone follows the serial sweep exactly (a vertex
+    // re-marked by an earlier vertex of its chunk is handled in the same
+    // iteration).
     const int64_t p = base + lane();
     int v = 0, dv = 0;
     int64_t e0v = 0, e1v = 0;
     double kv = 0.0;
-    bool cand = false;
+    bool elig = false;
     if (p < a.alen) {
       v = a.alist[p];
       e0v = a.off[v];
       e1v = a.off[v + 1];
-      cand = e1v - e0v <= kHubDeg && a.rng[v] && ld_u8(&a.U[v]);
-      if (cand) {
-        st_u8(&a.U[v], 0);
+      elig = e1v - e0v <= kHubDeg && a.rng[v];
+      if (elig) {
         dv = a.C[v];  // only this wavefront writes C[v] during the sweep
         kv = a.K[v];
       }
     }
-    unsigned long long m = __ballot(cand);
+    unsigned long long m = __ballot(elig && ld_u8(&a.U[v]));
     while (m) {
       const int k = __ffsll(m) - 1;
-      m &= m - 1;
+      m &= ~((2ull << k) - 1ull);  // positions after k
       const int i = __shfl(v, k), d = __shfl(dv, k);
       const int64_t e0 = __shfl(e0v, k), e1 = __shfl(e1v, k);
       const double Ki = __shfl(kv, k);
+      if (lane() == 0) st_u8(&a.U[i], 0);
       nv += 1;
       ne += (unsigned long long)(e1 - e0);
       EdgeBatch eb;
@@ -361,7 +365,11 @@ __global__ __launch_bounds__(256) void k_move_async(MoveArgs a) {
         gsum += bg;
         mv += 1;
       }
+      if (lane() == k) dv = bc;
       mark_edges(a.U, a.idx, i, e0, e1, eb);
+      // the move may have marked later vertices of the chunk unprocessed
+      wave_fence();
+      m = __ballot(lane() > k && elig && ld_u8(&a.U[v]));
     }
   }
   if (lane() == 0) {

@@ -40,12 +40,15 @@ struct Request {
   bool done = false;
 };
 
-// Device bytes an update of this batch may add to the handle's working set:
-// the directed batch (keys, values, sorted copies, weights, flags) and the
-// grown CSR.
+// Device bytes an admitted update may use beyond what is already held: the
+// handle's workspace growth for this batch (leiden_update_bytes: the grown
+// graph, its level and aggregation buffers, the directed batch) - taken when
+// the request is considered for admission, since an earlier update of the
+// same handle may have grown it since submission.
 int64_t request_bytes(const leiden_handle *h, const leiden_batch &b) {
-  const int64_t E = 2 * (b.n_del + b.n_ins);
-  return 64 * E + 8 * 2 * b.n_ins + 16 * (leiden_num_vertices(h) + 1) / 64;
+  int64_t bytes = 0;
+  if (leiden_update_bytes(h, b.n_del, b.n_ins, &bytes) != LEIDEN_OK) return 0;
+  return bytes;
 }
 
 }  // namespace
@@ -71,6 +74,7 @@ struct leiden_server {
     for (auto it = queue.begin(); it != queue.end(); ++it) {
       Request *r = *it;
       if (busy.count(r->h)) continue;
+      r->bytes = request_bytes(r->h, r->b);
       if (in_use > 0 && in_use + r->bytes > budget) continue;
       queue.erase(it);
       busy.insert(r->h);
@@ -150,7 +154,7 @@ extern "C" leiden_status leiden_server_submit(leiden_server *sv, leiden_handle *
   r->b = *batch;
   r->mode = mode;
   r->out = membership_out;
-  r->bytes = request_bytes(h, *batch);
+  r->bytes = 0;
   r->submitted = Clock::now();
   {
     std::lock_guard<std::mutex> lk(sv->mu);

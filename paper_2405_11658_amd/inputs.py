@@ -388,3 +388,62 @@ def batch_stream(g: CSR, size: int, count: int, ins_frac: float = 0.8, seed: int
         out.append(UBatch(du[d].astype(np.int32), dv[d].astype(np.int32), iu[i].astype(np.int32),
                           iv[i].astype(np.int32), np.full(len(iu[i]), weight, np.float32)))
     return out
+
+
+def batch_stream_device(n: int, off, idx, size: int, count: int, ins_frac: float = 0.8, seed: int = 0,
+                        weight: float = 1.0) -> list:
+    """The batch stream of ``batch_stream`` (Sec. 5.1.4: round(ins_frac*size)
+    insertions of uniformly random non-edges, the rest deletions of uniformly
+    chosen existing undirected edges, all distinct across the stream) drawn on
+    the graph's torch device, for graphs whose host copy would be slow to
+    search (RMAT scale 26).  off (int64, n+1) and idx (int32) are device
+    tensors of a CSR with rows sorted by neighbour id.  Random numbers come
+    from a ``torch.Generator`` seeded with ``seed``.  Returns a list of
+    (del_u, del_v, ins_u, ins_v, ins_w) device tensors."""
+    import torch
+    dev = off.device
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    n_ins = int(round(ins_frac * size))
+    n_del = size - n_ins
+    nnz = idx.numel()
+    rows = torch.repeat_interleave(torch.arange(n, dtype=torch.int64, device=dev), off[1:] - off[:-1])
+    keys = rows * n + idx.to(torch.int64)       # ascending: rows in order, sorted within rows
+    del rows
+    # deletions: an entry (u, v) with u < v names each undirected edge once;
+    # entries are drawn uniformly, so each edge is equally likely
+    need = n_del * count
+    picked = torch.empty(0, dtype=torch.int64, device=dev)
+    while picked.numel() < need:
+        e = torch.randint(0, nnz, (2 * (need - picked.numel()) + 64,), generator=gen, device=dev)
+        k = keys[e]
+        k = k[(k // n) < (k % n)]
+        picked = torch.unique(torch.cat([picked, k]))
+    picked = picked[torch.randperm(picked.numel(), generator=gen, device=dev)[:need]]
+    # insertions: distinct unordered pairs that are not edges, random orientation
+    need_i = n_ins * count
+    got = torch.empty(0, dtype=torch.int64, device=dev)
+    while got.numel() < need_i:
+        k = 2 * (need_i - got.numel()) + 64
+        a = torch.randint(0, n, (k,), generator=gen, device=dev)
+        b = torch.randint(0, n, (k,), generator=gen, device=dev)
+        lo, hi = torch.minimum(a, b), torch.maximum(a, b)
+        ok = lo != hi
+        cand = lo[ok] * n + hi[ok]
+        pos = torch.clamp(torch.searchsorted(keys, cand), max=nnz - 1)
+        cand = cand[keys[pos] != cand]
+        got = torch.unique(torch.cat([got, cand]))
+    got = got[torch.randperm(got.numel(), generator=gen, device=dev)[:need_i]]
+    del keys
+    flip = torch.rand(got.numel(), generator=gen, device=dev) < 0.5
+    iu, iv = got // n, got % n
+    iu, iv = torch.where(flip, iv, iu), torch.where(flip, iu, iv)
+    du, dv = picked // n, picked % n
+    out = []
+    for j in range(count):
+        d = slice(j * n_del, (j + 1) * n_del)
+        i = slice(j * n_ins, (j + 1) * n_ins)
+        out.append((du[d].to(torch.int32).contiguous(), dv[d].to(torch.int32).contiguous(),
+                    iu[i].to(torch.int32).contiguous(), iv[i].to(torch.int32).contiguous(),
+                    torch.full((n_ins,), weight, dtype=torch.float32, device=dev)))
+    return out

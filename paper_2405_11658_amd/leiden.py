@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import ctypes as ct
 import os
+import threading
 from dataclasses import dataclass
 
 import numpy as np
@@ -90,6 +91,63 @@ class leiden_trace(ct.Structure):
     _fields_ = [("affected", ct.c_void_p), ("in_range", ct.c_void_p), ("changed", ct.c_void_p)]
 
 
+_ALLOC_FN = ct.CFUNCTYPE(ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p)
+_RELEASE_FN = ct.CFUNCTYPE(None, ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_void_p)
+
+
+class leiden_allocator(ct.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("release", _RELEASE_FN), ("ctx", ct.c_void_p)]
+
+
+def _torch_stream(ptr):
+    return torch.cuda.default_stream() if not ptr else torch.cuda.ExternalStream(ptr)
+
+
+class TorchAllocator:
+    """leiden_allocator backed by torch's caching allocator: a handle's device
+    memory is taken from (and returned to) torch's pool, on the stream the
+    library names.  Memory released on another stream than the one it was
+    allocated on is handed back only after that stream's enqueued work (the
+    allocating stream waits for an event recorded on it)."""
+
+    def __init__(self):
+        self._home = {}
+        self._lock = threading.Lock()
+        self._alloc_cb = _ALLOC_FN(self._alloc)
+        self._release_cb = _RELEASE_FN(self._release)
+        self.c = leiden_allocator(self._alloc_cb, self._release_cb, None)
+
+    def _alloc(self, ctx, nbytes, stream):
+        s = stream or 0
+        try:
+            p = torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(), s)
+        except RuntimeError:
+            return None
+        with self._lock:
+            self._home[p] = s
+        return p
+
+    def _release(self, ctx, ptr, nbytes, stream):
+        s = stream or 0
+        with self._lock:
+            home = self._home.pop(ptr, s)
+        if home != s:
+            ev = torch.cuda.Event()
+            ev.record(_torch_stream(s))
+            _torch_stream(home).wait_event(ev)
+        torch.cuda.caching_allocator_delete(ptr)
+
+
+_torch_alloc = None
+
+
+def torch_allocator() -> TorchAllocator:
+    global _torch_alloc
+    if _torch_alloc is None:
+        _torch_alloc = TorchAllocator()
+    return _torch_alloc
+
+
 _lib = None
 
 
@@ -104,7 +162,18 @@ def load() -> ct.CDLL:
     P, i64, i32, dbl = ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_double
     sig = {
         "leiden_default_params": (None, [P]),
-        "leiden_create": (i32, [i64, i64, P, P, P, P, P, P]),
+        "leiden_create": (i32, [i64, i64, P, P, P, P, P, P, P]),
+        "leiden_mark_affected": (i32, [P, P, i32, P, P, P, P]),
+        "leiden_fleet_create": (i32, [i32, P, P, P, P, P, P, P, P, P]),
+        "leiden_fleet_run": (i32, [P, i32, P, P, P, P, P, P, P, P, P]),
+        "leiden_fleet_get_graph": (i32, [P, i32, P, P, P, P, P]),
+        "leiden_fleet_get_state": (i32, [P, i32, P, P, P, P, P]),
+        "leiden_fleet_set_variant": (i32, [P, i32]),
+        "leiden_fleet_variant_info": (i32, [i32, P, P]),
+        "leiden_fleet_count": (i32, [P]),
+        "leiden_fleet_last_error": (ct.c_char_p, [P]),
+        "leiden_fleet_destroy": (i32, [P]),
+        "leiden_update_bytes": (i32, [P, i64, i64, P]),
         "leiden_destroy": (i32, [P]),
         "leiden_set_params": (i32, [P, P]),
         "leiden_static": (i32, [P, P, P, P, P]),
@@ -174,16 +243,19 @@ class Handle:
             self.ptr = None
 
 
-def leiden_create(off, idx, w, params: leiden_params | None = None) -> Handle:
-    """Copy a CSR graph (int64 offsets, int32 ids, float32 weights) into a new handle."""
+def leiden_create(off, idx, w, params: leiden_params | None = None, allocator="torch") -> Handle:
+    """Copy a CSR graph (int64 offsets, int32 ids, float32 weights) into a new handle.
+    allocator: "torch" (torch's caching allocator, the default) or None (the
+    library's own stream-ordered allocation)."""
     lib = load()
     off = _dev(off, torch.int64)
     idx = _dev(idx, torch.int32)
     w = _dev(w, torch.float32)
     n = off.numel() - 1
     out = ct.c_void_p()
+    al = ct.byref(torch_allocator().c) if allocator == "torch" else None
     st = lib.leiden_create(n, idx.numel(), _ptr(off), _ptr(idx), _ptr(w),
-                           ct.byref(params) if params is not None else None, _stream(), ct.byref(out))
+                           ct.byref(params) if params is not None else None, al, _stream(), ct.byref(out))
     _check(st, None, "leiden_create")
     return Handle(out, n)
 
@@ -238,6 +310,29 @@ def leiden_update(h: Handle, batch, mode, want_q: bool = True, trace: bool = Fal
     if tr is not None:
         tr = {k: v[:h.n] for k, v in tr.items()}
     return out, (q.value if want_q else None), st.to_dict(), tr
+
+
+def _cbatch(batch):
+    du, dv, iu, iv, iw = batch
+    return leiden_batch(du.numel(), _ptr(du), _ptr(dv), iu.numel(), _ptr(iu), _ptr(iv), _ptr(iw))
+
+
+def leiden_mark_affected(h: Handle, batch, mode):
+    """Flags leiden_update would compute for this batch, without changing the
+    handle: dict of uint8 tensors affected / in_range / changed (n each)."""
+    if isinstance(mode, str):
+        mode = MODES[mode]
+    tr = {k: torch.zeros(max(h.n, 1), dtype=torch.uint8, device="cuda") for k in ("affected", "in_range", "changed")}
+    b = _cbatch(batch)
+    _check(load().leiden_mark_affected(h.ptr, ct.byref(b), int(mode), _ptr(tr["affected"]), _ptr(tr["in_range"]),
+                                       _ptr(tr["changed"]), _stream()), h.ptr, "leiden_mark_affected")
+    return {k: v[:h.n] for k, v in tr.items()}
+
+
+def leiden_update_bytes(h: Handle, n_del: int, n_ins: int) -> int:
+    out = ct.c_int64(0)
+    _check(load().leiden_update_bytes(h.ptr, int(n_del), int(n_ins), ct.byref(out)), h.ptr, "leiden_update_bytes")
+    return out.value
 
 
 def leiden_update_many(handles, batches, modes, want_q: bool = True, max_parallel: int = 0):
@@ -374,3 +469,118 @@ def leiden_num_vertices(h: Handle) -> int:
 
 def leiden_num_entries(h: Handle) -> int:
     return int(load().leiden_num_entries(h.ptr))
+
+
+FLEET_STATIC = 0
+FLEET_VARIANTS = 6
+
+
+def fleet_variant_info(v: int):
+    """(wavefronts per workgroup, LDS table slots) of fleet launch variant v."""
+    w, sl = ct.c_int32(), ct.c_int32()
+    _check(load().leiden_fleet_variant_info(int(v), ct.byref(w), ct.byref(sl)), None, "leiden_fleet_variant_info")
+    return w.value, sl.value
+
+
+class Fleet:
+    """leiden_fleet_*: many small graphs updated together, one persistent
+    launch per run (see include/leiden.h)."""
+
+    def __init__(self, graphs, params: leiden_params | None = None, allocator="torch"):
+        lib = load()
+        self.ptr = ct.c_void_p()
+        self._dev = []
+        ns, nnzs, offs, idxs, ws = [], [], [], [], []
+        for off, idx, w in graphs:
+            off = _dev(off, torch.int64)
+            idx = _dev(idx, torch.int32)
+            w = _dev(w, torch.float32)
+            self._dev.append((off, idx, w))
+            ns.append(off.numel() - 1)
+            nnzs.append(idx.numel())
+        k = len(ns)
+        self.n = ns
+        N = (ct.c_int64 * k)(*ns)
+        Z = (ct.c_int64 * k)(*nnzs)
+        O = (ct.c_void_p * k)(*[_ptr(d[0]).value for d in self._dev])
+        I = (ct.c_void_p * k)(*[_ptr(d[1]).value for d in self._dev])
+        W = (ct.c_void_p * k)(*[_ptr(d[2]).value for d in self._dev])
+        al = ct.byref(torch_allocator().c) if allocator == "torch" else None
+        st = lib.leiden_fleet_create(k, N, Z, O, I, W, ct.byref(params) if params is not None else None, al,
+                                     _stream(), ct.byref(self.ptr))
+        self._dev = None
+        if st != OK:
+            raise LeidenError(st, "leiden_fleet_create")
+
+    def _err(self, st, what):
+        if st != OK:
+            msg = load().leiden_fleet_last_error(self.ptr).decode() or load().leiden_strerror(st).decode()
+            raise LeidenError(st, f"{what}: {msg}")
+
+    def set_variant(self, v: int):
+        self._err(load().leiden_fleet_set_variant(self.ptr, int(v)), "leiden_fleet_set_variant")
+
+    def run(self, jobs, want_membership: bool = True):
+        """jobs: list of (graph index, mode, batch) with mode "static" / "nd" /
+        "ds" / "df" (batch None for static, else make_batch tensors).  One
+        launch.  Returns (list of (membership or None, q, status, stats dict),
+        launch ms)."""
+        lib = load()
+        k = len(jobs)
+        G = (ct.c_int32 * k)(*[int(j[0]) for j in jobs])
+        M = (ct.c_int32 * k)(*[FLEET_STATIC if j[1] == "static" else MODES[j[1]] if isinstance(j[1], str) else int(j[1])
+                               for j in jobs])
+        B = (leiden_batch * k)()
+        keep = []
+        for q, (_, mode, batch) in enumerate(jobs):
+            if batch is not None:
+                B[q] = _cbatch(batch)
+                keep.append(batch)
+        outs = [torch.empty(max(self.n[int(j[0])], 1), dtype=torch.int32, device="cuda") if want_membership else None
+                for j in jobs]
+        O = (ct.c_void_p * k)(*[_ptr(o).value if o is not None else None for o in outs])
+        Q = (ct.c_double * k)()
+        ST = (ct.c_int32 * k)()
+        S = (leiden_stats * k)()
+        ms = ct.c_double(0.0)
+        st = lib.leiden_fleet_run(self.ptr, k, G, M, B, O if want_membership else None, Q, ST, S, ct.byref(ms),
+                                  _stream())
+        if st != OK and all(x == OK for x in ST):
+            self._err(st, "leiden_fleet_run")
+        res = []
+        for q in range(k):
+            n = self.n[int(jobs[q][0])]
+            res.append(((outs[q][:n] if outs[q] is not None else None), Q[q], int(ST[q]), S[q].to_dict()))
+        return res, ms.value
+
+    def get_graph(self, k: int):
+        lib = load()
+        nnz = ct.c_int64(0)
+        self._err(lib.leiden_fleet_get_graph(self.ptr, k, None, None, None, ct.byref(nnz), _stream()),
+                  "leiden_fleet_get_graph")
+        off = torch.empty(self.n[k] + 1, dtype=torch.int64, device="cuda")
+        idx = torch.empty(max(nnz.value, 1), dtype=torch.int32, device="cuda")
+        w = torch.empty(max(nnz.value, 1), dtype=torch.float32, device="cuda")
+        self._err(lib.leiden_fleet_get_graph(self.ptr, k, _ptr(off), _ptr(idx), _ptr(w), ct.byref(nnz), _stream()),
+                  "leiden_fleet_get_graph")
+        return off, idx[:nnz.value], w[:nnz.value]
+
+    def get_state(self, k: int):
+        n = self.n[k]
+        C = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+        K = torch.empty(max(n, 1), dtype=torch.float64, device="cuda")
+        S = torch.empty(max(n, 1), dtype=torch.float64, device="cuda")
+        m2 = ct.c_double(0.0)
+        self._err(load().leiden_fleet_get_state(self.ptr, k, _ptr(C), _ptr(K), _ptr(S), ct.byref(m2), _stream()),
+                  "leiden_fleet_get_state")
+        return C[:n], K[:n], S[:n], m2.value
+
+    def close(self):
+        if self.ptr:
+            load().leiden_fleet_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and _lib is not None:
+            _lib.leiden_fleet_destroy(self.ptr)
+            self.ptr = None

@@ -93,3 +93,25 @@ def test_server_argument_checks_without_a_device():
         f = getattr(lib, name)
         f.restype = ct.c_int32
         assert f(*args) == 1
+
+
+def test_boundary_argument_checks_without_a_device():
+    """Marking, the update-size estimate and the allocator are checked before
+    any HIP call."""
+    lib = ct.CDLL(LIB)
+    P, i32, i64 = ct.c_void_p, ct.c_int32, ct.c_int64
+    lib.leiden_mark_affected.restype = i32
+    lib.leiden_mark_affected.argtypes = [P, P, i32, P, P, P, P]
+    assert lib.leiden_mark_affected(None, None, 3, None, None, None, None) == 1
+    lib.leiden_update_bytes.restype = i32
+    lib.leiden_update_bytes.argtypes = [P, i64, i64, P]
+    out = ct.c_int64()
+    assert lib.leiden_update_bytes(None, 1, 1, ct.byref(out)) == 1
+    from paper_2405_11658_amd import leiden as L
+    half = L.leiden_allocator()          # alloc and release both NULL
+    lib.leiden_create.restype = i32
+    lib.leiden_create.argtypes = [i64, i64, P, P, P, P, P, P, P]
+    h = ct.c_void_p()
+    off = (ct.c_int64 * 2)(0, 0)
+    assert lib.leiden_create(1, 0, ct.cast(off, P), None, None, None, ct.byref(half), None, ct.byref(h)) == 1
+    assert lib.leiden_create(-1, 0, ct.cast(off, P), None, None, None, None, None, ct.byref(h)) == 1

@@ -113,3 +113,34 @@ def test_async_quality_vs_oracle_rmat():
     gaps = np.array(gaps)
     say("rmat15 async Q_gpu - Q_oracle:", np.round(gaps, 5).tolist(), "mean", round(float(gaps.mean()), 5))
     assert gaps.mean() >= -3e-3
+
+
+@pytest.mark.parametrize("name,g", [
+    ("planted4096_perm", gen.planted_partition(4096, 64, 0.1, 0.001, seed=1, permute=True)),
+    ("rmat12", gen.rmat(12, 16, seed=2)),
+    ("grid64", gen.grid2d(64, seed=3)),
+])
+def test_async_one_wavefront_is_the_serial_oracle(name, g):
+    """With one wavefront the asynchronous sweeps (local moving and
+    refinement) visit the vertices one at a time in ascending id order, which
+    is the oracle's serial asynchronous reading of Alg. leidenMove and
+    leidenRefine: static Leiden and ND / DS / DF updates must then give the
+    oracle's serial membership element by element (graphs without vertices
+    of degree > 2048, which take the multi-workgroup hub path)."""
+    assert np.diff(g.off).max() <= 2048
+    h = L.leiden_create(g.off, g.idx, g.w, L.leiden_default_params(async_waves=1))
+    C, q, st = L.leiden_static(h)
+    ref, rst = oracle.static(og(g))
+    assert np.array_equal(to_np(C), ref.C), name
+    assert st["move_iters"] == rst["move_iters"] and st["passes"] == rst["passes"]
+    say(name, "one-wavefront static equals the serial oracle, passes", st["passes"])
+    for k, mode in enumerate(("df", "ds", "nd")):
+        h = L.leiden_create(g.off, g.idx, g.w, L.leiden_default_params(async_waves=1))
+        L.leiden_set_state(h, ref.C)
+        b = gen.random_batch(g, gen.batch_count(g.nnz, 1e-3), seed=40 + k)
+        C, q, st, _ = L.leiden_update(h, dev_batch(b), mode)
+        new, _, _, ost = oracle.update(ref, ob(b), mode)
+        assert np.array_equal(to_np(C), new.C), (name, mode)
+        assert st["move_iters"] == ost["move_iters"] and st["moves_pass0"] == ost["moves_pass0"]
+        assert st["affected"] == ost["affected"] and st["changed"] == ost["changed"]
+        say(name, mode, "one-wavefront update equals the serial oracle")

@@ -31,3 +31,28 @@ def test_rmat_device_is_seeded():
     c = gen.rmat_device(9, 8, seed=6, device="cpu")
     assert all(np.array_equal(x.numpy(), y.numpy()) for x, y in zip(a[1:], b[1:]))
     assert not np.array_equal(a[2].numpy(), c[2].numpy())
+
+
+def test_device_batch_stream_valid_on_cpu_tensors():
+    """batch_stream_device (run here on CPU tensors): every deletion is an
+    existing edge, every insertion a non-edge without self-loop, nothing is
+    repeated across the stream, and the 80/20 split holds."""
+    import torch
+    g = gen.rmat(12, 16, seed=4)
+    off = torch.as_tensor(g.off)
+    idx = torch.as_tensor(g.idx)
+    bs = gen.batch_stream_device(g.n, off, idx, 50, 6, seed=3)
+    edges = set(zip(np.repeat(np.arange(g.n), np.diff(g.off)).tolist(), g.idx.tolist()))
+    seen = set()
+    for du, dv, iu, iv, iw in bs:
+        assert len(du) == 10 and len(iu) == 40 and bool((iw == 1).all())
+        for u, v in zip(du.tolist(), dv.tolist()):
+            assert (u, v) in edges
+            key = (min(u, v), max(u, v))
+            assert key not in seen
+            seen.add(key)
+        for u, v in zip(iu.tolist(), iv.tolist()):
+            assert u != v and (u, v) not in edges
+            key = (min(u, v), max(u, v))
+            assert key not in seen
+            seen.add(key)
