@@ -95,6 +95,12 @@ typedef struct {
   int32_t profile; /* 0 or 1 */
   int32_t async_waves; /* 0 .. 65536; 1 = one wavefront: the serial sweep */
   int32_t hub_slices;  /* 0 .. 256, asynchronous mode only */
+  int32_t verts_per_wave;        /* asynchronous sweeps: vertices with edges per
+                                    wavefront on the first level (0 = 1024) */
+  int32_t verts_per_wave_upper;  /* the same on aggregated levels (0 = 256) */
+  int32_t trim;        /* 1: every call releases its working buffers when it
+                          ends (stream-ordered; the graph and the community
+                          state stay), for many resident graphs; 0: kept */
 } leiden_params;
 
 #define LEIDEN_MAX_PASSES 64
@@ -279,6 +285,18 @@ typedef struct leiden_server leiden_server;
 leiden_status leiden_server_create(int32_t slots, int64_t memory_budget, leiden_server **out);
 leiden_status leiden_server_submit(leiden_server *server, leiden_handle *h, const leiden_batch *batch,
                                    int32_t mode, int32_t *membership_out, int64_t *request_id /* host */);
+/* A job for graph `graph` of a fleet (mode 0 static, or LEIDEN_ND / DS / DF
+ * with batch; see leiden_fleet_run).  Queued fleet jobs are gathered into
+ * one launch when a slot takes the first of them: every later queued job of
+ * the same fleet on another graph joins it (a graph's jobs run in submission
+ * order, one per launch); the fleet runs one launch at a time.  The batch and
+ * membership_out (device, nullable) must stay valid, and the fleet must not
+ * be used by the caller, until leiden_server_wait for the request returns;
+ * the reported service time is the launch's. */
+struct leiden_fleet;
+leiden_status leiden_server_submit_fleet(leiden_server *server, struct leiden_fleet *fleet, int32_t graph,
+                                         const leiden_batch *batch, int32_t mode, int32_t *membership_out,
+                                         int64_t *request_id /* host */);
 leiden_status leiden_server_wait(leiden_server *server, int64_t request_id, leiden_status *status,
                                  double *q_out, leiden_stats *stats, double *latency_ms,
                                  double *service_ms);

@@ -155,8 +155,10 @@ constexpr int64_t kAggRelabelMin = 1 << 20;  // level entries from which aggrega
 // Larger per-wavefront LDS tables when the level's average degree is high.
 bool wide_tables(int64_t nnz, int64_t with_edges) { return with_edges > 0 && nnz / with_edges > 128; }
 
-int level_waves(int cap, int64_t n, int pass) {
-  int64_t w = n / (pass == 0 ? kVertsPerWave : kVertsPerWaveUpper);
+int level_waves(const leiden_params &p, int cap, int64_t n, int pass) {
+  const int64_t vpw0 = p.verts_per_wave > 0 ? p.verts_per_wave : kVertsPerWave;
+  const int64_t vpw1 = p.verts_per_wave_upper > 0 ? p.verts_per_wave_upper : kVertsPerWaveUpper;
+  int64_t w = n / (pass == 0 ? vpw0 : vpw1);
   w = std::max<int64_t>(1, std::min<int64_t>(w, cap));
   return (int)(w < 4 ? w : w / 4 * 4);  // whole 4-wavefront workgroups, never above cap
 }
@@ -722,7 +724,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
       if (async) {
         // after the hubs: the other vertices then see the hubs' new communities
         hipEvent_t t0 = x.kp ? x.kp->begin() : nullptr;
-        move_async(ma, level_waves(NW, alen, pass), wide_tables(g.nnz, alen), x.s);
+        move_async(ma, level_waves(p, NW, alen, pass), wide_tables(g.nnz, alen), x.s);
         if (x.kp) x.kp->end(t0, LEIDEN_PROF_MOVE_SWEEP, 0, 0);
       }
       if (gi) tiled_sum(gi, nl, tiles, &sc->gain, x.s);
@@ -742,7 +744,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
       // indefinitely, each move scored as a gain; the tolerance test then
       // never passes.  Stop when the number of moves has not reached a new
       // minimum for kStallIters iterations in a row.
-      if (async && pass > 0 && level_waves(NW, alen, pass) > 1) {
+      if (async && pass > 0 && level_waves(p, NW, alen, pass) > 1) {
         if (r.moves < min_moves) {
           min_moves = r.moves;
           stall = 0;
@@ -797,7 +799,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
       refine_accept(ra, B.region.data(), x.s);
     }
     if (async) {
-      refine_async(ra, level_waves(NW, alen, pass), wide_tables(g.nnz, alen), x.s);
+      refine_async(ra, level_waves(p, NW, alen, pass), wide_tables(g.nnz, alen), x.s);
     }
     x.launched("refine sweep");
     const int rounds = 1;
@@ -891,7 +893,8 @@ bool valid_params(const leiden_params *p) {
          p->max_passes >= 1 && p->max_passes <= LEIDEN_MAX_PASSES && (p->sync_mode == 0 || p->sync_mode == 1) &&
          p->refine_variant >= 0 && p->refine_variant <= 2 && p->nslices >= 1 && p->nslices <= kMaxSlices &&
          (p->profile == 0 || p->profile == 1) && p->async_waves >= 0 && p->async_waves <= kMaxAsyncWaves &&
-         p->hub_slices >= 0 && p->hub_slices <= kMaxSlices;
+         p->hub_slices >= 0 && p->hub_slices <= kMaxSlices && (p->trim == 0 || p->trim == 1) &&
+         p->verts_per_wave >= 0 && p->verts_per_wave_upper >= 0;
 }
 
 }  // namespace
@@ -1052,12 +1055,21 @@ void leave(leiden_handle *h, hipStream_t s) {
   if (h->order && hipEventRecord(h->order, s) == hipSuccess) h->used = true;
   else (void)hipGetLastError();
 }
-// A call on handle h: ordered after the handle's previous work, guarded.
+// A call on handle h: ordered after the handle's previous work, guarded;
+// with leiden_params.trim the working buffers and the spare CSR are released
+// (stream-ordered) when it ends.
 leiden_status run_handle(leiden_handle *h, Ctx &x, const std::function<void()> &f) {
   leiden_status st = run_guarded(h->w, [&] {
     enter(x, h);
     f();
   });
+  if (h->prm.trim) {
+    h->w.release(x.s);
+    for (DBuf *b : {&h->t_off, &h->t_idx, &h->t_w}) {
+      h->w.al.put(b->p, b->cap, x.s);
+      *b = DBuf{};
+    }
+  }
   leave(h, x.s);
   return st;
 }
@@ -1079,6 +1091,9 @@ void leiden_default_params(leiden_params *p) {
   p->profile = 0;
   p->async_waves = 0;
   p->hub_slices = 0;
+  p->verts_per_wave = 0;
+  p->verts_per_wave_upper = 0;
+  p->trim = 0;
 }
 
 const char *leiden_strerror(int32_t status) {
@@ -1143,6 +1158,13 @@ leiden_status leiden_create(int64_t n, int64_t nnz, const int64_t *offsets, cons
     h->release(x.s);
     delete h;
     return st;
+  }
+  if (h->prm.trim) {
+    h->w.release(x.s);
+    for (DBuf *b : {&h->t_off, &h->t_idx, &h->t_w}) {
+      h->w.al.put(b->p, b->cap, x.s);
+      *b = DBuf{};
+    }
   }
   leave(h, x.s);
   *out = h;

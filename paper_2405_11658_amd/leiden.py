@@ -42,7 +42,8 @@ class leiden_params(ct.Structure):
                 ("max_iter", ct.c_int32), ("max_passes", ct.c_int32),
                 ("sync_mode", ct.c_int32), ("refine_variant", ct.c_int32), ("nslices", ct.c_int32),
                 ("profile", ct.c_int32), ("async_waves", ct.c_int32),
-                ("hub_slices", ct.c_int32)]
+                ("hub_slices", ct.c_int32), ("verts_per_wave", ct.c_int32),
+                ("verts_per_wave_upper", ct.c_int32), ("trim", ct.c_int32)]
 
 
 class leiden_stats(ct.Structure):
@@ -182,6 +183,7 @@ def load() -> ct.CDLL:
         "leiden_server_create": (i32, [i32, i64, P]),
         "leiden_server_submit": (i32, [P, P, P, i32, P, P]),
         "leiden_server_wait": (i32, [P, i64, P, P, P, P, P]),
+        "leiden_server_submit_fleet": (i32, [P, P, i32, P, i32, P, P]),
         "leiden_server_destroy": (i32, [P]),
         "leiden_modularity": (i32, [i64, P, P, P, P, P, P]),
         "leiden_aggregate": (i32, [i64, P, P, P, P, i64, P, P, P, P, P]),
@@ -379,6 +381,18 @@ class Server:
         _check(load().leiden_server_submit(self.ptr, h.ptr, ct.byref(b), int(mode), _ptr(out), ct.byref(rid)),
                None, "leiden_server_submit")
         self._pending[rid.value] = (out, b, batch, h)  # keep buffers alive until wait
+        return rid.value
+
+    def submit_fleet(self, fleet, graph: int, batch, mode) -> int:
+        """Queue a job on graph `graph` of a Fleet (mode "static" with batch
+        None, or "nd" / "ds" / "df"); returns the request id."""
+        m = FLEET_STATIC if mode == "static" else MODES[mode] if isinstance(mode, str) else int(mode)
+        b = _cbatch(batch) if batch is not None else None
+        out = torch.empty(max(fleet.n[graph], 1), dtype=torch.int32, device="cuda")
+        rid = ct.c_int64()
+        _check(load().leiden_server_submit_fleet(self.ptr, fleet.ptr, int(graph), ct.byref(b) if b is not None else None,
+                                                 int(m), _ptr(out), ct.byref(rid)), None, "leiden_server_submit_fleet")
+        self._pending[rid.value] = (out, b, batch, fleet)
         return rid.value
 
     def wait(self, rid: int):
