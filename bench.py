@@ -1,43 +1,47 @@
 #!/usr/bin/env python3
 """Dynamic Frontier Leiden update benchmark on one MI355X.
 
-Workload (synthetic, seeded): RMAT scale 22, edge factor 16 with
-(a, b, c) = (0.57, 0.19, 0.19), symmetrised, self-loops and repeated edges
-removed, vertex ids randomly permuted, unit float32 weights (4,194,304
-vertices, ~128.3M directed CSR entries).  Static Leiden runs once; then a
-stream of batches, each of round(f * |E|) undirected updates (80% insertions
-of uniformly random non-edges, 20% deletions of uniformly chosen existing
-edges; Sec. 5.1.4), is applied with the Dynamic Frontier front-end
-(Sec. 4.5, Alg. "dynamicFrontier").  The batches of the whole run are drawn
-up front (disjoint, so they apply one after another) and copied to HBM before
-any timing.
+Headline workload (synthetic, seeded; the largest single-GPU configuration):
+RMAT scale 26, edge factor 16, (a, b, c) = (0.57, 0.19, 0.19), symmetrised,
+self-loops and repeated edges removed, vertex ids randomly permuted, unit
+float32 weights - 67,108,864 vertices and ~2.10e9 directed CSR entries, hubs
+of degree above 1e5 - generated on the device.  Static Leiden runs on it,
+then a stream of batches of round(1e-4 |E|) undirected updates each (80 %
+insertions of uniformly random non-edges, 20 % deletions of uniformly chosen
+existing edges; Sec. 5.1.4) is applied one after another with the Dynamic
+Frontier front-end (Sec. 4.5, Alg. "dynamicFrontier"): --warmup batches
+untimed, then --steps (default 10) timed.  The batches are drawn up front
+(disjoint, so they apply in order) and are resident in HBM before timing.
 
 One step = one leiden_update(mode=DF) call through the C ABI: batch
 validation and graph update, DF marking, changedCommunities, updateWeights,
-the pass loop (local-moving, refinement, aggregation), final relabel, and the
-modularity of the result (Eq. 1).  `value` is |E^t| / (wall time per step)
-over the timed steps; latencies p50/p99 come from HIP events inside the
-library and exclude the graph update, which the paper does not time
-(Sec. 5.1.4).  Static Leiden on the same graph is timed for the comparison.
-Modularity: the mean over the last five updates against the mean of
---static-reps static runs on the final graph (both are asynchronous heuristics
-whose results vary from run to run by about 1e-3).
+the pass loop (local-moving, refinement, aggregation), final relabel and the
+modularity of the result (Eq. 1).  `value` = |E^t| / (wall time per step) over
+the timed steps; latencies p50/p99 come from HIP events inside the library and
+exclude the graph update, which the paper does not time (Sec. 5.1.4).  Static
+Leiden on the same graph is timed for the comparison; modularity of the last
+updates is compared with static runs on the final graph (both asynchronous,
+so means are compared).
 
-roofline: the timed kernel (leiden_params.profile) with the largest share of
-the timed steps; achieved = algorithmic bytes / event-timed duration.
+The RMAT-22 configuration (4,194,304 vertices, ~128.3M entries) is measured
+as well (key "rmat22": static and DF p50 on the same kind of stream, and the
+DF update's modularity against the serial oracle's from the same installed
+membership); it is also where the oracle runs: cpu_baseline is the serial C
+oracle (test infrastructure) doing one DF update of the first RMAT-22 batch
+after its own static run (untimed preparation), edges/s = |E^t| / its time,
+one host thread.  The oracle cannot run the RMAT-26 stream within minutes.
+
+roofline: the kernel timed by the library (leiden_params.profile: HIP events
+around each launch, on the call's stream) with the largest share of the timed
+steps; achieved = algorithmic bytes per launch / average launch time.
 Algorithmic bytes per unit: hub gather 12 B per scanned entry (id, weight,
 community of the neighbour); aggregation merge 12 B per entry plus 12 B per
-member vertex (community-CSR entry and its community); modularity scan 12 B
-per entry plus 4 B per vertex; graph-update merge 16 B per entry (read and
-write of id + weight) plus 16 B per vertex (old and new offsets); asynchronous
-local-moving sweep 12 B per scanned edge (id, weight, community of the
-neighbour) plus 34 B per evaluated vertex (list entry, two offsets, range and
-processed flags, community, K); Sigma reads and neighbour marks are not
-counted (a lower bound).
-
-cpu_baseline: the serial C oracle (test infrastructure) on the same graph and
-first batch: its own static run (untimed preparation), then one DF update,
-timed; edges/s = |E^t| / that time; one host thread.
+member vertex; modularity scan 12 B per entry plus 4 B per vertex; graph
+update merge 16 B per entry plus 16 B per vertex; asynchronous local-moving
+sweep 12 B per scanned edge plus 34 B per evaluated vertex (Sigma reads and
+neighbour marks not counted: a lower bound).  traffic = HBM bytes per launch
+from the committed counter runs (profiles/traffic.json) when they were taken
+on the current kernel sources and this workload, else null.
 """
 from __future__ import annotations
 
@@ -63,7 +67,7 @@ BYTES_PER_UNIT = {  # (per entry, per vertex)
 }
 PROF_KERNEL_NAMES = {  # symbol of each timed kernel, as rocprofv3 lists it
     "hub_gather": "lk::k_hub_gather(lk::MoveArgs)",
-    "agg_merge": "lk::k_agg_items(lk::AggArgs, long)",
+    "agg_merge": "lk::k_agg_keys",
     "mod_scan": "lk::k_mod_edges",
     "batch_merge": "lk::k_batch_apply_old(lk::BatchArgs)",
     "move_sweep": "lk::k_move_async",  # both launch shapes, <4, 512> and <2, 2048>
@@ -82,18 +86,18 @@ def ratio(a, b):
     return round(a / b, 4) if b else None
 
 
-def measured_traffic(kernel: str):
-    """Bytes per launch of `kernel` from the committed counter runs
-    (profiles/traffic.json: FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy),
-    or None when there is none for the kernels as they are now (the entry
-    records a hash of the kernel sources it was measured on)."""
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed counter runs
+    (profiles/traffic.json: FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB
+    copy), or None when there is none for this workload and the kernels as
+    they are now (each entry records a hash of the kernel sources)."""
     import glob
     import hashlib
     path = os.path.join(HERE, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     entry = json.load(open(path)).get(kernel)
-    if not entry:
+    if not entry or entry.get("workload") != workload:
         return None
     h = hashlib.sha256()
     for p in sorted(glob.glob(os.path.join(HERE, "paper_2405_11658_amd", "csrc", "*"))):
@@ -113,18 +117,64 @@ def cpu_model() -> str:
     return "unknown"
 
 
+def run_stream(L, torch, h, batches, warmup, steps, mode, static_reps, tag):
+    """Static runs, warm-up updates, timed updates (with kernel timing),
+    static runs on the final graph.  Returns a dict of measurements."""
+    static_ms = []
+    q_static0 = None
+    for r in range(max(1, static_reps)):
+        _, q_static0, st = L.leiden_static(h)
+        static_ms.append(st["ms_total"])
+        log(f"{tag} static #{r}: {st['ms_total']:.2f} ms Q={q_static0:.6f} passes={st['passes']}")
+    static_timed = static_ms[1:] if len(static_ms) > 1 else static_ms
+    for k in range(warmup):
+        _, q, st, _ = L.leiden_update(h, batches[k], mode)
+        log(f"{tag} warmup {k}: {st['ms_total']:.2f} ms Q={q:.6f} passes={st['passes']}")
+    L.leiden_set_params(h, L.leiden_default_params(profile=1))
+    lat, lat_all, ents, qs, passes = [], [], [], [], []
+    prof = {name: {"launches": 0, "ms": 0.0, "entries": 0, "vertices": 0} for name in L.PROF_KERNELS}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        _, q, st, _ = L.leiden_update(h, batches[warmup + k], mode)
+        lat.append(st["ms_total"] - st["ms_apply"])
+        lat_all.append(st["ms_total"])
+        qs.append(q)
+        passes.append(st["passes"])
+        for name, v in st["prof"].items():
+            for key in v:
+                prof[name][key] += v[key]
+        ents.append(st["level_entries"][0] if st["passes"] else 0)
+        log(f"{tag} step {k}: {st['ms_total']:.2f} ms (apply {st['ms_apply']:.2f}) Q={q:.6f} "
+            f"affected={st['affected']} passes={st['passes']} iters={st['move_iters']}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    L.leiden_set_params(h, L.leiden_default_params())
+    q_static_final = []
+    for r in range(max(1, static_reps)):
+        _, q, st = L.leiden_static(h)
+        q_static_final.append(q)
+        log(f"{tag} static on final graph #{r}: {st['ms_total']:.2f} ms Q={q:.6f}")
+    tail = qs[-5:]
+    return {"lat": lat, "lat_all": lat_all, "ents": ents, "qs": qs, "passes": passes, "prof": prof,
+            "wall": wall, "static_ms": static_timed, "q_static0": q_static0,
+            "q_static_final": q_static_final, "q_tail": float(np.mean(tail)),
+            "q_static_mean": float(np.mean(q_static_final))}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--scale", type=int, default=22)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--scale", type=int, default=26)
     ap.add_argument("--edge-factor", type=int, default=16)
     ap.add_argument("--frac", type=float, default=1e-4, help="batch size as a fraction of |E|")
     ap.add_argument("--mode", default="df", choices=["df", "ds", "nd"])
-    ap.add_argument("--static-reps", type=int, default=3)
+    ap.add_argument("--static-reps", type=int, default=2)
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg")
+    ap.add_argument("--no-rmat22", action="store_true", help="skip the RMAT-22 leg (and the oracle)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with a 1 GiB device-to-device copy (reference for counter runs)")
     args = ap.parse_args()
@@ -145,75 +195,32 @@ def main() -> int:
         raise SystemExit("bench.py: no HIP device visible")
     torch.cuda.set_device(0)
     L.load()
+    workload = f"rmat{args.scale}_ef{args.edge_factor}_{args.mode}_f{args.frac:g}_stream{args.steps}"
 
+    # ---- the headline stream on the device-generated graph ----
     t = time.time()
-    g = gen.rmat(args.scale, args.edge_factor, seed=args.seed)
-    log(f"graph: RMAT scale {args.scale} ef {args.edge_factor}: n={g.n} entries={g.nnz} ({time.time() - t:.1f}s)")
-    B = gen.batch_count(g.nnz, args.frac)
-    nb = args.warmup + args.steps
+    n, off, idx, w = gen.rmat_device(args.scale, args.edge_factor, seed=args.seed)
+    nnz0 = idx.numel()
+    torch.cuda.synchronize()
+    log(f"graph: RMAT scale {args.scale} ef {args.edge_factor}: n={n} entries={nnz0} ({time.time() - t:.1f}s)")
+    B = gen.batch_count(nnz0, args.frac)
     t = time.time()
-    batches_h = gen.batch_stream(g, B, nb, seed=args.seed + 1000)
-    log(f"batches: {nb} x {B} updates ({time.time() - t:.1f}s)")
-
-    h = L.leiden_create(g.off, g.idx, g.w, L.leiden_default_params())
-    batches = [L.make_batch(b.del_u, b.del_v, b.ins_u, b.ins_v, b.ins_w) for b in batches_h]
+    batches = gen.batch_stream_device(n, off, idx, B, args.warmup + args.steps, seed=args.seed + 1000)
     torch.cuda.synchronize()
-
-    # static Leiden on the initial graph (the first run also warms up)
-    static_ms = []
-    q_static0 = None
-    for r in range(max(1, args.static_reps)):
-        _, q_static0, st = L.leiden_static(h)
-        static_ms.append(st["ms_total"])
-        log(f"static #{r}: {st['ms_total']:.2f} ms Q={q_static0:.6f} passes={st['passes']}")
-    static_ms_timed = static_ms[1:] if len(static_ms) > 1 else static_ms
-
-    q_first = None
-    for k in range(args.warmup):
-        _, q, st, _ = L.leiden_update(h, batches[k], args.mode)
-        if k == 0:
-            q_first = q
-        log(f"warmup {k}: {st['ms_total']:.2f} ms Q={q:.6f}")
-
-    L.leiden_set_params(h, L.leiden_default_params(profile=1))
-    lat, lat_all, ents, qs = [], [], [], []
-    prof = {name: {"launches": 0, "ms": 0.0, "entries": 0, "vertices": 0} for name in L.PROF_KERNELS}
+    log(f"batches: {args.warmup + args.steps} x {B} updates ({time.time() - t:.1f}s)")
+    h = L.leiden_create(off, idx, w, L.leiden_default_params())
+    del off, idx, w
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        _, q, st, _ = L.leiden_update(h, batches[args.warmup + k], args.mode)
-        lat.append(st["ms_total"] - st["ms_apply"])
-        lat_all.append(st["ms_total"])
-        qs.append(q)
-        for name, v in st["prof"].items():
-            for key in v:
-                prof[name][key] += v[key]
-        ents.append(st["level_entries"][0] if st["passes"] else 0)
-        log(f"step {k}: {st['ms_total']:.2f} ms (apply {st['ms_apply']:.2f}) Q={q:.6f} "
-            f"affected={st['affected']} passes={st['passes']}")
+    torch.cuda.empty_cache()
+    r = run_stream(L, torch, h, batches, args.warmup, args.steps, args.mode, args.static_reps, "main")
+    del h, batches
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    L.leiden_set_params(h, L.leiden_default_params())
-    if q_first is None:
-        q_first = qs[0]
+    torch.cuda.empty_cache()
 
-    ms_per_step = wall * 1e3 / args.steps
-    entries = float(np.mean(ents))
+    ms_per_step = r["wall"] * 1e3 / args.steps
+    entries = float(np.mean(r["ents"]))
     value = entries / (ms_per_step / 1e3)
-
-    # static Leiden on the final graph: modularity reference for the updates.
-    # Both sides are asynchronous heuristics whose modularity varies from run
-    # to run by about 1e-3, so the comparison is of means: the last five
-    # updates against several static runs on the final graph.
-    q_static_final = []
-    for r in range(max(1, args.static_reps)):
-        _, q, st = L.leiden_static(h)
-        q_static_final.append(q)
-        log(f"static on final graph #{r}: {st['ms_total']:.2f} ms Q={q:.6f}")
-    q_upd_tail = float(np.mean(qs[-5:]))
-    q_stat_mean = float(np.mean(q_static_final))
-
-    # roofline of the timed kernel with the largest total time
+    prof = r["prof"]
     dom = max(prof, key=lambda k: prof[k]["ms"])
     pd = prof[dom]
     roofline = None
@@ -223,33 +230,63 @@ def main() -> int:
         avg_ms = pd["ms"] / pd["launches"]
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(PROF_KERNEL_NAMES[dom]),
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic(PROF_KERNEL_NAMES[dom], workload),
                     "kernel": PROF_KERNEL_NAMES[dom], "avg_launch_us": round(avg_ms * 1e3, 2),
                     "launches_per_step": pd["launches"] / args.steps,
                     "algorithmic_bytes_per_launch": round(bytes_per_launch),
                     "share_of_step": round(pd["ms"] / args.steps / ms_per_step, 4)}
+    kernels = {name: {"ms_per_step": round(v["ms"] / args.steps, 3), "launches_per_step": v["launches"] / args.steps}
+               for name, v in prof.items() if v["launches"]}
 
+    # ---- RMAT-22: GPU stream, and the oracle (cpu_baseline, same-state gap) ----
+    c2 = None
     cpu = None
-    q_oracle_first = None
-    if not args.no_cpu_baseline:
-        import oracle
-        oracle.build()
-        og = oracle.as_graph(g.n, g.off, g.idx, g.w)
-        t = time.perf_counter()
-        ost, _ = oracle.static(og, oracle.make_params())
-        t_static = time.perf_counter() - t
-        log(f"oracle static: {t_static:.1f}s")
-        b = batches_h[0]
-        t = time.perf_counter()
-        ost2, _, _, _ = oracle.update(ost, oracle.Batch(b.del_u, b.del_v, b.ins_u, b.ins_v, b.ins_w),
-                                      args.mode, oracle.make_params())
-        t_upd = time.perf_counter() - t
-        q_oracle_first = oracle.modularity(ost2.g, ost2.C)
-        log(f"oracle {args.mode} update: {t_upd:.2f}s Q={q_oracle_first:.6f}")
-        cpu = {"value": ratio(ost2.g.nnz, t_upd), "unit": "edges/s", "cores": 1, "kind": "oracle",
-               "sample": (f"one {args.mode.upper()} update (batch 0, {B} updates) of the serial oracle on "
-                          f"the same graph after its own static run ({t_static:.1f}s, untimed); "
-                          f"update {t_upd:.2f}s; host CPU {cpu_model()}, os.cpu_count()={os.cpu_count()}")}
+    if not args.no_rmat22:
+        t = time.time()
+        g = gen.rmat(22, 16, seed=args.seed)
+        log(f"rmat22: n={g.n} entries={g.nnz} ({time.time() - t:.1f}s)")
+        B2 = gen.batch_count(g.nnz, args.frac)
+        bh = gen.batch_stream(g, B2, 2 + 10, seed=args.seed + 1000)
+        b2 = [L.make_batch(b.del_u, b.del_v, b.ins_u, b.ins_v, b.ins_w) for b in bh]
+        h2 = L.leiden_create(g.off, g.idx, g.w, L.leiden_default_params())
+        r2 = run_stream(L, torch, h2, b2, 2, 10, args.mode, args.static_reps, "rmat22")
+        del h2
+        c2 = {"workload": f"rmat22_ef16_{args.mode}_f{args.frac:g}", "entries": int(g.nnz), "batch_updates": B2,
+              "latency_ms": {"p50": round(pct(r2["lat"], 50), 3), "p99": round(pct(r2["lat"], 99), 3)},
+              "edges_per_s": round(float(np.mean(r2["ents"])) / (r2["wall"] / 10), 1),
+              "static_ms_p50": round(pct(r2["static_ms"], 50), 3),
+              "speedup_vs_static": ratio(pct(r2["static_ms"], 50), pct(r2["lat"], 50)),
+              "passes": r2["passes"],
+              "dq_update_vs_static": r2["q_tail"] - r2["q_static_mean"]}
+        if not args.no_cpu_baseline:
+            import oracle
+            oracle.build()
+            og = oracle.as_graph(g.n, g.off, g.idx, g.w)
+            t = time.perf_counter()
+            ost, _ = oracle.static(og, oracle.make_params())
+            t_static = time.perf_counter() - t
+            log(f"oracle static: {t_static:.1f}s")
+            b = bh[0]
+            t = time.perf_counter()
+            ost2, _, _, _ = oracle.update(ost, oracle.Batch(b.del_u, b.del_v, b.ins_u, b.ins_v, b.ins_w),
+                                          args.mode, oracle.make_params())
+            t_upd = time.perf_counter() - t
+            q_or = oracle.modularity(ost2.g, ost2.C)
+            log(f"oracle {args.mode} update: {t_upd:.2f}s Q={q_or:.6f}")
+            # the library's update of the same batch from the oracle's membership
+            h3 = L.leiden_create(g.off, g.idx, g.w, L.leiden_default_params())
+            L.leiden_set_state(h3, ost.C)
+            _, q_gpu, st3, _ = L.leiden_update(h3, b2[0], args.mode)
+            del h3
+            c2["same_state_first_batch"] = {"q_gpu": q_gpu, "q_oracle": q_or, "dq": q_gpu - q_or,
+                                            "gpu_ms": round(st3["ms_total"] - st3["ms_apply"], 3),
+                                            "oracle_s": round(t_upd, 3)}
+            cpu = {"value": ratio(ost2.g.nnz, t_upd), "unit": "edges/s", "cores": 1, "kind": "oracle",
+                   "sample": (f"RMAT-22 ef16 (the RMAT-26 stream is beyond the serial oracle's minutes): one "
+                              f"{args.mode.upper()} update of {B2} updates after the oracle's own static run "
+                              f"({t_static:.1f}s, untimed); update {t_upd:.2f}s; host CPU {cpu_model()}, "
+                              f"os.cpu_count()={os.cpu_count()}")}
 
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -259,6 +296,7 @@ def main() -> int:
         torch.cuda.synchronize()
         log("1 GiB calibration copy done")
 
+    lat = r["lat"]
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -272,22 +310,21 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"rmat{args.scale}_ef{args.edge_factor}_{args.mode}_f{args.frac:g}",
-                   "n": g.n, "entries": int(g.nnz), "batch_updates": B, "mode": args.mode,
-                   "hub_slices": 64},
+        "config": {"workload": workload, "n": n, "entries": int(nnz0), "batch_updates": B, "mode": args.mode},
         "latency_ms": {"p50": round(pct(lat, 50), 3), "p99": round(pct(lat, 99), 3),
                        "mean": round(float(np.mean(lat)), 3)},
-        "latency_with_graph_update_ms": {"p50": round(pct(lat_all, 50), 3), "p99": round(pct(lat_all, 99), 3)},
+        "latency_with_graph_update_ms": {"p50": round(pct(r["lat_all"], 50), 3),
+                                         "p99": round(pct(r["lat_all"], 99), 3)},
         "updates_per_s": ratio(B * 1e3, pct(lat, 50)),
-        "static_ms": {"p50": round(pct(static_ms_timed, 50), 3), "reps": len(static_ms_timed)},
-        "speedup_vs_static": ratio(pct(static_ms_timed, 50), pct(lat, 50)),
-        "modularity": {"update_last": qs[-1], "update_last5_mean": q_upd_tail,
-                       "static_final_graph": q_static_final, "static_final_mean": q_stat_mean,
-                       "dq_update_vs_static": q_upd_tail - q_stat_mean,
-                       "update_first": q_first, "oracle_update_first": q_oracle_first,
-                       "dq_vs_oracle": (q_first - q_oracle_first) if q_oracle_first is not None else None,
-                       "static_initial": q_static0},
+        "static_ms": {"p50": round(pct(r["static_ms"], 50), 3), "reps": len(r["static_ms"])},
+        "speedup_vs_static": ratio(pct(r["static_ms"], 50), pct(lat, 50)),
+        "passes": r["passes"],
+        "modularity": {"update_last": r["qs"][-1], "update_last5_mean": r["q_tail"],
+                       "static_final_graph": r["q_static_final"], "static_final_mean": r["q_static_mean"],
+                       "dq_update_vs_static": r["q_tail"] - r["q_static_mean"], "static_initial": r["q_static0"]},
+        "kernels": kernels,
         "roofline": roofline,
+        "rmat22": c2,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

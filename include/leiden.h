@@ -98,6 +98,9 @@ typedef struct {
   int32_t verts_per_wave;        /* asynchronous sweeps: vertices with edges per
                                     wavefront on the first level (0 = 1024) */
   int32_t verts_per_wave_upper;  /* the same on aggregated levels (0 = 256) */
+  int32_t hub_degree;  /* asynchronous mode: vertices of higher degree move in
+                          the hub slices before each sweep (0 = 2048;
+                          64 .. 2048) */
   int32_t trim;        /* 1: every call releases its working buffers when it
                           ends (stream-ordered; the graph and the community
                           state stay), for many resident graphs; 0: kept */

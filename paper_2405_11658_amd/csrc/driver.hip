@@ -389,14 +389,15 @@ struct Layout {
   int64_t nhub;
 };
 
-Layout level_layout(Ctx &x, const Level &g, int S, int32_t *region_dev, int32_t *counts_tmp, int32_t *scnt,
+Layout level_layout(Ctx &x, const Level &g, int S, int64_t hubdeg, int32_t *region_dev, int32_t *counts_tmp,
+                    int32_t *scnt,
                     int32_t *soff_dev, int32_t *sfill, int32_t *vbyslice) {
   Layout L;
   L.S = S;
   const int nb = S * kNB;
   x.zero(counts_tmp, nb);
   x.zero(scnt, S);
-  slice_hist(g.off, g.n, S, counts_tmp, scnt, x.s);
+  slice_hist(g.off, g.n, S, hubdeg, counts_tmp, scnt, x.s);
   x.launched("slice_hist");
   int32_t *hp = (int32_t *)x.pin();
   x.check(hipMemcpyAsync(hp, counts_tmp, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, x.s), "D2H");
@@ -447,7 +448,7 @@ struct HubHost {
   std::vector<int64_t> hs, qs, gs;  // per-slice starts (S+1): hubs, chunks, segments
 };
 
-HubHost hub_plan(Ctx &x, const Level &g, int S, const Layout &B) {
+HubHost hub_plan(Ctx &x, const Level &g, int S, int64_t hubdeg, const Layout &B) {
   HubHost H;
   memset(&H.p, 0, sizeof(H.p));
   H.hs.assign(S + 1, 0);
@@ -465,7 +466,7 @@ HubHost hub_plan(Ctx &x, const Level &g, int S, const Layout &B) {
   x.check(hipMemcpyAsync(hsoff, up, sizeof(int32_t) * (S + 1), hipMemcpyHostToDevice, x.s), "H2D");
   x.zero(hfill, S);
   H.p.hubv = x.get<int32_t>(H_v, nh);
-  hub_find(g.off, g.n, S, hsoff, hfill, H.p.hubv, x.s);
+  hub_find(g.off, g.n, S, hubdeg, hsoff, hfill, H.p.hubv, x.s);
   int64_t *cnt = x.get<int64_t>(H_cnt, 3 * (nh + 1));
   hub_sizes(g.off, H.p.hubv, nh, cnt, cnt + (nh + 1), cnt + 2 * (nh + 1), x.s);
   x.launched("hub plan");
@@ -629,6 +630,9 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
   double *tiles = x.get<double>(L_tiles, n / 256 + 2);
   uint8_t *act = x.get<uint8_t>(L_act, n);
   const bool async = p.sync_mode == 0;
+  // degree above which a vertex moves in the hub slices before the sweep
+  // (asynchronous mode); the synchronous mode keeps the table-size boundary
+  const int64_t hubdeg = (async && p.hub_degree > 0) ? p.hub_degree : kHubDeg;
   const int NW = async ? (p.async_waves > 0 ? p.async_waves : kDefaultAsyncWaves) : 0;
   int *akeys = async ? x.get<int>(W_keys, (int64_t)NW * 2 * kHubDeg) : nullptr;
   double *avals = async ? x.get<double>(W_vals, (int64_t)NW * 2 * kHubDeg) : nullptr;
@@ -655,8 +659,8 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
   for (pass = 0; pass < p.max_passes; ++pass) {
     tm.pass = pass;
     const int64_t nl = g.n;
-    const Layout B = level_layout(x, g, NS, region, counts, scnt, soff, sfill, vbs);
-    const HubHost hh = hub_plan(x, g, NS, B);
+    const Layout B = level_layout(x, g, NS, hubdeg, region, counts, scnt, soff, sfill, vbs);
+    const HubHost hh = hub_plan(x, g, NS, hubdeg, B);
     const int64_t alen = B.region[NS * kNB];  // vertices with edges
     int32_t *alist = nullptr;
     if (async && alen > 0) {
@@ -686,10 +690,12 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     ma.sweep_work = x.kp && x.kp->on ? sc->sweep_work : nullptr;
     ma.anext = &sc->anext; ma.akeys = akeys; ma.avals = avals;
     ma.alist = alist; ma.alen = alen;
+    ma.hubdeg = hubdeg;
     int li = 0;
     int64_t moves_total = 0;
     unsigned long long min_moves = ~0ull;
     int stall = 0;
+    bool stalled = false;
     tm.mark(CAT_OTHER);
     for (int it = 0; it < p.max_iter; ++it) {
       reset_iter(counts, NS * kNB, &sc->gain, &sc->moves, async ? &sc->anext : nullptr, x.s);
@@ -743,12 +749,15 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
       // that concurrently processed neighbours are changing can trade places
       // indefinitely, each move scored as a gain; the tolerance test then
       // never passes.  Stop when the number of moves has not reached a new
-      // minimum for kStallIters iterations in a row.
+      // minimum for kStallIters iterations in a row - the level has converged
+      // up to those trades, so the pass counts as converged for the stop
+      // test of the pass loop below.
       if (async && pass > 0 && level_waves(p, NW, alen, pass) > 1) {
         if (r.moves < min_moves) {
           min_moves = r.moves;
           stall = 0;
         } else if (++stall >= kStallIters) {
+          stalled = true;
           break;
         }
       }
@@ -779,6 +788,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     ra.refined = &sc->refined;
     ra.anext = &sc->anext; ra.akeys = akeys; ra.avals = avals;
     ra.alist = alist; ra.alen = alen;
+    ra.hubdeg = hubdeg;
     reset_iter(counts, NS * kNB, nullptr, &sc->refined, async ? &sc->anext : nullptr, x.s);
     refine_break(ra, x.s);
     x.launched("break");
@@ -809,7 +819,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
       st->refined_vertices[pass] = (int64_t)x.read(&sc->refined);
       st->passes = pass + 1;
     }
-    if ((pass > 0 || p.refine_variant == 2) && li <= 1) {
+    if ((pass > 0 || p.refine_variant == 2) && (li <= 1 || stalled)) {
       if (st && pass < LEIDEN_MAX_PASSES) {
         // communities of this level, for the statistics only
         int32_t *tmpC = x.get<int32_t>(L_CB, nl);
@@ -894,7 +904,8 @@ bool valid_params(const leiden_params *p) {
          p->refine_variant >= 0 && p->refine_variant <= 2 && p->nslices >= 1 && p->nslices <= kMaxSlices &&
          (p->profile == 0 || p->profile == 1) && p->async_waves >= 0 && p->async_waves <= kMaxAsyncWaves &&
          p->hub_slices >= 0 && p->hub_slices <= kMaxSlices && (p->trim == 0 || p->trim == 1) &&
-         p->verts_per_wave >= 0 && p->verts_per_wave_upper >= 0;
+         p->verts_per_wave >= 0 && p->verts_per_wave_upper >= 0 && p->hub_degree >= 0 &&
+         p->hub_degree <= kHubDeg && (p->hub_degree == 0 || p->hub_degree >= 64);
 }
 
 }  // namespace
@@ -1093,6 +1104,7 @@ void leiden_default_params(leiden_params *p) {
   p->hub_slices = 0;
   p->verts_per_wave = 0;
   p->verts_per_wave_upper = 0;
+  p->hub_degree = 0;
   p->trim = 0;
 }
 

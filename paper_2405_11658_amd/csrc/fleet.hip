@@ -138,7 +138,8 @@ struct leiden_fleet {
   int exec_variant = -1;
   hipEvent_t t0 = nullptr, t1 = nullptr;
   hipStream_t last = nullptr;
-  bool used = false;
+  bool used = false;           // a call has enqueued work (recorded in `order`)
+  hipEvent_t order = nullptr;  // end of the latest call's work
 
   void check(hipError_t e, const char *what) {
     if (e != hipSuccess) {
@@ -282,18 +283,26 @@ bool valid_params(const leiden_params *p) {
          p->max_passes <= kFleetMaxPasses && p->refine_variant >= 0 && p->refine_variant <= 2;
 }
 
+// A call on a stream other than the previous call's first waits for the
+// fleet's latest work, recorded at the end of every call (the previous
+// stream itself may no longer exist).
 void enter(leiden_fleet *f, hipStream_t s) {
-  if (f->used && f->last != s) {
-    hipEvent_t e;
-    f->check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
-    const hipError_t r1 = hipEventRecord(e, f->last);
-    const hipError_t r2 = hipStreamWaitEvent(s, e, 0);
-    (void)hipEventDestroy(e);
-    f->check(r1, "hipEventRecord");
-    f->check(r2, "hipStreamWaitEvent");
-  }
+  if (!f->order) f->check(hipEventCreateWithFlags(&f->order, hipEventDisableTiming), "hipEventCreate");
+  if (f->used && f->last != s) f->check(hipStreamWaitEvent(s, f->order, 0), "hipStreamWaitEvent");
   f->last = s;
-  f->used = true;
+}
+void leave(leiden_fleet *f, hipStream_t s) {
+  if (f->order && hipEventRecord(f->order, s) == hipSuccess) f->used = true;
+  else (void)hipGetLastError();
+}
+// A fleet call: ordered after the fleet's previous work, guarded.
+leiden_status run_fleet(leiden_fleet *f, hipStream_t s, const std::function<void()> &fn) {
+  const leiden_status st = guarded(f, [&] {
+    enter(f, s);
+    fn();
+  });
+  leave(f, s);
+  return st;
 }
 
 }  // namespace
@@ -322,8 +331,7 @@ leiden_status leiden_fleet_create(int32_t count, const int64_t *n, const int64_t
     f->al.custom = true;
   }
   hipStream_t s = (hipStream_t)stream;
-  const leiden_status st = guarded(f, [&] {
-    enter(f, s);
+  const leiden_status st = run_fleet(f, s, [&] {
     f->host.assign(count, FleetGraph{});
     f->arena.assign(count, DBuf{});
     f->ensure(f->table, sizeof(FleetGraph) * count, s);
@@ -402,20 +410,16 @@ leiden_status leiden_fleet_create(int32_t count, const int64_t *n, const int64_t
 
 leiden_status leiden_fleet_destroy(leiden_fleet *f) {
   if (!f) return LEIDEN_EINVAL;
+  // no wait for the device: the releases are ordered after the fleet's last
+  // work (on the null stream, which first waits for that work)
   hipStream_t s = nullptr;
-  if (f->used && f->last) {
-    hipEvent_t e;
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess) {
-      (void)hipEventRecord(e, f->last);
-      (void)hipStreamWaitEvent(s, e, 0);
-      (void)hipEventDestroy(e);
-    }
-  }
+  if (f->used && f->order) (void)hipStreamWaitEvent(s, f->order, 0);
   f->release(s);
   if (f->exec) (void)hipGraphExecDestroy(f->exec);
   if (f->cap_stream) (void)hipStreamDestroy(f->cap_stream);
   if (f->t0) (void)hipEventDestroy(f->t0);
   if (f->t1) (void)hipEventDestroy(f->t1);
+  if (f->order) (void)hipEventDestroy(f->order);
   if (f->pin) {
     (void)hipStreamSynchronize(s);
     (void)hipHostFree(f->pin);
@@ -458,8 +462,7 @@ leiden_status leiden_fleet_run(leiden_fleet *f, int32_t count, const int32_t *gr
     }
   }
   hipStream_t s = (hipStream_t)stream;
-  return guarded(f, [&] {
-    enter(f, s);
+  return run_fleet(f, s, [&] {
     // capacity of each graph for its insertions
     bool grown = false;
     for (int32_t k = 0; k < count; ++k) {
@@ -575,8 +578,7 @@ leiden_status leiden_fleet_get_graph(leiden_fleet *f, int32_t graph, int64_t *of
                                      float *weights, int64_t *nnz, void *stream) {
   if (!f || graph < 0 || graph >= f->count) return LEIDEN_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  return guarded(f, [&] {
-    enter(f, s);
+  return run_fleet(f, s, [&] {
     const FleetGraph &g = f->host[graph];
     if (nnz) *nnz = g.nnz;
     const int c = g.cur;
@@ -594,8 +596,7 @@ leiden_status leiden_fleet_get_state(leiden_fleet *f, int32_t graph, int32_t *me
   if (!f || graph < 0 || graph >= f->count) return LEIDEN_EINVAL;
   if (!f->host[graph].has_state) return LEIDEN_ESTATE;
   hipStream_t s = (hipStream_t)stream;
-  return guarded(f, [&] {
-    enter(f, s);
+  return run_fleet(f, s, [&] {
     const FleetGraph &g = f->host[graph];
     if (membership && g.n > 0)
       f->check(hipMemcpyAsync(membership, g.C, g.n * sizeof(int32_t), hipMemcpyDeviceToDevice, s), "copy");

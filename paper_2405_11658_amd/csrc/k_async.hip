@@ -330,7 +330,7 @@ __global__ __launch_bounds__(256) void k_move_async(MoveArgs a) {
       v = a.alist[p];
       e0v = a.off[v];
       e1v = a.off[v + 1];
-      elig = e1v - e0v <= kHubDeg && a.rng[v];
+      elig = e1v - e0v <= a.hubdeg && a.rng[v];
       if (elig) {
         dv = a.C[v];  // only this wavefront writes C[v] during the sweep
         kv = a.K[v];
@@ -397,6 +397,19 @@ void move_async(const MoveArgs &a, int waves, bool wide, hipStream_t s) {
   launch_async(k_move_async<4, 512>, k_move_async<2, 2048>, a, waves, wide, s);
 }
 
+constexpr int kRefineTries = 4;  // evaluations of a refinement candidate whose target emptied
+
+// Sigma[target] += x unless the target community had become empty (Sigma
+// 0: its last member left), in which case the addition is taken back; one
+// atomic add (not a compare-and-swap loop, which would serialise on popular
+// targets).  Returns whether the merge happened.
+__device__ __forceinline__ bool join_nonempty(double *sig, double x) {
+  const double old = unsafeAtomicAdd(sig, x);
+  if (old != 0.0) return true;
+  unsafeAtomicAdd(sig, -x);
+  return false;
+}
+
 template <int WPB, int LDSCAP>
 __global__ __launch_bounds__(256) void k_refine_async(RefineArgs a) {
   __shared__ WaveLds<LDSCAP> lds[WPB];
@@ -421,7 +434,7 @@ __global__ __launch_bounds__(256) void k_refine_async(RefineArgs a) {
       e0v = a.off[v];
       e1v = a.off[v + 1];
       cbv = a.CB[v];
-      cand = e1v - e0v <= kHubDeg && a.dC[cbv];
+      cand = e1v - e0v <= a.hubdeg && a.dC[cbv];
       if (cand) {
         cv = a.C[v];  // only this wavefront moves vertex v
         kv = a.K[v];
@@ -435,25 +448,42 @@ __global__ __launch_bounds__(256) void k_refine_async(RefineArgs a) {
       const int i = __shfl(v, k), c = __shfl(cv, k), cb = __shfl(cbv, k);
       const int64_t e0 = __shfl(e0v, k), e1 = __shfl(e1v, k);
       const double Ki = __shfl(kv, k);
-      EdgeBatch eb;
-      batch_ids(eb, a.idx, a.w, i, e0, e1);
-      batch_comms(eb, a.C, a.CB, cb, i);
-      WaveTable t = wave_table(lds[wv], gk, gv, e1 - e0);
-      const double b = table_edges(t, eb, a.idx, a.w, a.C, a.CB, cb, i, c, e0, e1);
-      tab_sync(t);
-      double bg;
-      int bc;
-      best_move(t, a.M2, c, b, Ki, Ki, a.Sig, bg, bc);
-      tab_release(t);
-      if (bc == kNoComm) continue;
-      if (lane() == 0 && ld_int(&a.C[bc]) == bc) {
-        // claim the singleton: Sigma[c] K_i -> 0 fails if someone joined it
-        unsigned long long *sc = (unsigned long long *)&a.Sig[c];
-        const unsigned long long want = __double_as_longlong(Ki);
-        if (atomicCAS(sc, want, 0ull) == want) {
-          unsafeAtomicAdd(&a.Sig[bc], Ki);
-          st_int(&a.C[i], bc);
+      // A target chosen from communities read while other wavefronts move
+      // may empty before the merge (its representative joined another
+      // community); the vertex then looks again with fresh labels instead of
+      // staying alone.  Alone (one wavefront) this never happens: a table
+      // only holds communities that have members.
+      for (int attempt = 0; attempt < kRefineTries; ++attempt) {
+        EdgeBatch eb;
+        batch_ids(eb, a.idx, a.w, i, e0, e1);
+        batch_comms(eb, a.C, a.CB, cb, i);
+        WaveTable t = wave_table(lds[wv], gk, gv, e1 - e0);
+        const double b = table_edges(t, eb, a.idx, a.w, a.C, a.CB, cb, i, c, e0, e1);
+        tab_sync(t);
+        double bg;
+        int bc;
+        best_move(t, a.M2, c, b, Ki, Ki, a.Sig, bg, bc);
+        tab_release(t);
+        if (bc == kNoComm) break;
+        int again = 0;
+        if (lane() == 0) {
+          if (ld_int(&a.C[bc]) != bc) {
+            again = 1;
+          } else {
+            // claim the singleton: Sigma[c] K_i -> 0 fails if someone joined it
+            unsigned long long *sc = (unsigned long long *)&a.Sig[c];
+            const unsigned long long want = __double_as_longlong(Ki);
+            if (atomicCAS(sc, want, 0ull) == want) {
+              if (join_nonempty(&a.Sig[bc], Ki)) {
+                st_int(&a.C[i], bc);
+              } else {
+                unsafeAtomicAdd(&a.Sig[c], Ki);  // the target emptied meanwhile: stay, look again
+                again = 1;
+              }
+            }
+          }
         }
+        if (!__shfl(again, 0)) break;
       }
     }
   }

@@ -491,12 +491,15 @@ struct FleetRun {
     __syncthreads();
     for (int64_t i = B::tid(); i < n; i += T) g.Cl[i] = ldx(&rep[g.Cl[i]]);
     __syncthreads();
-    double *ts = g.Sl;
-    g.Sl = g.S2;
-    g.S2 = ts;
-    uint8_t *tc = g.dC;
-    g.dC = g.dC2;
-    g.dC2 = tc;
+    if (B::tid() == 0) {
+      double *ts = g.Sl;
+      g.Sl = g.S2;
+      g.S2 = ts;
+      uint8_t *tc = g.dC;
+      g.dC = g.dC2;
+      g.dC2 = tc;
+    }
+    __syncthreads();
   }
 
   __device__ void break_changed(int64_t n) {
@@ -759,9 +762,11 @@ struct FleetRun {
       nw[o] = job.bw[sp[t]];
     }
     __syncthreads();
-    // every thread holds its own copy of the graph record: all update it
-    g.cur = nb;
-    g.nnz = nnz_new;
+    if (B::tid() == 0) {
+      g.cur = nb;
+      g.nnz = nnz_new;
+    }
+    __syncthreads();
     return 0;
   }
 
@@ -851,7 +856,9 @@ struct FleetRun {
       dm += del ? -x : x;
     }
     dm = B::sum_d(dm, s);
-    g.M2 = g.M2 + dm;  // in every thread's copy
+    __syncthreads();
+    if (B::tid() == 0) g.M2 = g.M2 + dm;
+    __syncthreads();
     long long aff = 0;
     for (int64_t i = B::tid(); i < n; i += T) aff += g.U[i] ? 1 : 0;
     aff = B::sum_l(aff, s);
@@ -928,7 +935,8 @@ struct FleetRun {
       double m2 = 0.0;
       for (int64_t i = B::tid(); i < n; i += T) m2 += g.K[i];
       m2 = B::sum_d(m2, s);
-      g.M2 = m2;  // in every thread's copy
+      if (B::tid() == 0) g.M2 = m2;
+      __syncthreads();
       M2 = m2;
       track = false;
       if (B::tid() == 0) res->affected = n;
@@ -956,8 +964,10 @@ struct FleetRun {
     const double q = modularity();
     if (job.out)
       for (int64_t i = B::tid(); i < n; i += T) job.out[i] = g.C[i];
-    if (B::tid() == 0) res->q = q;
-    g.has_state = 1;
+    if (B::tid() == 0) {
+      res->q = q;
+      g.has_state = 1;
+    }
     __syncthreads();
   }
 };
@@ -983,18 +993,17 @@ __global__ __launch_bounds__(T) void k_fleet(FleetLaunch a) {
       s.g = a.graphs[s.job.graph];
     }
     __syncthreads();
-    FleetJob job = s.job;
-    FleetGraph g = s.g;
-    __syncthreads();
-    FleetRun<T, SLOTS> run{s, g, job, &a.results[j], a.prm};
+    // the graph record and the job stay in LDS: fields every thread reads,
+    // written by thread 0 between barriers
+    FleetRun<T, SLOTS> run{s, s.g, s.job, &a.results[j], a.prm};
     run.run();
     __syncthreads();
     if (threadIdx.x == 0) {
-      FleetGraph *dst = &a.graphs[job.graph];
-      dst->nnz = g.nnz;
-      dst->cur = g.cur;
-      dst->M2 = g.M2;
-      dst->has_state = g.has_state;
+      FleetGraph *dst = &a.graphs[s.job.graph];
+      dst->nnz = s.g.nnz;
+      dst->cur = s.g.cur;
+      dst->M2 = s.g.M2;
+      dst->has_state = s.g.has_state;
     }
     __syncthreads();
   }

@@ -21,8 +21,8 @@
 
 namespace lk {
 
-__device__ __forceinline__ int bucket_of_d(int64_t deg) {
-  return deg <= 4 ? 0 : deg <= 8 ? 1 : deg <= 32 ? 2 : deg <= 256 ? 3 : deg <= 2048 ? 4 : 5;
+__device__ __forceinline__ int bucket_of_d(int64_t deg, int64_t hubdeg) {
+  return deg > hubdeg ? 5 : deg <= 4 ? 0 : deg <= 8 ? 1 : deg <= 32 ? 2 : deg <= 256 ? 3 : 4;
 }
 
 // Keyed appends are aggregated per workgroup: a tile of kTile vertices is
@@ -31,8 +31,8 @@ __device__ __forceinline__ int bucket_of_d(int64_t deg) {
 constexpr int kTile = 4096;
 constexpr int kMaxKeys = 2048;  // >= 256 slices * (kNB + 1)
 
-__global__ __launch_bounds__(256) void k_slice_hist(const int64_t *off, int64_t n, int S, int32_t *counts,
-                                                    int32_t *slice_cnt) {
+__global__ __launch_bounds__(256) void k_slice_hist(const int64_t *off, int64_t n, int S, int64_t hubdeg,
+                                                    int32_t *counts, int32_t *slice_cnt) {
   __shared__ int cnt[kMaxKeys];
   const int K = S * kNB + S;  // bucket keys, then slice keys
   for (int k = threadIdx.x; k < K; k += blockDim.x) cnt[k] = 0;
@@ -41,7 +41,7 @@ __global__ __launch_bounds__(256) void k_slice_hist(const int64_t *off, int64_t 
     const int64_t deg = off[i + 1] - off[i];
     const int sl = slice_of(i, S);
     atomicAdd(&cnt[S * kNB + sl], 1);
-    if (deg > 0) atomicAdd(&cnt[sl * kNB + bucket_of_d(deg)], 1);
+    if (deg > 0) atomicAdd(&cnt[sl * kNB + bucket_of_d(deg, hubdeg)], 1);
   }
   __syncthreads();
   for (int k = threadIdx.x; k < K; k += blockDim.x) {
@@ -49,8 +49,9 @@ __global__ __launch_bounds__(256) void k_slice_hist(const int64_t *off, int64_t 
     if (c) atomicAdd(k < S * kNB ? &counts[k] : &slice_cnt[k - S * kNB], c);
   }
 }
-void slice_hist(const int64_t *off, int64_t n, int S, int32_t *counts, int32_t *slice_cnt, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_slice_hist, flat_grid(n, 256, 1024), 256, 0, s, off, n, S, counts, slice_cnt);
+void slice_hist(const int64_t *off, int64_t n, int S, int64_t hubdeg, int32_t *counts, int32_t *slice_cnt,
+                hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_slice_hist, flat_grid(n, 256, 1024), 256, 0, s, off, n, S, hubdeg, counts, slice_cnt);
 }
 
 __global__ __launch_bounds__(256) void k_slice_scatter(int64_t n, int S, const int32_t *slice_off,
@@ -87,7 +88,7 @@ void slice_scatter(int64_t n, int S, const int32_t *slice_off, int32_t *slice_fi
 __device__ __forceinline__ int frontier_key(const MoveArgs &a, int i) {
   if (!a.U[i] || !a.rng[i]) return -1;
   const int64_t deg = a.off[i + 1] - a.off[i];
-  return deg > 0 ? bucket_of_d(deg) : -1;
+  return deg > 0 ? bucket_of_d(deg, a.hubdeg) : -1;
 }
 
 __global__ __launch_bounds__(256) void k_frontier(MoveArgs a) {
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(256) void k_frontier(MoveArgs a) {
       const int key = frontier_key(a, i);
       a.prop[i] = -1;
       a.U[i] = 0;
-      if (a.act && a.off[i + 1] - a.off[i] > kHubDeg) a.act[i] = key >= 0;
+      if (a.act && a.off[i + 1] - a.off[i] > a.hubdeg) a.act[i] = key >= 0;
       if (key >= 0) a.lists[region[key] + base[key] + atomicAdd(&cnt[key], 1)] = i;
     }
     __syncthreads();
@@ -369,17 +370,17 @@ __global__ __launch_bounds__(256) void k_hub_final(MoveArgs a) {
 }
 
 // ---- hub plan -------------------------------------------------------------------
-__global__ void k_hub_find(const int64_t *off, int64_t n, int S, const int32_t *hub_soff, int32_t *hub_fill,
-                           int32_t *hubv) {
+__global__ void k_hub_find(const int64_t *off, int64_t n, int S, int64_t hubdeg, const int32_t *hub_soff,
+                           int32_t *hub_fill, int32_t *hubv) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    if (off[i + 1] - off[i] <= kHubDeg) continue;
+    if (off[i + 1] - off[i] <= hubdeg) continue;
     const int sl = slice_of(i, S);
     hubv[hub_soff[sl] + atomicAdd(&hub_fill[sl], 1)] = (int32_t)i;
   }
 }
-void hub_find(const int64_t *off, int64_t n, int S, const int32_t *hub_soff, int32_t *hub_fill, int32_t *hubv,
-              hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_hub_find, flat_grid(n), 256, 0, s, off, n, S, hub_soff, hub_fill, hubv);
+void hub_find(const int64_t *off, int64_t n, int S, int64_t hubdeg, const int32_t *hub_soff, int32_t *hub_fill,
+              int32_t *hubv, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_hub_find, flat_grid(n), 256, 0, s, off, n, S, hubdeg, hub_soff, hub_fill, hubv);
 }
 
 __global__ void k_hub_sizes(const int64_t *off, const int32_t *hubv, int64_t nhub, int64_t *nch, int64_t *ncap,

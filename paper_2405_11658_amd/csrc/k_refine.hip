@@ -16,8 +16,8 @@
 
 namespace lk {
 
-__device__ __forceinline__ int bucket_of_r(int64_t deg) {
-  return deg <= 4 ? 0 : deg <= 8 ? 1 : deg <= 32 ? 2 : deg <= 256 ? 3 : deg <= 2048 ? 4 : 5;
+__device__ __forceinline__ int bucket_of_r(int64_t deg, int64_t hubdeg) {
+  return deg > hubdeg ? 5 : deg <= 4 ? 0 : deg <= 8 ? 1 : deg <= 32 ? 2 : deg <= 256 ? 3 : 4;
 }
 
 __global__ void k_rep_min(int64_t n, const int32_t *C, int32_t *rep) {
@@ -55,7 +55,7 @@ constexpr int kRMaxKeys = 2048;  // >= 256 slices * kNB
 __device__ __forceinline__ int break_key(const RefineArgs &a, int64_t i, int cb) {
   if (!a.dC[cb]) return -2;  // not in a changed bound
   const int64_t deg = a.off[i + 1] - a.off[i];
-  return deg > 0 ? slice_of(i, a.nsl) * kNB + bucket_of_r(deg) : -1;
+  return deg > 0 ? slice_of(i, a.nsl) * kNB + bucket_of_r(deg, a.hubdeg) : -1;
 }
 
 __global__ __launch_bounds__(256) void k_break(RefineArgs a) {

@@ -145,17 +145,20 @@ struct MoveArgs {
   int64_t alen;
   int *akeys;                 // per-wavefront global tables, 2*kHubDeg slots each
   double *avals;
+  int64_t hubdeg;             // degree above which a vertex takes the hub path (<= kHubDeg)
 };
 // Per level: counts[s*kNB+b] of vertices with edges, slice sizes, and the
 // vertex-by-slice grouping (slice_fill zeroed, slice_off = starts of slices).
-void slice_hist(const int64_t *off, int64_t n, int S, int32_t *counts, int32_t *slice_cnt, hipStream_t s);
+// Vertices of degree > hubdeg (<= kHubDeg) go to the last (hub) bucket.
+void slice_hist(const int64_t *off, int64_t n, int S, int64_t hubdeg, int32_t *counts, int32_t *slice_cnt,
+                hipStream_t s);
 void slice_scatter(int64_t n, int S, const int32_t *slice_off, int32_t *slice_fill, int32_t *vbyslice,
                    hipStream_t s);
 // Hub plan construction (per level): hubs of each slice placed at
 // slice_off[s] + fill; per-hub chunk / slot / segment counts (to be scanned
 // into hch, htab, hsg); expansion into chub / shub; bounds[k] = arr[at[k]].
-void hub_find(const int64_t *off, int64_t n, int S, const int32_t *hub_soff, int32_t *hub_fill, int32_t *hubv,
-              hipStream_t s);
+void hub_find(const int64_t *off, int64_t n, int S, int64_t hubdeg, const int32_t *hub_soff, int32_t *hub_fill,
+              int32_t *hubv, hipStream_t s);
 void hub_sizes(const int64_t *off, const int32_t *hubv, int64_t nhub, int64_t *nch, int64_t *ncap, int64_t *nseg,
                hipStream_t s);
 void hub_expand(const HubPlan &h, int64_t nhub, hipStream_t s);
@@ -205,6 +208,7 @@ struct RefineArgs {
   HubPlan hp;
   uint8_t *act;
   int64_t hbeg, hend, qbeg, qend, gbeg, gend;
+  int64_t hubdeg;
 };
 void refine_break(const RefineArgs &a, hipStream_t s);
 void refine_propose_bucket(const RefineArgs &a, const int64_t *region_h, int b, hipStream_t s);
@@ -213,7 +217,7 @@ void refine_accept(const RefineArgs &a, const int64_t *region_h, hipStream_t s);
 
 // ---- k_async.hip ---------------------------------------------------------------
 constexpr int kAsyncChunk = 64;  // vertex ids taken per grab of the asynchronous sweeps
-// `waves` wavefronts sweep the list; vertices of degree <= kHubDeg only.
+// `waves` wavefronts sweep the list; vertices of degree <= a.hubdeg only.
 // Tables: LDS, else 2*kHubDeg slots per wavefront in akeys/avals; `wide`
 // selects larger LDS tables (for levels of high average degree).
 void move_async(const MoveArgs &a, int waves, bool wide, hipStream_t s);

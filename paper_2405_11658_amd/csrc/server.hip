@@ -8,7 +8,10 @@
 // admitted updates overlap on the device.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
+#include <cstring>
+#include <iterator>
 #include <condition_variable>
 #include <deque>
 #include <mutex>
@@ -25,7 +28,9 @@ using Clock = std::chrono::steady_clock;
 
 struct Request {
   int64_t id;
-  leiden_handle *h;
+  leiden_handle *h;      // a handle's update, or
+  leiden_fleet *fleet;   // a job on one graph of a fleet (run with the fleet's other queued jobs)
+  int32_t graph;
   leiden_batch b;
   int32_t mode;
   int32_t *out;
@@ -40,14 +45,17 @@ struct Request {
   bool done = false;
 };
 
+constexpr int kMaxFleetJobs = 4096;  // jobs gathered into one fleet launch
+
 // Device bytes an admitted update may use beyond what is already held: the
 // handle's workspace growth for this batch (leiden_update_bytes: the grown
 // graph, its level and aggregation buffers, the directed batch) - taken when
 // the request is considered for admission, since an earlier update of the
 // same handle may have grown it since submission.
-int64_t request_bytes(const leiden_handle *h, const leiden_batch &b) {
+int64_t request_bytes(const Request &r) {
+  if (r.fleet) return 64 * (r.b.n_del + r.b.n_ins);  // the launch's batch scratch
   int64_t bytes = 0;
-  if (leiden_update_bytes(h, b.n_del, b.n_ins, &bytes) != LEIDEN_OK) return 0;
+  if (leiden_update_bytes(r.h, r.b.n_del, r.b.n_ins, &bytes) != LEIDEN_OK) return 0;
   return bytes;
 }
 
@@ -61,7 +69,7 @@ struct leiden_server {
   std::condition_variable cv_work, cv_done;
   std::deque<Request *> queue;
   std::unordered_map<int64_t, Request *> reqs;
-  std::unordered_set<const leiden_handle *> busy;
+  std::unordered_set<const void *> busy;  // handles and fleets being updated
   int64_t in_use = 0;
   int64_t next_id = 1;
   bool stop = false;
@@ -69,46 +77,103 @@ struct leiden_server {
   // counters
   int64_t completed = 0;
 
-  // first queued request that fits; nullptr if none (called with mu held)
-  Request *admit() {
+  // First queued request that fits, into `out`; for a fleet request, also
+  // every later queued request of the same fleet on another graph (in queue
+  // order, each graph's first only, within the budget), so that they share one
+  // launch.  Empty if none fits (called with mu held).
+  void admit(std::vector<Request *> &out) {
+    out.clear();
     for (auto it = queue.begin(); it != queue.end(); ++it) {
       Request *r = *it;
-      if (busy.count(r->h)) continue;
-      r->bytes = request_bytes(r->h, r->b);
+      const void *owner = r->fleet ? (const void *)r->fleet : (const void *)r->h;
+      if (busy.count(owner)) continue;
+      r->bytes = request_bytes(*r);
       if (in_use > 0 && in_use + r->bytes > budget) continue;
-      queue.erase(it);
-      busy.insert(r->h);
+      busy.insert(owner);
       in_use += r->bytes;
-      return r;
+      out.push_back(r);
+      if (r->fleet) {
+        std::unordered_set<int32_t> graphs{r->graph};
+        for (auto jt = std::next(it); jt != queue.end() && (int)out.size() < kMaxFleetJobs; ++jt) {
+          Request *q = *jt;
+          if (q->fleet != r->fleet || graphs.count(q->graph)) {
+            if (q->fleet == r->fleet) graphs.insert(q->graph);  // later requests of that graph wait
+            continue;
+          }
+          q->bytes = request_bytes(*q);
+          if (in_use + q->bytes > budget) continue;
+          graphs.insert(q->graph);
+          in_use += q->bytes;
+          out.push_back(q);
+        }
+      }
+      for (Request *a : out) queue.erase(std::find(queue.begin(), queue.end(), a));
+      return;
     }
-    return nullptr;
   }
 
   void worker() {
     (void)hipSetDevice(device);
     hipStream_t s;
     const bool ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+    std::vector<Request *> rs;
+    std::vector<int32_t> graphs, modes;
+    std::vector<leiden_batch> batches;
+    std::vector<int32_t *> outs;
+    std::vector<double> qs;
+    std::vector<leiden_status> sts;
+    std::vector<leiden_stats> stats;
     for (;;) {
-      Request *r = nullptr;
+      rs.clear();  // the previous batch's requests may already be freed by their waiters
       {
         std::unique_lock<std::mutex> lk(mu);
-        cv_work.wait(lk, [&] { return stop || (r = admit()) != nullptr; });
+        cv_work.wait(lk, [&] {
+          if (stop) return true;
+          admit(rs);
+          return !rs.empty();
+        });
+        if (rs.empty()) break;
       }
-      if (!r) break;
       const Clock::time_point t0 = Clock::now();
-      if (ok)
+      Request *r = rs[0];
+      if (!ok) {
+        for (Request *a : rs) a->st = LEIDEN_EHIP;
+      } else if (!r->fleet) {
         r->st = leiden_update(r->h, &r->b, r->mode, r->out, &r->q, &r->stats, nullptr, s);
-      else
-        r->st = LEIDEN_EHIP;
+      } else {
+        const size_t k = rs.size();
+        graphs.resize(k);
+        modes.resize(k);
+        batches.resize(k);
+        outs.resize(k);
+        qs.assign(k, 0.0);
+        sts.assign(k, LEIDEN_OK);
+        stats.resize(k);
+        for (size_t j = 0; j < k; ++j) {
+          graphs[j] = rs[j]->graph;
+          modes[j] = rs[j]->mode;
+          batches[j] = rs[j]->b;
+          outs[j] = rs[j]->out;
+        }
+        const leiden_status st = leiden_fleet_run(r->fleet, (int32_t)k, graphs.data(), modes.data(), batches.data(),
+                                                  outs.data(), qs.data(), sts.data(), stats.data(), nullptr, s);
+        for (size_t j = 0; j < k; ++j) {
+          rs[j]->st = (st == LEIDEN_OK || sts[j] != LEIDEN_OK) ? sts[j] : st;
+          rs[j]->q = qs[j];
+          rs[j]->stats = stats[j];
+        }
+      }
       const Clock::time_point t1 = Clock::now();
       {
         std::lock_guard<std::mutex> lk(mu);
-        r->service_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-        r->latency_ms = std::chrono::duration<double, std::milli>(t1 - r->submitted).count();
-        r->done = true;
-        busy.erase(r->h);
-        in_use -= r->bytes;
-        ++completed;
+        for (Request *a : rs) {
+          a->service_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+          a->latency_ms = std::chrono::duration<double, std::milli>(t1 - a->submitted).count();
+          a->done = true;
+          in_use -= a->bytes;
+          ++completed;
+        }
+        busy.erase(r->fleet ? (const void *)r->fleet : (const void *)r->h);
       }
       cv_work.notify_all();
       cv_done.notify_all();
@@ -151,7 +216,41 @@ extern "C" leiden_status leiden_server_submit(leiden_server *sv, leiden_handle *
   Request *r = new (std::nothrow) Request();
   if (!r) return LEIDEN_ENOMEM;
   r->h = h;
+  r->fleet = nullptr;
+  r->graph = -1;
   r->b = *batch;
+  r->mode = mode;
+  r->out = membership_out;
+  r->bytes = 0;
+  r->submitted = Clock::now();
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->stop) {
+      delete r;
+      return LEIDEN_EINVAL;
+    }
+    r->id = sv->next_id++;
+    sv->reqs[r->id] = r;
+    sv->queue.push_back(r);
+    *request_id = r->id;
+  }
+  sv->cv_work.notify_all();
+  return LEIDEN_OK;
+}
+
+extern "C" leiden_status leiden_server_submit_fleet(leiden_server *sv, leiden_fleet *fleet, int32_t graph,
+                                                    const leiden_batch *batch, int32_t mode,
+                                                    int32_t *membership_out, int64_t *request_id) {
+  if (!sv || !fleet || !request_id || graph < 0 || graph >= leiden_fleet_count(fleet)) return LEIDEN_EINVAL;
+  if (mode != 0 && mode != LEIDEN_ND && mode != LEIDEN_DS && mode != LEIDEN_DF) return LEIDEN_EINVAL;
+  if (mode != 0 && !batch) return LEIDEN_EINVAL;
+  Request *r = new (std::nothrow) Request();
+  if (!r) return LEIDEN_ENOMEM;
+  r->h = nullptr;
+  r->fleet = fleet;
+  r->graph = graph;
+  if (batch) r->b = *batch;
+  else memset(&r->b, 0, sizeof(r->b));
   r->mode = mode;
   r->out = membership_out;
   r->bytes = 0;

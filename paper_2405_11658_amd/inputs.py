@@ -196,47 +196,15 @@ def rmat(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c:
     return _symmetric_csr(nn, u, v)
 
 
-def rmat_device(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c: float = 0.19,
-                seed: int = 1, device: str = "cuda"):
-    """The R-MAT graph of ``rmat`` (same model, symmetrised, self-loops and
-    duplicates removed, unit weights, ids relabelled by a random permutation)
-    drawn and assembled on a torch device, for sizes whose host assembly would
-    take minutes (scale 26: ~1.9e9 directed entries).  Random numbers come from
-    a ``torch.Generator`` seeded with ``seed``, so the graph differs from
-    ``rmat``'s at the same seed.  Returns (n, off int64, idx int32, w float32)
-    as device tensors, rows sorted by neighbour id.
-
-    Assembly: the unique undirected keys a*n+b (a < b) are sorted once (the
-    rows' forward halves) and their mirrors b*n+a once more (backward halves);
-    every entry's CSR position is its row offset plus its rank inside its own
-    half of the row plus the number of entries of the other half of the row
-    that precede it, found by binary search in the other sorted half."""
+def _assemble_device(N: int, key1, dev):
+    """Symmetric CSR (rows sorted by neighbour id, unit weights) from the
+    sorted unique undirected keys a*N+b (a < b) on a torch device: the rows'
+    forward halves are key1, their backward halves the sorted mirrors; every
+    entry's CSR position is its row offset plus its rank inside its own half
+    of the row plus the number of entries of the other half of the row that
+    precede it, found by binary search in the other sorted half."""
     import torch
-    dev = torch.device(device)
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(seed)
-    N = 1 << scale
-    m = edge_factor * N
-    ab, abc = a + b, a + b + c
-    perm = torch.randperm(N, generator=gen, device=dev)
     chunk = 1 << 26
-    keys = []
-    for s0 in range(0, m, chunk):
-        k = min(chunk, m - s0)
-        u = torch.zeros(k, dtype=torch.int64, device=dev)
-        v = torch.zeros(k, dtype=torch.int64, device=dev)
-        for _ in range(scale):
-            r = torch.rand(k, generator=gen, device=dev)
-            u = (u << 1) | (r >= ab).to(torch.int64)
-            v = (v << 1) | (((r >= a) & (r < ab)) | (r >= abc)).to(torch.int64)
-        u = perm[u]
-        v = perm[v]
-        keep = u != v
-        u, v = u[keep], v[keep]
-        keys.append(torch.minimum(u, v) * N + torch.maximum(u, v))
-        del u, v, r, keep
-    key1 = torch.unique(torch.cat(keys))          # sorted, a < b
-    del keys, perm
     key2, _ = torch.sort((key1 % N) * N + key1 // N)
     bounds = torch.arange(N + 1, dtype=torch.int64, device=dev) * N
     h1 = torch.searchsorted(key1, bounds)
@@ -254,9 +222,83 @@ def rmat_device(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0
             before = torch.searchsorted(other, k) - ho[src]
             idx[off[src] + rank + before] = (k % N).to(torch.int32)
             del k, src, rank, before
-    del key1, key2, h1, h2, bounds, deg
+    del key2, h1, h2, bounds, deg
     w = torch.ones(nnz, dtype=torch.float32, device=dev)
-    return N, off, idx, w
+    return off, idx, w
+
+
+def rmat_device(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19, c: float = 0.19,
+                seed: int = 1, device: str = "cuda", n: int | None = None):
+    """The R-MAT graph of ``rmat`` (same model, symmetrised, self-loops and
+    duplicates removed, unit weights, ids relabelled by a random permutation)
+    drawn and assembled on a torch device, for sizes whose host assembly would
+    take minutes (scale 26: ~1.9e9 directed entries).  Random numbers come from
+    a ``torch.Generator`` seeded with ``seed``, so the graph differs from
+    ``rmat``'s at the same seed.  With n < 2**scale the ids are folded modulo
+    n (as ``rmat`` does).  Returns (n, off int64, idx int32, w float32) as
+    device tensors, rows sorted by neighbour id."""
+    import torch
+    dev = torch.device(device)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    N = 1 << scale
+    m = edge_factor * N
+    ab, abc = a + b, a + b + c
+    perm = torch.randperm(N, generator=gen, device=dev)
+    nn = n if (n is not None and n < N) else N
+    chunk = 1 << 26
+    keys = []
+    for s0 in range(0, m, chunk):
+        k = min(chunk, m - s0)
+        u = torch.zeros(k, dtype=torch.int64, device=dev)
+        v = torch.zeros(k, dtype=torch.int64, device=dev)
+        for _ in range(scale):
+            r = torch.rand(k, generator=gen, device=dev)
+            u = (u << 1) | (r >= ab).to(torch.int64)
+            v = (v << 1) | (((r >= a) & (r < ab)) | (r >= abc)).to(torch.int64)
+        u = perm[u] % nn
+        v = perm[v] % nn
+        keep = u != v
+        u, v = u[keep], v[keep]
+        keys.append(torch.minimum(u, v) * nn + torch.maximum(u, v))
+        del u, v, r, keep
+    key1 = torch.unique(torch.cat(keys))          # sorted, a < b
+    del keys, perm
+    off, idx, w = _assemble_device(nn, key1, dev)
+    return nn, off, idx, w
+
+
+def planted_device(n: int, block: int = 64, deg_in: float = 6.3, deg_out: float = 4.0, seed: int = 1,
+                   device: str = "cuda"):
+    """Planted partition drawn on a torch device: vertices in consecutive
+    blocks of `block` (ids then relabelled by a random permutation), about
+    deg_in expected neighbours inside the block and deg_out outside per
+    vertex: n*deg_in/2 intra-block and n*deg_out/2 inter-block vertex pairs
+    drawn uniformly, repeats and self-loops dropped, unit weights.  Returns
+    (n, off, idx, w) device tensors, rows sorted by neighbour id."""
+    import torch
+    dev = torch.device(device)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    perm = torch.randperm(n, generator=gen, device=dev)
+    m_in = int(round(n * deg_in / 2))
+    m_out = int(round(n * deg_out / 2))
+    u = torch.randint(0, n, (m_in,), generator=gen, device=dev)
+    v = (u // block) * block + torch.randint(0, block, (m_in,), generator=gen, device=dev)
+    v = torch.minimum(v, torch.full_like(v, n - 1))
+    a = torch.randint(0, n, (m_out,), generator=gen, device=dev)
+    b = torch.randint(0, n, (m_out,), generator=gen, device=dev)
+    cross = (a // block) != (b // block)
+    u = torch.cat([u, a[cross]])
+    v = torch.cat([v, b[cross]])
+    del a, b, cross
+    u, v = perm[u], perm[v]
+    keep = u != v
+    u, v = u[keep], v[keep]
+    key1 = torch.unique(torch.minimum(u, v) * n + torch.maximum(u, v))
+    del u, v, keep, perm
+    off, idx, w = _assemble_device(n, key1, dev)
+    return n, off, idx, w
 
 
 def grid2d(side: int = 4096, p_diag: float = 0.05, p_drop: float = 0.02, seed: int = 1) -> CSR:
@@ -390,7 +432,7 @@ def batch_stream(g: CSR, size: int, count: int, ins_frac: float = 0.8, seed: int
     return out
 
 
-def batch_stream_device(n: int, off, idx, size: int, count: int, ins_frac: float = 0.8, seed: int = 0,
+def batch_stream_device(n: int, off, idx, size, count: int, ins_frac: float = 0.8, seed: int = 0,
                         weight: float = 1.0) -> list:
     """The batch stream of ``batch_stream`` (Sec. 5.1.4: round(ins_frac*size)
     insertions of uniformly random non-edges, the rest deletions of uniformly
@@ -404,15 +446,17 @@ def batch_stream_device(n: int, off, idx, size: int, count: int, ins_frac: float
     dev = off.device
     gen = torch.Generator(device=dev)
     gen.manual_seed(seed)
-    n_ins = int(round(ins_frac * size))
-    n_del = size - n_ins
+    sizes = [int(size)] * count if np.isscalar(size) else [int(x) for x in size]
+    count = len(sizes)
+    ins = [int(round(ins_frac * x)) for x in sizes]
+    dels = [x - y for x, y in zip(sizes, ins)]
     nnz = idx.numel()
     rows = torch.repeat_interleave(torch.arange(n, dtype=torch.int64, device=dev), off[1:] - off[:-1])
     keys = rows * n + idx.to(torch.int64)       # ascending: rows in order, sorted within rows
     del rows
     # deletions: an entry (u, v) with u < v names each undirected edge once;
     # entries are drawn uniformly, so each edge is equally likely
-    need = n_del * count
+    need = sum(dels)
     picked = torch.empty(0, dtype=torch.int64, device=dev)
     while picked.numel() < need:
         e = torch.randint(0, nnz, (2 * (need - picked.numel()) + 64,), generator=gen, device=dev)
@@ -421,7 +465,7 @@ def batch_stream_device(n: int, off, idx, size: int, count: int, ins_frac: float
         picked = torch.unique(torch.cat([picked, k]))
     picked = picked[torch.randperm(picked.numel(), generator=gen, device=dev)[:need]]
     # insertions: distinct unordered pairs that are not edges, random orientation
-    need_i = n_ins * count
+    need_i = sum(ins)
     got = torch.empty(0, dtype=torch.int64, device=dev)
     while got.numel() < need_i:
         k = 2 * (need_i - got.numel()) + 64
@@ -440,10 +484,57 @@ def batch_stream_device(n: int, off, idx, size: int, count: int, ins_frac: float
     iu, iv = torch.where(flip, iv, iu), torch.where(flip, iu, iv)
     du, dv = picked // n, picked % n
     out = []
+    d0 = i0 = 0
     for j in range(count):
-        d = slice(j * n_del, (j + 1) * n_del)
-        i = slice(j * n_ins, (j + 1) * n_ins)
+        d = slice(d0, d0 + dels[j])
+        i = slice(i0, i0 + ins[j])
+        d0 += dels[j]
+        i0 += ins[j]
         out.append((du[d].to(torch.int32).contiguous(), dv[d].to(torch.int32).contiguous(),
                     iu[i].to(torch.int32).contiguous(), iv[i].to(torch.int32).contiguous(),
-                    torch.full((n_ins,), weight, dtype=torch.float32, device=dev)))
+                    torch.full((ins[j],), weight, dtype=torch.float32, device=dev)))
     return out
+
+
+def temporal_stream(gT: CSR, frac: float, count: int, preload: float = 0.9, ins_frac: float = 0.8,
+                    seed: int = 0):
+    """A synthetic stand-in for the paper's temporal graphs (Sec. 5.1.3,
+    5.1.4): the undirected edges of gT get a seeded random order (their
+    arrival times); the first `preload` fraction forms the initial graph, and
+    then `count` consecutive batches of B = round(frac * |E_T|) updates follow
+    (|E_T| = undirected edges of gT): round(ins_frac * B) insertions taken from
+    the remaining edges in arrival order and the rest deletions of edges
+    present at that point, chosen uniformly.  The stream stops early when the
+    arrivals run out.  Returns (initial graph CSR, list of UBatch)."""
+    rng = _rng(seed)
+    src = np.repeat(np.arange(gT.n, dtype=np.int64), np.diff(gT.off))
+    dst = gT.idx.astype(np.int64)
+    und = np.flatnonzero(src < dst)
+    und = und[rng.permutation(len(und))]
+    eu, ev = src[und], dst[und]
+    T = len(und)
+    n0 = int(round(preload * T))
+    B = max(1, int(round(frac * T)))
+    n_ins = int(round(ins_frac * B))
+    n_del = B - n_ins
+    au = eu[:n0].copy()
+    av = ev[:n0].copy()
+    live = np.ones(len(au), bool)
+    g0 = from_edges(gT.n, eu[:n0], ev[:n0])
+    out = []
+    nxt = n0
+    for _ in range(count):
+        if nxt + n_ins > T:
+            break
+        cand = np.flatnonzero(live)
+        pick = cand[rng.choice(len(cand), size=min(n_del, len(cand)), replace=False)] if n_del else np.empty(0, np.int64)
+        live[pick] = False
+        du, dv = au[pick], av[pick]
+        iu, iv = eu[nxt:nxt + n_ins], ev[nxt:nxt + n_ins]
+        nxt += n_ins
+        au = np.concatenate([au, iu])
+        av = np.concatenate([av, iv])
+        live = np.concatenate([live, np.ones(len(iu), bool)])
+        out.append(UBatch(du.astype(np.int32), dv.astype(np.int32), iu.astype(np.int32), iv.astype(np.int32),
+                          np.ones(len(iu), np.float32)))
+    return g0, out

