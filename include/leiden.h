@@ -364,6 +364,21 @@ leiden_status leiden_modularity(int64_t n, const int64_t *offsets, const int32_t
                                 const float *weights, const int32_t *membership, double *q_out,
                                 void *stream);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation): Eq. 1 as
+ * leiden_modularity computes it, with nnz given by the caller and the result
+ * written to q_out in device memory (NaN when a label or neighbour id is out
+ * of [0, n)).  Nothing is allocated, freed or waited for: the working arrays
+ * live in one fixed array of the library per device (64 MiB, held until the
+ * process ends), which every call on that device shares and which keeps the
+ * last call's contents - calls that overlap on one device race.  n above
+ * leiden_modularity_noalloc_max_vertices() (8,388,576) is LEIDEN_EINVAL and
+ * enqueues nothing. */
+leiden_status leiden_modularity_noalloc(int64_t n, int64_t nnz, const int64_t *offsets, const int32_t *indices,
+                                        const float *weights, const int32_t *membership, double *q_out /* device */,
+                                        void *stream);
+int64_t leiden_modularity_noalloc_max_vertices(void);
+
 /* Alg. "leidenAggregate" for a given membership with dense labels in
  * [0, ncomm): super-vertex CSR with, for each pair of communities, the FP64
  * sum of the weights rounded to float32.  out_offsets: ncomm+1 int64;

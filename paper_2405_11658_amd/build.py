@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libleiden_hip.so")
 BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["k_util.hip", "k_move.hip", "k_async.hip", "k_refine.hip", "k_aggregate.hip", "k_modularity.hip",
-           "k_batch.hip", "driver.hip", "many.hip", "server.hip", "k_fleet.hip", "fleet.hip"]
+           "k_batch.hip", "driver.hip", "many.hip", "server.hip", "k_fleet.hip", "fleet.hip", "noalloc.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
          "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include"), "-Wno-unused-result"]
