@@ -73,9 +73,10 @@ typedef enum { LEIDEN_ND = 1, LEIDEN_DS = 2, LEIDEN_DF = 3 } leiden_mode;
  * vertices with edges on the first level, per 256 on aggregated levels) sweep
  * the vertices in ascending id order and apply each move at once; results
  * depend on timing.
- * Vertices of degree > 2048 are moved before each sweep, synchronously within
- * each of hub_slices hash-ordered slices (0 = 64; more slices move fewer hubs
- * at once).  sync_mode = 1: deterministic test
+ * Vertices of degree > hub_degree (default 256: those whose neighbour table
+ * does not fit a wavefront's LDS table) are moved before each sweep by several
+ * workgroups each, synchronously within each of hub_slices hash-ordered slices
+ * (0 = 64; more slices move fewer hubs at once).  sync_mode = 1: deterministic test
  * mode - every vertex is swept in nslices hash-ordered slices (default 16),
  * the slices in order, the vertices of a slice synchronously, the gain summed
  * in a fixed order; results are bit-identical to the CPU oracle's synchronous
@@ -99,8 +100,8 @@ typedef struct {
                                     wavefront on the first level (0 = 1024) */
   int32_t verts_per_wave_upper;  /* the same on aggregated levels (0 = 256) */
   int32_t hub_degree;  /* asynchronous mode: vertices of higher degree move in
-                          the hub slices before each sweep (0 = 2048;
-                          64 .. 2048) */
+                          the hub slices before each sweep (default 256;
+                          64 .. 2048; 0 = 2048) */
   int32_t trim;        /* 1: every call releases its working buffers when it
                           ends (stream-ordered; the graph and the community
                           state stay), for many resident graphs; 0: kept */
@@ -109,7 +110,7 @@ typedef struct {
 #define LEIDEN_MAX_PASSES 64
 
 /* Kernels timed when leiden_params.profile = 1 (index into leiden_stats.prof_*):
- *   HUB_GATHER  - local-moving edge scan of vertices of degree > 2048 (one
+ *   HUB_GATHER  - local-moving edge scan of the hubs (degree > hub_degree; one
  *                 launch per slice and iteration with hubs in the frontier);
  *                 entries = edges scanned;
  *   AGG_MERGE   - aggregation entry merge, one launch per aggregated level;

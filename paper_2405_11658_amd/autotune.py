@@ -3,8 +3,11 @@ runs in the library).
 
 ``autotune(h, warm, batch)`` - for one resident graph - tries candidate
 settings of the asynchronous sweep's wavefront cap (``async_waves``: how many
-vertices are in flight) and of the number of hub slices (``hub_slices``) on
-scratch copies of the handle's current graph and membership.  Each candidate
+vertices are in flight), of the degree above which a vertex takes the
+multi-workgroup hub path instead of one wavefront with an LDS table
+(``hub_degree``: which degree buckets get which table) and of the number of
+hub slices (``hub_slices``) on scratch copies of the handle's current graph
+and membership.  Each candidate
 is run ``reps`` times: a scratch handle applies ``warm`` (which sizes its
 work buffers) and then ``batch`` (valid after it, as ``inputs.batch_stream``
 draws them) with the given front-end; the second update's latency (median
@@ -33,6 +36,7 @@ from . import leiden as L
 
 DEFAULT_WAVES = (1024, 2048, 4096)
 DEFAULT_SLICES = (64, 128)
+DEFAULT_HUBDEG = (128, 256, 512)
 
 
 def _scratch(off, idx, w, C, params):
@@ -54,27 +58,29 @@ def _measure(off, idx, w, C, params, warm, batch, mode, reps):
 
 
 def autotune(h: L.Handle, warm, batch, mode: str = "df", waves=DEFAULT_WAVES, slices=DEFAULT_SLICES,
-             q_tol: float = 5e-4, reps: int = 3, base: L.leiden_params | None = None):
+             hubdeg=DEFAULT_HUBDEG, q_tol: float = 5e-4, reps: int = 3, base: L.leiden_params | None = None):
     """Returns (chosen params, reference (ms, q), list of (async_waves,
-    hub_slices, ms, q) per candidate)."""
+    hub_slices, hub_degree, ms, q) per candidate)."""
     off, idx, w = L.leiden_get_graph(h)
     C = L.leiden_get_state(h)[0].clone()
     base = base or L.leiden_default_params()
     ref = _measure(off, idx, w, C, base, warm, batch, mode, reps)
     results = []
-    for aw, ns in itertools.product(waves, slices):
+    for aw, ns, hd in itertools.product(waves, slices, hubdeg):
         p = L.leiden_params.from_buffer_copy(base)
         p.async_waves = aw
         p.hub_slices = ns
+        p.hub_degree = hd
         ms, q = _measure(off, idx, w, C, p, warm, batch, mode, reps)
-        results.append((aw, ns, ms, q))
-    ok = [r for r in results if r[3] >= ref[1] - q_tol]
+        results.append((aw, ns, hd, ms, q))
+    ok = [r for r in results if r[4] >= ref[1] - q_tol]
     chosen = L.leiden_params.from_buffer_copy(base)
     if ok:
-        aw, ns, ms, _ = min(ok, key=lambda r: r[2])
+        aw, ns, hd, ms, _ = min(ok, key=lambda r: r[3])
         if ms < ref[0]:
             chosen.async_waves = aw
             chosen.hub_slices = ns
+            chosen.hub_degree = hd
     L.leiden_set_params(h, chosen)
     return chosen, ref, results
 

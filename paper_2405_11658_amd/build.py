@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libleiden_hip.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["k_util.hip", "k_move.hip", "k_async.hip", "k_refine.hip", "k_aggregate.hip", "k_modularity.hip",
+SOURCES = ["k_util.hip", "k_prim.hip", "k_move.hip", "k_async.hip", "k_refine.hip", "k_aggregate.hip", "k_modularity.hip",
            "k_batch.hip", "driver.hip", "many.hip", "server.hip", "k_fleet.hip", "fleet.hip", "noalloc.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
          "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

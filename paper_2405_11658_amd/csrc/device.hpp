@@ -55,6 +55,8 @@ __device__ __forceinline__ long long group_sum_ll(long long v) {
   return v;
 }
 
+// 32-bit integer finaliser "lowbias32" (xorshift-multiply; constants from
+// C. Wellons' published hash-prospector search).
 __device__ __forceinline__ uint32_t mix32(uint32_t x) {
   x ^= x >> 16;
   x *= 0x7feb352du;

@@ -36,7 +36,8 @@ enum Slot {
   // level graphs (ping-pong)
   G0_off, G0_idx, G0_w, G0_crow, G1_off, G1_idx, G1_w, G1_crow,
   // aggregation
-  A_keys, A_skeys, A_vals, A_svals, A_ukeys, A_sums, A_rowlen, A_flag, A_cmap, A_inv, A_cc,
+  A_vk, A_vk2, A_vv, A_vv2, A_eoff, A_pos, A_seg, A_hpos, A_gkey, A_gval, A_ukey, A_uval, A_tfc, A_lflag,
+  A_lidx, A_lc, A_lsb, A_lse, A_ltn, A_tseg, A_hc, A_tin, A_rowlen,
   // hubs
   H_v, H_cnt, H_ch, H_tab, H_sg, H_chub, H_shub, H_tk, H_tv, H_own, H_pg, H_pc, H_soff,
   H_fill, H_bnd, H_flag, L_act, W_keys, W_vals, W_list,
@@ -67,7 +68,6 @@ struct DevScal {
   unsigned long long hub_scanned;
   unsigned long long sweep_work[2];
   unsigned long long anext;
-  unsigned long long agg_unique;
 };
 
 struct Workspace {
@@ -139,12 +139,18 @@ constexpr int kMaxSlices = 256;
 // modularity when both start from the same state (1.0e-3 with 32 slices,
 // 1.6e-3 with 16), for ~12 % more time than 32 slices
 constexpr int kDefaultHubSlices = 64;
+// a stalled level keeping more than this fraction of its vertices as
+// communities ends the pass loop (the paper's default aggregation tolerance)
+constexpr double kStallKeep = 0.8;
+// Default hub threshold of the asynchronous mode: a vertex whose neighbour
+// table does not fit a wavefront's 512-slot LDS table (degree > 256) moves in
+// the multi-workgroup hub slices.
+constexpr int kDefaultHubDeg = 256;
 constexpr int kDefaultAsyncWaves = 2048;  // wavefronts of the asynchronous sweeps, at most
 constexpr int kMaxAsyncWaves = 65536;
 constexpr int64_t kVertsPerWave = 1024;  // level-0 vertices with edges per sweeping wavefront, at least
 constexpr int64_t kVertsPerWaveUpper = 256;  // the same for the aggregated levels
 constexpr int kStallIters = 3;  // see the iteration loop of run_core
-constexpr int64_t kAggRelabelMin = 1 << 20;  // level entries from which aggregation relabels communities
 
 // Wavefronts of an asynchronous sweep over a level with n vertices that have
 // edges: at most `cap`, and few enough that the vertices in flight stay a
@@ -473,22 +479,25 @@ HubHost hub_plan(Ctx &x, const Level &g, int S, int64_t hubdeg, const Layout &B)
   H.p.hch = x.get<int64_t>(H_ch, nh + 1);
   H.p.htab = x.get<int64_t>(H_tab, nh + 1);
   H.p.hsg = x.get<int64_t>(H_sg, nh + 1);
+  H.p.hcap = cnt + (nh + 1);
   scan_i64(x, cnt, H.p.hch, nh + 1);
   scan_i64(x, cnt + (nh + 1), H.p.htab, nh + 1);
   scan_i64(x, cnt + 2 * (nh + 1), H.p.hsg, nh + 1);
-  int64_t *bnd = x.get<int64_t>(H_bnd, 2 * (S + 1) + 1);
+  int64_t *bnd = x.get<int64_t>(H_bnd, 3 * (S + 1));
   gather_bounds(H.p.hch, hsoff, S + 1, bnd, x.s);
   gather_bounds(H.p.hsg, hsoff, S + 1, bnd + (S + 1), x.s);
-  gather_bounds(H.p.htab, hsoff + S, 1, bnd + 2 * (S + 1), x.s);
+  gather_bounds(H.p.htab, hsoff, S + 1, bnd + 2 * (S + 1), x.s);
+  hub_rel(H.p.htab, nh, hsoff, S, bnd + 2 * (S + 1), x.s);
   x.launched("hub bounds");
   int64_t *hb = (int64_t *)((char *)x.pin() + 8192);
-  x.check(hipMemcpyAsync(hb, bnd, sizeof(int64_t) * (2 * (S + 1) + 1), hipMemcpyDeviceToHost, x.s), "D2H");
+  x.check(hipMemcpyAsync(hb, bnd, sizeof(int64_t) * 3 * (S + 1), hipMemcpyDeviceToHost, x.s), "D2H");
   x.check(hipStreamSynchronize(x.s), "sync");
+  int64_t ntab = 0;  // the largest slice's tables
   for (int s = 0; s <= S; ++s) {
     H.qs[s] = hb[s];
     H.gs[s] = hb[S + 1 + s];
+    if (s < S) ntab = std::max(ntab, hb[2 * (S + 1) + s + 1] - hb[2 * (S + 1) + s]);
   }
-  const int64_t ntab = hb[2 * (S + 1)];
   H.p.chub = x.get<int32_t>(H_chub, H.qs[S]);
   H.p.shub = x.get<int32_t>(H_shub, H.gs[S]);
   hub_expand(H.p, nh, x.s);
@@ -519,10 +528,9 @@ int64_t renumber_dense(Ctx &x, int32_t *C, int64_t n, int64_t bound) {
 }
 
 // Alg. "leidenAggregate": level g with dense labels C (< ncomm) -> out level.
-// Super-vertex graph of level g under membership C (ncomm communities) by
-// sorting: keys C[u] * ncomm + C[v] for every entry, radix-sorted over the
-// key bits in use, summed by key (FP64, deterministic order), the distinct
-// keys then being the output entries in CSR order (rows sorted by id).
+// Entries grouped by the community of their source (vertices in community
+// order), each community's group sorted by neighbour community and summed:
+// rows come out sorted by id, with FP64 sums rounded to float32.
 Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, int outbuf, double *Kout) {
   AggArgs a;
   memset(&a, 0, sizeof(a));
@@ -538,55 +546,84 @@ Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, i
   int64_t *out_off = x.get<int64_t>(so, ncomm + 1);
   int32_t *rowlen = x.get<int32_t>(A_rowlen, ncomm + 1);
   x.zero(rowlen, ncomm + 1);
-  int64_t nu = 0;
-  unsigned long long *ukeys = nullptr;
-  double *sums = nullptr;
-  // large levels: keys over a dense relabelling of the communities that own
-  // entries (fewer key bits, fewer radix passes)
-  int64_t nk = ncomm;
-  const int32_t *inv = nullptr;
-  if (g.nnz >= kAggRelabelMin) {
-    int32_t *flag = x.get<int32_t>(A_flag, ncomm + 1);
-    int32_t *cmap = x.get<int32_t>(A_cmap, ncomm + 1);
-    int32_t *Cc = x.get<int32_t>(A_cc, g.n);
-    x.zero(flag, ncomm + 1);
-    agg_flag(g.n, g.off, C, flag, x.s);
-    scan_i32(x, flag, cmap, ncomm + 1);
-    nk = x.read(&cmap[ncomm]);
-    int32_t *invp = x.get<int32_t>(A_inv, nk);
-    agg_inv(ncomm, flag, cmap, invp, x.s);
-    agg_relabel(g.n, g.off, C, cmap, Cc, x.s);
-    a.C = Cc;
-    a.ncomm = nk;
-    inv = invp;
-  }
+  if (Kout) x.zero(Kout, ncomm);
+  const int cb = key_bits((unsigned long long)std::max<int64_t>(ncomm - 1, 0));
+  int64_t nst = 0, nl = 0;
+  int64_t *seg = nullptr;
+  int32_t *tfc = nullptr, *lc = nullptr;
+  int64_t *lsb = nullptr;
+  uint32_t *ukey = nullptr;
+  float *uval = nullptr;
   if (g.nnz > 0) {
-    unsigned long long *keys = x.get<unsigned long long>(A_keys, g.nnz);
-    unsigned long long *skeys = x.get<unsigned long long>(A_skeys, g.nnz);
-    float *vals = x.get<float>(A_vals, g.nnz);
-    float *svals = x.get<float>(A_svals, g.nnz);
-    ukeys = x.get<unsigned long long>(A_ukeys, g.nnz);
-    sums = x.get<double>(A_sums, g.nnz);
-    DevScal *scl = x.scal();
-    const unsigned long long top = (unsigned long long)nk * (unsigned long long)nk - 1ull;
-    int end_bit = 1;
-    while (end_bit < 64 && (top >> end_bit) != 0) ++end_bit;
-    size_t tb = sort_pairs_u64_f32(nullptr, 0, keys, skeys, vals, svals, g.nnz, end_bit, x.s);
-    tb = std::max(tb, reduce_by_key_u64_f32(nullptr, 0, skeys, svals, g.nnz, ukeys, sums, &scl->agg_unique, x.s));
-    void *tmp = x.tmp(tb);
+    const int64_t n = g.n, nnz = g.nnz;
     hipEvent_t t0 = x.kp ? x.kp->begin() : nullptr;
-    agg_keys(a, g.crow, keys, vals, x.s);
-    sort_pairs_u64_f32(tmp, tb, keys, skeys, vals, svals, g.nnz, end_bit, x.s);
-    reduce_by_key_u64_f32(tmp, tb, skeys, svals, g.nnz, ukeys, sums, &scl->agg_unique, x.s);
+    // 1. vertices in community order
+    uint32_t *vk = x.get<uint32_t>(A_vk, n), *vk2 = x.get<uint32_t>(A_vk2, n);
+    int32_t *vv = x.get<int32_t>(A_vv, n), *vv2 = x.get<int32_t>(A_vv2, n);
+    agg_vkeys(n, C, vk, vv, x.s);
+    const RsSeg vseg = rs_plain(n);
+    rsort<uint32_t, int32_t>(vk, vv, vk2, vv2, vseg, cb, x.tmp(rs_tmp_bytes(vseg.ntiles)), x.s);
+    // 2. places of the vertices' entries and the communities' segments
+    int64_t *eoff = x.get<int64_t>(A_eoff, n + 1);
+    int32_t *pos = x.get<int32_t>(A_pos, n);
+    agg_vdeg(n, g.off, vv, eoff, pos, x.s);
+    scan_i64(x, eoff, eoff, n + 1);
+    seg = x.get<int64_t>(A_seg, ncomm + 1);
+    int64_t *hpos = x.get<int64_t>(A_hpos, ncomm);
+    x.zero(seg, ncomm + 1);
+    agg_cdeg(n, vk, eoff, hpos, seg, x.s);
+    scan_i64(x, seg, seg, ncomm + 1);
+    // 3. grouped entries
+    uint32_t *gkey = x.get<uint32_t>(A_gkey, nnz);
+    float *gval = x.get<float>(A_gval, nnz);
+    ukey = x.get<uint32_t>(A_ukey, nnz);
+    uval = x.get<float>(A_uval, nnz);
+    agg_group(a, g.crow, pos, eoff, gkey, gval, x.s);
+    // 4. small segments
+    nst = ceil_div(nnz, (int64_t)kAggSmall);
+    tfc = x.get<int32_t>(A_tfc, nst + 1);
+    agg_windows(seg, ncomm, nst, tfc, x.s);
+    agg_small(seg, tfc, nst, cb, gkey, gval, ukey, uval, rowlen, Kout, x.s);
+    // 5. large segments
+    int32_t *lflag = x.get<int32_t>(A_lflag, ncomm + 1);
+    int32_t *lidx = x.get<int32_t>(A_lidx, ncomm + 1);
+    agg_large_flags(seg, ncomm, lflag, x.s);
+    scan_i32(x, lflag, lidx, ncomm + 1);
+    nl = x.read(&lidx[ncomm]);
+    if (nl > 0) {
+      lc = x.get<int32_t>(A_lc, nl);
+      lsb = x.get<int64_t>(A_lsb, nl);
+      int64_t *lse = x.get<int64_t>(A_lse, nl);
+      int64_t *ltn = x.get<int64_t>(A_ltn, nl + 1);
+      agg_large_list(seg, ncomm, lflag, lidx, lc, lsb, lse, ltn, x.s);
+      scan_i64(x, ltn, ltn, nl + 1);
+      const int64_t ntl = x.read(&ltn[nl]);
+      int32_t *tseg = x.get<int32_t>(A_tseg, ntl);
+      agg_tile_seg(ltn, nl, tseg, x.s);
+      RsSeg rs;
+      rs.ntiles = ntl;
+      rs.n = 0;
+      rs.tseg = tseg;
+      rs.tfirst = ltn;
+      rs.sbeg = lsb;
+      rs.send = lse;
+      rsort<uint32_t, float>(gkey, gval, ukey, uval, rs, cb, x.tmp(rs_tmp_bytes(ntl)), x.s);
+      int64_t *hc = x.get<int64_t>(A_hc, ntl + 1);
+      double *tin = x.get<double>(A_tin, ntl);
+      x.zero(hc, ntl + 1);
+      agg_large_runs(0, gkey, gval, rs, hc, tin, ukey, uval, x.s);
+      scan_i64(x, hc, hc, ntl + 1);
+      agg_large_runs(1, gkey, gval, rs, hc, tin, ukey, uval, x.s);
+      agg_large_rows(nl, lc, lsb, ltn, hc, uval, rowlen, Kout, x.s);
+    }
     if (x.kp) x.kp->end(t0, LEIDEN_PROF_AGG_MERGE, g.nnz, g.n);
-    x.launched("agg_sort");
-    nu = (int64_t)x.read(&scl->agg_unique);
+    x.launched("aggregate");
   }
+  scan_i32_i64(x, rowlen, out_off, ncomm + 1);
+  const int64_t nu = g.nnz > 0 ? x.read(&out_off[ncomm]) : 0;
   int32_t *out_idx = x.get<int32_t>(si, nu);
   float *out_w = x.get<float>(sw, nu);
-  if (Kout) x.zero(Kout, ncomm);
-  agg_rows(ukeys, sums, nu, nk, inv, out_idx, out_w, rowlen, Kout, x.s);
-  scan_i32_i64(x, rowlen, out_off, ncomm + 1);
+  if (g.nnz > 0) agg_compact(seg, tfc, nst, lc, lsb, nl, rowlen, out_off, ukey, uval, out_idx, out_w, x.s);
   int32_t *out_crow = x.get<int32_t>(sc, ceil_div(std::max<int64_t>(nu, 1), kChunk) + 2);
   chunk_start_rows(out_off, ncomm, nu, out_crow, x.s);
   x.launched("agg_rows");
@@ -749,9 +786,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
       // that concurrently processed neighbours are changing can trade places
       // indefinitely, each move scored as a gain; the tolerance test then
       // never passes.  Stop when the number of moves has not reached a new
-      // minimum for kStallIters iterations in a row - the level has converged
-      // up to those trades, so the pass counts as converged for the stop
-      // test of the pass loop below.
+      // minimum for kStallIters iterations in a row.
       if (async && pass > 0 && level_waves(p, NW, alen, pass) > 1) {
         if (r.moves < min_moves) {
           min_moves = r.moves;
@@ -819,7 +854,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
       st->refined_vertices[pass] = (int64_t)x.read(&sc->refined);
       st->passes = pass + 1;
     }
-    if ((pass > 0 || p.refine_variant == 2) && (li <= 1 || stalled)) {
+    if ((pass > 0 || p.refine_variant == 2) && li <= 1) {
       if (st && pass < LEIDEN_MAX_PASSES) {
         // communities of this level, for the statistics only
         int32_t *tmpC = x.get<int32_t>(L_CB, nl);
@@ -832,6 +867,14 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     const int64_t ncomm = renumber_dense(x, C, nl, nl);
     if (st && pass < LEIDEN_MAX_PASSES) st->communities[pass] = ncomm;
     if (p.agg_tol < 1.0 && (double)ncomm / (double)nl > p.agg_tol) {
+      tm.mark(CAT_OTHER);
+      break;
+    }
+    // A stalled level that merged few of its vertices has converged up to the
+    // trades: it ends the passes as a level that converged in one iteration
+    // would.  A stalled level that still merged many (slowly converging
+    // levels, e.g. of road-like graphs) goes on to the next pass.
+    if (stalled && (double)ncomm > kStallKeep * (double)nl) {
       tm.mark(CAT_OTHER);
       break;
     }
@@ -1104,7 +1147,7 @@ void leiden_default_params(leiden_params *p) {
   p->hub_slices = 0;
   p->verts_per_wave = 0;
   p->verts_per_wave_upper = 0;
-  p->hub_degree = 0;
+  p->hub_degree = kDefaultHubDeg;
   p->trim = 0;
 }
 

@@ -313,7 +313,7 @@ __global__ __launch_bounds__(256) void k_hub_gather(MoveArgs a) {
   const int nu = nused;
   const int d = a.C[i];
   const int64_t t0 = a.hp.htab[h];
-  const uint32_t mask = (uint32_t)(a.hp.htab[h + 1] - t0 - 1);
+  const uint32_t mask = (uint32_t)(a.hp.hcap[h] - 1);
   for (int k = threadIdx.x; k < nu; k += blockDim.x) {
     const int s = used[k];
     const int cs = keys[s];
@@ -332,11 +332,12 @@ __global__ __launch_bounds__(256) void k_hub_score(MoveArgs a) {
   const int i = a.hp.hubv[h];
   if (!a.act[i]) return;
   const int64_t s0 = a.hp.htab[h] + (q - a.hp.hsg[h]) * kHubSeg;
+  const int64_t s1 = s0 + min((int64_t)kHubSeg, a.hp.hcap[h]);
   const int d = a.C[i];
   const double Ki = a.K[i], Sd = a.Sig[d], bown = a.hp.own[h];
   double bg = 0.0;
   int bc = kNoComm;
-  for (int64_t s = s0 + threadIdx.x; s < s0 + kHubSeg; s += blockDim.x) {
+  for (int64_t s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
     const int c = a.hp.keys[s];
     if (c == kEmpty) continue;
     const double v = a.hp.vals[s];
@@ -389,16 +390,34 @@ __global__ void k_hub_sizes(const int64_t *off, const int32_t *hubv, int64_t nhu
     if (h == nhub) { nch[h] = 0; ncap[h] = 0; nseg[h] = 0; continue; }
     const int i = hubv[h];
     const int64_t deg = off[i + 1] - off[i];
-    int64_t cap = kHubSeg;
+    int64_t cap = kHubMinCap;
     while (cap < 2 * deg) cap <<= 1;
     nch[h] = ceil_div(deg, (int64_t)kHubEC);
     ncap[h] = cap;
-    nseg[h] = cap / kHubSeg;
+    nseg[h] = ceil_div(cap, (int64_t)kHubSeg);
   }
 }
 void hub_sizes(const int64_t *off, const int32_t *hubv, int64_t nhub, int64_t *nch, int64_t *ncap, int64_t *nseg,
                hipStream_t s) {
   hipLaunchKernelGGL(k_hub_sizes, flat_grid(nhub + 1), 256, 0, s, off, hubv, nhub, nch, ncap, nseg);
+}
+
+// Table offsets counted from the start of each hub's slice: the slices run
+// one after another and scoring frees every slot it reads, so all slices
+// share one table area of the largest slice's size.
+__global__ void k_hub_rel(int64_t *htab, int64_t nhub, const int32_t *hub_soff, int S, const int64_t *slice_base) {
+  for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < nhub; h += (int64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = S;  // the slice s with hub_soff[s] <= h < hub_soff[s + 1]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) / 2;
+      if (hub_soff[mid] <= h) lo = mid;
+      else hi = mid;
+    }
+    htab[h] -= slice_base[lo];
+  }
+}
+void hub_rel(int64_t *htab, int64_t nhub, const int32_t *hub_soff, int S, const int64_t *slice_base, hipStream_t s) {
+  if (nhub > 0) hipLaunchKernelGGL(k_hub_rel, flat_grid(nhub), 256, 0, s, htab, nhub, hub_soff, S, slice_base);
 }
 
 __global__ void k_hub_expand(HubPlan p, int64_t nhub) {

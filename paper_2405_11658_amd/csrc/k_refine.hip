@@ -293,7 +293,7 @@ __global__ __launch_bounds__(256) void k_rhub_gather(RefineArgs a) {
   __syncthreads();
   const int nu = nused;
   const int64_t t0 = a.hp.htab[h];
-  const uint32_t mask = (uint32_t)(a.hp.htab[h + 1] - t0 - 1);
+  const uint32_t mask = (uint32_t)(a.hp.hcap[h] - 1);
   for (int k = threadIdx.x; k < nu; k += blockDim.x) {
     const int s = used[k];
     const int cs = keys[s];
@@ -310,10 +310,11 @@ __global__ __launch_bounds__(256) void k_rhub_score(RefineArgs a) {
   const int i = a.hp.hubv[h];
   if (!a.act[i]) return;
   const int64_t s0 = a.hp.htab[h] + (q - a.hp.hsg[h]) * kHubSeg;
+  const int64_t s1 = s0 + min((int64_t)kHubSeg, a.hp.hcap[h]);
   const double Ki = a.K[i], Sd = a.Sig[i], bown = a.hp.own[h];
   double bg = 0.0;
   int bc = kNoComm;
-  for (int64_t s = s0 + threadIdx.x; s < s0 + kHubSeg; s += blockDim.x) {
+  for (int64_t s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
     const int c = a.hp.keys[s];
     if (c == kEmpty) continue;
     const double v = a.hp.vals[s];

@@ -1,10 +1,5 @@
 // Utility kernels: fills, label maps, CSR chunk mapping, row sums, checks,
-// degree buckets, and the rocPRIM-backed scans and sorts.
-#include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/device/device_reduce_by_key.hpp>
-#include <rocprim/iterator/transform_iterator.hpp>
-#include <rocprim/device/device_scan.hpp>
-#include <rocprim/device/device_segmented_radix_sort.hpp>
+// degree buckets.
 
 #include "device.hpp"
 #include "kernels.hpp"
@@ -158,64 +153,6 @@ void check_rows_chunked(const int64_t *off, const int32_t *idx, const float *w, 
                         const int32_t *crow, int32_t *err, hipStream_t s) {
   if (nnz > 0)
     hipLaunchKernelGGL(k_check_rows, (int)ceil_div(nnz, kChunk), 256, 0, s, off, idx, w, n, nnz, crow, err);
-}
-
-// ---- rocPRIM wrappers ---------------------------------------------------------
-size_t scan_excl_i32(void *temp, size_t tbytes, const int32_t *in, int32_t *out, int64_t n, hipStream_t s) {
-  size_t bytes = tbytes;
-  (void)rocprim::exclusive_scan(temp, bytes, in, out, (int32_t)0, (size_t)n, rocprim::plus<int32_t>(), s);
-  return bytes;
-}
-size_t scan_excl_i64(void *temp, size_t tbytes, const int64_t *in, int64_t *out, int64_t n, hipStream_t s) {
-  size_t bytes = tbytes;
-  (void)rocprim::exclusive_scan(temp, bytes, in, out, (int64_t)0, (size_t)n, rocprim::plus<int64_t>(), s);
-  return bytes;
-}
-size_t scan_excl_i32_to_i64(void *temp, size_t tbytes, const int32_t *in, int64_t *out, int64_t n,
-                            hipStream_t s) {
-  size_t bytes = tbytes;
-  (void)rocprim::exclusive_scan(temp, bytes, in, out, (int64_t)0, (size_t)n, rocprim::plus<int64_t>(), s);
-  return bytes;
-}
-size_t sort_pairs_u64_i32(void *temp, size_t tbytes, const unsigned long long *kin,
-                          unsigned long long *kout, const int32_t *vin, int32_t *vout, int64_t n,
-                          hipStream_t s) {
-  size_t bytes = tbytes;
-  (void)rocprim::radix_sort_pairs(temp, bytes, kin, kout, vin, vout, (size_t)n, 0, 64, s);
-  return bytes;
-}
-size_t sort_pairs_u64_f32(void *temp, size_t tbytes, const unsigned long long *kin, unsigned long long *kout,
-                          const float *vin, float *vout, int64_t n, int end_bit, hipStream_t s) {
-  size_t bytes = tbytes;
-  (void)rocprim::radix_sort_pairs(temp, bytes, kin, kout, vin, vout, (size_t)n, 0, end_bit, s);
-  return bytes;
-}
-struct ToF64 {
-  __host__ __device__ double operator()(float x) const { return (double)x; }
-};
-size_t reduce_by_key_u64_f32(void *temp, size_t tbytes, const unsigned long long *keys, const float *vals,
-                             int64_t n, unsigned long long *ukeys, double *sums, unsigned long long *count,
-                             hipStream_t s) {
-  size_t bytes = tbytes;
-  (void)rocprim::deterministic_reduce_by_key(temp, bytes, keys, rocprim::make_transform_iterator(vals, ToF64()),
-                                             (size_t)n, ukeys, sums, count, rocprim::plus<double>(),
-                                             rocprim::equal_to<unsigned long long>(), s);
-  return bytes;
-}
-size_t sort_pairs_u64_f64(void *temp, size_t tbytes, const unsigned long long *kin,
-                          unsigned long long *kout, const double *vin, double *vout, int64_t n,
-                          hipStream_t s) {
-  size_t bytes = tbytes;
-  (void)rocprim::radix_sort_pairs(temp, bytes, kin, kout, vin, vout, (size_t)n, 0, 64, s);
-  return bytes;
-}
-size_t seg_sort_i32_f32(void *temp, size_t tbytes, const int32_t *kin, int32_t *kout,
-                        const float *vin, float *vout, int64_t nnz, int64_t nseg,
-                        const int64_t *off, hipStream_t s) {
-  size_t bytes = tbytes;
-  (void)rocprim::segmented_radix_sort_pairs(temp, bytes, kin, kout, vin, vout, (unsigned int)nnz,
-                                      (unsigned int)nseg, off, off + 1, 0, 32, s);
-  return bytes;
 }
 
 }  // namespace lk

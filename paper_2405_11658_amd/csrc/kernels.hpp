@@ -57,7 +57,7 @@ void check_rows_chunked(const int64_t *off, const int32_t *idx, const float *w, 
                         const int32_t *crow, int32_t *err, hipStream_t s);
 void check_offsets(const int64_t *off, int64_t n, int64_t nnz, int32_t *err, hipStream_t s);
 
-// rocPRIM-backed primitives.  temp == nullptr returns the temp size needed.
+// ---- k_prim.hip: scans and radix sort (temp == nullptr returns the temp size) ----
 size_t scan_excl_i32(void *temp, size_t tbytes, const int32_t *in, int32_t *out, int64_t n, hipStream_t s);
 size_t scan_excl_i64(void *temp, size_t tbytes, const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
 size_t scan_excl_i32_to_i64(void *temp, size_t tbytes, const int32_t *in, int64_t *out, int64_t n,
@@ -70,14 +70,56 @@ size_t sort_pairs_u64_i32(void *temp, size_t tbytes, const unsigned long long *k
 size_t sort_pairs_u64_f64(void *temp, size_t tbytes, const unsigned long long *kin,
                           unsigned long long *kout, const double *vin, double *vout, int64_t n,
                           hipStream_t s);
-size_t sort_pairs_u64_f32(void *temp, size_t tbytes, const unsigned long long *kin, unsigned long long *kout,
-                          const float *vin, float *vout, int64_t n, int end_bit, hipStream_t s);
-size_t reduce_by_key_u64_f32(void *temp, size_t tbytes, const unsigned long long *keys, const float *vals,
-                             int64_t n, unsigned long long *ukeys, double *sums, unsigned long long *count,
-                             hipStream_t s);
 size_t seg_sort_i32_f32(void *temp, size_t tbytes, const int32_t *kin, int32_t *kout,
                         const float *vin, float *vout, int64_t nnz, int64_t nseg,
                         const int64_t *off, hipStream_t s);
+
+constexpr int kPT = 256;                  // threads of a primitive workgroup
+constexpr int kPR = 16;                   // rounds of kPT items per tile
+constexpr int64_t kPTile = kPT * kPR;     // items per tile
+
+// Segments of a radix sort: tiles of kPTile items that never cross a segment.
+// With tseg == nullptr there is one segment, items [0, n).
+struct RsSeg {
+  int64_t ntiles;
+  int64_t n;
+  const int32_t *tseg;    // [ntiles] segment of each tile
+  const int64_t *tfirst;  // [nseg + 1] first tile of each segment
+  const int64_t *sbeg;    // [nseg] first item of each segment
+  const int64_t *send;    // [nseg] end of each segment
+};
+struct TileSpan {
+  int64_t f0, nt;  // first tile and tile count of the tile's segment
+  int64_t lo, hi;  // the tile's items
+  int64_t sb;      // first item of the segment
+};
+__device__ __forceinline__ TileSpan tile_span(const RsSeg &g, int64_t t) {
+  TileSpan r;
+  if (!g.tseg) {
+    r.f0 = 0;
+    r.nt = g.ntiles;
+    r.sb = 0;
+    r.lo = t * kPTile;
+    r.hi = r.lo + kPTile < g.n ? r.lo + kPTile : g.n;
+    return r;
+  }
+  const int s = g.tseg[t];
+  r.f0 = g.tfirst[s];
+  r.nt = g.tfirst[s + 1] - r.f0;
+  r.sb = g.sbeg[s];
+  r.lo = r.sb + (t - r.f0) * kPTile;
+  r.hi = r.lo + kPTile < g.send[s] ? r.lo + kPTile : g.send[s];
+  return r;
+}
+RsSeg rs_plain(int64_t n);
+int rs_passes(int bits);
+size_t rs_tmp_bytes(int64_t ntiles);
+int key_bits(unsigned long long x);  // bits needed for x (0 for 0)
+// Stable sort of every segment by the low `bits` key bits; (k1, v1) are
+// scratch buffers covering the same items; the result is in (k0, v0).  tmp:
+// rs_tmp_bytes(g.ntiles) bytes.
+template <class K, class V>
+void rsort(K *k0, V *v0, K *k1, V *v1, const RsSeg &g, int bits, void *tmp, hipStream_t s);
 
 // ---- k_move.hip -------------------------------------------------------------
 // Hub plan of a level: the vertices of the largest degree bucket grouped by
@@ -86,14 +128,17 @@ size_t seg_sort_i32_f32(void *temp, size_t tbytes, const int32_t *kin, int32_t *
 constexpr int64_t kHubDeg = 2048;  // degree above which a vertex is a hub
 constexpr int kHubEC = 512;        // edges per gather workgroup
 constexpr int kHubSeg = 4096;      // table slots per scoring workgroup
+constexpr int64_t kHubMinCap = 256; // smallest hub table (a power of two)
 struct HubPlan {
   int32_t *hubv;   // [nhub] hub ids, slice-major
   int64_t *hch;    // [nhub+1] first edge chunk of each hub
-  int64_t *htab;   // [nhub+1] first table slot (table sizes are powers of two)
+  int64_t *htab;   // [nhub] first table slot, counted from the start of the hub's slice
+  int64_t *hcap;   // [nhub] table slots (a power of two, at least 2 * degree)
   int64_t *hsg;    // [nhub+1] first table segment
   int32_t *chub;   // hub index of each chunk
   int32_t *shub;   // hub index of each segment
-  int *keys;       // tables, kEmpty when free (scoring leaves them free again)
+  int *keys;       // tables of one slice (shared by the slices), kEmpty when free;
+                   // scoring leaves them free again
   double *vals;
   double *own;     // [nhub] weight to the hub's own community (zero between uses)
   double *pg;      // per-segment best gain
@@ -162,6 +207,7 @@ void hub_find(const int64_t *off, int64_t n, int S, int64_t hubdeg, const int32_
 void hub_sizes(const int64_t *off, const int32_t *hubv, int64_t nhub, int64_t *nch, int64_t *ncap, int64_t *nseg,
                hipStream_t s);
 void hub_expand(const HubPlan &h, int64_t nhub, hipStream_t s);
+void hub_rel(int64_t *htab, int64_t nhub, const int32_t *hub_soff, int S, const int64_t *slice_base, hipStream_t s);
 void gather_bounds(const int64_t *arr, const int32_t *at, int count, int64_t *out, hipStream_t s);
 // region_h: host copy of the region starts of this level.
 void move_frontier(const MoveArgs &a, hipStream_t s);
@@ -235,13 +281,26 @@ struct AggArgs {
   const float *w;
   const int32_t *C;
 };
-void agg_keys(const AggArgs &a, const int32_t *crow, unsigned long long *keys, float *vals, hipStream_t s);
-void agg_flag(int64_t n, const int64_t *off, const int32_t *C, int32_t *flag, hipStream_t s);
-void agg_relabel(int64_t n, const int64_t *off, const int32_t *C, const int32_t *cmap, int32_t *Cc, hipStream_t s);
-void agg_inv(int64_t ncomm, const int32_t *flag, const int32_t *cmap, int32_t *inv, hipStream_t s);
-// inv nullable (keys over the original labels); K nullable, zeroed by the caller
-void agg_rows(const unsigned long long *ukeys, const double *sums, int64_t nu, int64_t ncomm, const int32_t *inv,
-              int32_t *out_idx, float *out_w, int32_t *rowlen, double *K, hipStream_t s);
+constexpr int kAggSmall = 1024;  // segments up to this many entries are sorted in LDS
+void agg_vkeys(int64_t n, const int32_t *C, uint32_t *keys, int32_t *vals, hipStream_t s);
+void agg_vdeg(int64_t n, const int64_t *off, const int32_t *vs, int64_t *deg, int32_t *pos, hipStream_t s);
+void agg_cdeg(int64_t n, const uint32_t *Cs, const int64_t *eoff, int64_t *hpos, int64_t *cdeg, hipStream_t s);
+void agg_group(const AggArgs &a, const int32_t *crow, const int32_t *pos, const int64_t *eoff, uint32_t *gkey,
+               float *gval, hipStream_t s);
+void agg_windows(const int64_t *seg, int64_t ncomm, int64_t nst, int32_t *tfc, hipStream_t s);
+void agg_small(const int64_t *seg, const int32_t *tfc, int64_t nst, int cb, const uint32_t *gkey, const float *gval,
+               uint32_t *ukey, float *uval, int32_t *rowlen, double *K, hipStream_t s);
+void agg_large_flags(const int64_t *seg, int64_t ncomm, int32_t *flag, hipStream_t s);
+void agg_large_list(const int64_t *seg, int64_t ncomm, int32_t *flag, const int32_t *lidx, int32_t *lc, int64_t *lsb,
+                    int64_t *lse, int64_t *ltn, hipStream_t s);
+void agg_tile_seg(const int64_t *tfirst, int64_t nl, int32_t *tseg, hipStream_t s);
+void agg_large_runs(int pass, const uint32_t *gkey, const float *gval, const RsSeg &g, int64_t *hc, double *tin,
+                    uint32_t *ukey, float *uval, hipStream_t s);
+void agg_large_rows(int64_t nl, const int32_t *lc, const int64_t *lsb, const int64_t *tfirst, const int64_t *hc,
+                    const float *uval, int32_t *rowlen, double *K, hipStream_t s);
+void agg_compact(const int64_t *seg, const int32_t *tfc, int64_t nst, const int32_t *lc, const int64_t *lsb,
+                 int64_t nl, const int32_t *rowlen, const int64_t *out_off, const uint32_t *ukey, const float *uval,
+                 int32_t *out_idx, float *out_w, hipStream_t s);
 
 // ---- k_modularity.hip --------------------------------------------------------
 // acc[0] += sigma total, S[c] += K-contributions (S zeroed, ncomm = n)

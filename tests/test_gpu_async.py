@@ -96,23 +96,30 @@ def test_async_wave_counts(waves):
 
 
 def test_async_quality_vs_oracle_rmat():
-    """Static then DF on id-permuted RMAT graphs: mean gap to the oracle's
-    serial asynchronous modularity."""
+    """The default DF update against the serial oracle's DF update of the same
+    batch, both from the oracle's static membership installed on a fresh
+    handle, on id-permuted RMAT-18 graphs (two seeds, five batches of 1e-4
+    |E| each): the mean modularity gap over the ten updates lies within 1e-3
+    either way.  Single updates of the two sweep orders differ by about 1e-3,
+    so the gate is on the mean; the static runs' gaps are reported."""
     gaps = []
     for seed in (1, 2):
-        g = gen.rmat(15, 16, seed=seed)
+        g = gen.rmat(18, 16, seed=seed)
+        ost, _ = oracle.static(og(g))
         h = L.leiden_create(g.off, g.idx, g.w)
         C, q, st = L.leiden_static(h)
-        ost, _ = oracle.static(og(g))
-        gaps.append(q - oracle.modularity(og(g), ost.C))
-        b = gen.random_batch(g, gen.batch_count(g.nnz, 1e-4), seed=3)
-        L.leiden_set_state(h, ost.C)
-        C, q, st, _ = L.leiden_update(h, dev_batch(b), "df")
-        new, _, _, _ = oracle.update(ost, ob(b), "df")
-        gaps.append(q - oracle.modularity(new.g, new.C))
+        say("rmat18 seed", seed, "static gap", q - oracle.modularity(og(g), ost.C))
+        for k in range(5):
+            b = gen.random_batch(g, gen.batch_count(g.nnz, 1e-4), seed=700 + k)
+            h = L.leiden_create(g.off, g.idx, g.w)
+            L.leiden_set_state(h, ost.C)
+            C, q, st, _ = L.leiden_update(h, dev_batch(b), "df")
+            _check_state(h, _graph_of(h), C, q)
+            new, _, _, _ = oracle.update(ost, ob(b), "df")
+            gaps.append(q - oracle.modularity(new.g, new.C))
     gaps = np.array(gaps)
-    say("rmat15 async Q_gpu - Q_oracle:", np.round(gaps, 5).tolist(), "mean", round(float(gaps.mean()), 5))
-    assert gaps.mean() >= -3e-3
+    say("rmat18 DF Q_gpu - Q_oracle:", np.round(gaps, 5).tolist(), "mean", round(float(gaps.mean()), 5))
+    assert abs(gaps.mean()) <= 1e-3
 
 
 @pytest.mark.parametrize("name,g", [
@@ -126,16 +133,18 @@ def test_async_one_wavefront_is_the_serial_oracle(name, g):
     is the oracle's serial asynchronous reading of Alg. leidenMove and
     leidenRefine: static Leiden and ND / DS / DF updates must then give the
     oracle's serial membership element by element (graphs without vertices
-    of degree > 2048, which take the multi-workgroup hub path)."""
+    of degree > 2048 and the hub threshold at 2048, so that no vertex takes
+    the multi-workgroup hub path)."""
     assert np.diff(g.off).max() <= 2048
-    h = L.leiden_create(g.off, g.idx, g.w, L.leiden_default_params(async_waves=1))
+    one = L.leiden_default_params(async_waves=1, hub_degree=2048)
+    h = L.leiden_create(g.off, g.idx, g.w, one)
     C, q, st = L.leiden_static(h)
     ref, rst = oracle.static(og(g))
     assert np.array_equal(to_np(C), ref.C), name
     assert st["move_iters"] == rst["move_iters"] and st["passes"] == rst["passes"]
     say(name, "one-wavefront static equals the serial oracle, passes", st["passes"])
     for k, mode in enumerate(("df", "ds", "nd")):
-        h = L.leiden_create(g.off, g.idx, g.w, L.leiden_default_params(async_waves=1))
+        h = L.leiden_create(g.off, g.idx, g.w, one)
         L.leiden_set_state(h, ref.C)
         b = gen.random_batch(g, gen.batch_count(g.nnz, 1e-3), seed=40 + k)
         C, q, st, _ = L.leiden_update(h, dev_batch(b), mode)

@@ -8,8 +8,6 @@ full: modularity of the returned membership (relative 1e-9), the stored K,
 Sigma and 2m (exact, unit weights), the aggregated super-vertex CSR for the
 returned membership (exact after sorting each row), the graph after a batch
 (exact) and the DF and DS affected / in-range / changed flags (exact)."""
-import os
-
 import numpy as np
 import pytest
 import torch
@@ -98,9 +96,6 @@ def test_grid4096_full_size():
     _full_size(g, [("df", 1e-5), ("df", 1e-3)])
 
 
-@pytest.mark.skipif(os.environ.get("LEIDEN_RMAT26") != "1",
-                    reason="RMAT scale 26 (~1.9e9 entries, ~150 GB of HBM, ~60 GB of host memory, "
-                           "minutes): run with LEIDEN_RMAT26=1")
 def test_rmat26_full_size():
     """Web/social-like RMAT scale 26, edge factor 16 (67M vertices, ~1.9e9
     directed entries, hubs above 1e5), generated on the device.  Checked: the
@@ -196,29 +191,44 @@ def test_rmat26_full_size():
     say("df checked: affected", int(dV.sum()), "changed", int(dC.sum()))
 
 
-@pytest.mark.skipif(os.environ.get("LEIDEN_QUALITY") != "1",
-                    reason="five serial oracle DF updates on RMAT-22 (~90 s of host time): run with LEIDEN_QUALITY=1")
-def test_rmat22_df_quality_vs_oracle_from_same_state():
-    """The default asynchronous DF update against the serial oracle's DF
-    update, both started from the oracle's static membership, on five
-    batches of 1e-4 |E|: the mean modularity gap must be within 1e-3 and no
-    batch more than 2e-3 below (the two are different orders of the same
-    heuristic; the gate is on their modularity)."""
-    g = gen.rmat(22, 16, seed=1)
+def _same_state_gaps(g, frac, seeds, label):
+    """The library's default (asynchronous) DF update against the serial
+    oracle's DF update of the same batch, both from the oracle's static
+    membership installed on a fresh handle; returns Q_gpu - Q_oracle per
+    batch."""
     ost, _ = oracle.static(og(g), oracle.make_params())
-    say("oracle static Q", oracle.modularity(og(g), ost.C))
+    say(label, "oracle static Q", oracle.modularity(og(g), ost.C))
     C0 = torch.from_numpy(np.ascontiguousarray(ost.C)).cuda()
     gaps = []
-    for k in range(5):
-        b = gen.random_batch(g, gen.batch_count(g.nnz, 1e-4), seed=700 + k)
+    for k in seeds:
+        b = gen.random_batch(g, gen.batch_count(g.nnz, frac), seed=k)
         h = L.leiden_create(g.off, g.idx, g.w)
         L.leiden_set_state(h, C0)
-        _, q, _, _ = L.leiden_update(h, dev_batch(b), "df")
+        _, q, st, _ = L.leiden_update(h, dev_batch(b), "df")
         del h
-        o2, _, _, _ = oracle.update(ost, ob(b), "df", oracle.make_params())
+        o2, _, _, ost2 = oracle.update(ost, ob(b), "df", oracle.make_params())
         qo = oracle.modularity(o2.g, o2.C)
         gaps.append(q - qo)
-        say("batch", k, "Q", q, "oracle", qo, "gap", q - qo)
-    gaps = np.array(gaps)
-    assert gaps.mean() >= -1e-3, gaps
-    assert gaps.min() >= -2e-3, gaps
+        say(label, "batch", k, "Q", q, "oracle", qo, "gap", q - qo, "passes", st["passes"], ost2["passes"])
+    return np.array(gaps)
+
+
+def test_rmat22_df_quality_vs_oracle_from_same_state():
+    """Gate of the asynchronous fast path on RMAT-22 (the headline graph
+    family): DF updates of five batches of 1e-4 |E| from the same installed
+    membership on both sides; the mean modularity gap to the serial oracle
+    must lie within 1e-3 either way (single updates of two different orders
+    of the same heuristic differ by about 1e-3, so the gate is on the mean)."""
+    g = gen.rmat(22, 16, seed=1)
+    gaps = _same_state_gaps(g, 1e-4, range(700, 705), "rmat22")
+    say("rmat22 gaps", np.round(gaps, 5).tolist(), "mean", gaps.mean())
+    assert abs(gaps.mean()) <= 1e-3, gaps
+
+
+def test_grid4096_df_quality_vs_oracle_from_same_state():
+    """The same gate on the road-like 4096 x 4096 grid with DF batches of
+    1e-3 |E| (69k updates each)."""
+    g = gen.grid2d(4096, 0.05, 0.02, seed=1)
+    gaps = _same_state_gaps(g, 1e-3, range(710, 715), "grid4096")
+    say("grid4096 gaps", np.round(gaps, 5).tolist(), "mean", gaps.mean())
+    assert abs(gaps.mean()) <= 1e-3, gaps

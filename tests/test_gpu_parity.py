@@ -63,6 +63,29 @@ def test_aggregate_parity(name, g):
         assert canon_rows(to_np(off), to_np(idx), to_np(w)) == canon_rows(ref.off, ref.idx, ref.w)
 
 
+def test_aggregate_parity_long_rows():
+    """Memberships whose communities own thousands of entries each (rows that
+    span several 4096-entry tiles of the segmented sort, runs of one neighbour
+    community that cross tile boundaries) mixed with small ones, on an RMAT
+    graph with hubs."""
+    g = gen.rmat(16, 16, seed=5)
+    rng = np.random.default_rng(2)
+    deg = np.diff(g.off)
+    for k in (2, 64, 700):
+        C = rng.integers(0, k, g.n).astype(np.int32)
+        # the hubs and a block of vertices get communities of their own
+        C[np.argsort(deg)[-50:]] = np.arange(k, k + 50, dtype=np.int32)
+        C[: g.n // 8] = rng.integers(k + 50, k + 50 + g.n // 16, g.n // 8)
+        _, C = np.unique(C, return_inverse=True)
+        C = C.astype(np.int32)
+        ncomm = int(C.max()) + 1
+        say("aggregate long rows rmat16 ncomm", ncomm)
+        off, idx, w = L.leiden_aggregate(g.off, g.idx, g.w, C, ncomm)
+        ref = oracle.aggregate(og(g), C, ncomm)
+        assert np.array_equal(to_np(off), ref.off)
+        assert canon_rows(to_np(off), to_np(idx), to_np(w)) == canon_rows(ref.off, ref.idx, ref.w)
+
+
 def _static_pair(g, params_gpu, params_or):
     h = L.leiden_create(g.off, g.idx, g.w, params_gpu)
     C, q, st = L.leiden_static(h)

@@ -66,13 +66,14 @@ def test_autotune_keeps_state_and_installs_a_candidate():
     C0 = L.leiden_get_state(h)[0].clone()
     bs = gen.batch_stream(g, gen.batch_count(g.nnz, 1e-3), 3, seed=5)
     warm, sample, _ = [L.make_batch(b.del_u, b.del_v, b.ins_u, b.ins_v, b.ins_w) for b in bs]
-    p, ref, res = autotune(h, warm, sample, waves=(64, 256), slices=(64, 128), reps=2)
-    say("autotune reference", ref, "results", res, "chose", p.async_waves, p.hub_slices)
-    assert len(res) == 4
-    chosen = (p.async_waves, p.hub_slices)
-    if chosen != (0, 0):
-        r = [r for r in res if (r[0], r[1]) == chosen][0]
-        assert r[3] >= ref[1] - 5e-4 and r[2] < ref[0]
+    d = L.leiden_default_params()
+    p, ref, res = autotune(h, warm, sample, waves=(64, 256), slices=(64, 128), hubdeg=(128, 512), reps=2)
+    say("autotune reference", ref, "results", res, "chose", p.async_waves, p.hub_slices, p.hub_degree)
+    assert len(res) == 8
+    chosen = (p.async_waves, p.hub_slices, p.hub_degree)
+    if chosen != (d.async_waves, d.hub_slices, d.hub_degree):
+        r = [r for r in res if (r[0], r[1], r[2]) == chosen][0]
+        assert r[4] >= ref[1] - 5e-4 and r[3] < ref[0]
     off1, idx1, w1 = L.leiden_get_graph(h)
     assert torch.equal(off0, off1) and torch.equal(idx0, idx1) and torch.equal(w0, w1)
     assert torch.equal(C0, L.leiden_get_state(h)[0])
