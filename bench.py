@@ -31,15 +31,15 @@ oracle (test infrastructure) doing one DF update of the first RMAT-22 batch
 after its own static run (untimed preparation), edges/s = |E^t| / its time,
 one host thread.  The oracle cannot run the RMAT-26 stream within minutes.
 
-roofline: the kernel timed by the library (leiden_params.profile: HIP events
-around each launch, on the call's stream) with the largest share of the timed
-steps; achieved = algorithmic bytes per launch / average launch time.
-Algorithmic bytes per unit: hub gather 12 B per scanned entry (id, weight,
-community of the neighbour); aggregation merge 12 B per entry plus 12 B per
-member vertex; modularity scan 12 B per entry plus 4 B per vertex; graph
-update merge 16 B per entry plus 16 B per vertex; asynchronous local-moving
-sweep 12 B per scanned edge plus 34 B per evaluated vertex (Sigma reads and
-neighbour marks not counted: a lower bound).  traffic = HBM bytes per launch
+roofline: the single kernel timed by the library (leiden_params.profile: HIP
+events around each launch, on the call's stream) with the largest share of the
+timed steps (the aggregation, timed as one region of several kernels, is
+reported beside it); achieved = algorithmic bytes per launch / average launch
+time.  Algorithmic bytes per unit: hub gather 12 B per scanned entry (id,
+weight, community of the neighbour); modularity scan 12 B per entry plus 4 B
+per vertex; graph update merge 16 B per entry plus 16 B per vertex;
+asynchronous local-moving sweep 12 B per scanned edge plus 34 B per evaluated
+vertex (Sigma reads and neighbour marks not counted: a lower bound).  traffic = HBM bytes per launch
 from the committed counter runs (profiles/traffic.json) when they were taken
 on the current kernel sources and this workload, else null.
 """
@@ -67,7 +67,7 @@ BYTES_PER_UNIT = {  # (per entry, per vertex)
 }
 PROF_KERNEL_NAMES = {  # symbol of each timed kernel, as rocprofv3 lists it
     "hub_gather": "lk::k_hub_gather(lk::MoveArgs)",
-    "agg_merge": "lk::k_agg_keys",
+    "agg_merge": "aggregation region (k_agg_*, k_rs_*, k_scan_*)",
     "mod_scan": "lk::k_mod_edges",
     "batch_merge": "lk::k_batch_apply_old(lk::BatchArgs)",
     "move_sweep": "lk::k_move_async",  # both launch shapes, <4, 512> and <2, 2048>
@@ -98,12 +98,82 @@ def measured_traffic(kernel: str, workload: str):
         return None
     entry = json.load(open(path)).get(kernel)
     if not entry or entry.get("workload") != workload:
-        return None
+        return None  # another graph, front-end or batch size
     h = hashlib.sha256()
     for p in sorted(glob.glob(os.path.join(HERE, "paper_2405_11658_amd", "csrc", "*"))):
         with open(p, "rb") as f:
             h.update(f.read())
     return entry["bytes_per_launch"] if entry.get("source_sha256") == h.hexdigest() else None
+
+
+# ---- summaries of rocprofv3 results (run on any host, from the .db files) ----
+def _trace_rows(db: str):
+    import sqlite3
+    con = sqlite3.connect(db)
+    return con.execute("select name, start, end, dispatch_id from kernels order by start").fetchall()
+
+
+def _update_window(rows):
+    """[start, end) of the dynamic updates of a bench run: from the first
+    graph-update merge to the end of the first modularity scan after the last
+    one (static runs come before and after)."""
+    merges = [r for r in rows if r[0].startswith("lk::k_batch_apply_old")]
+    if not merges:
+        return None
+    last = merges[-1][1]
+    ends = [r[2] for r in rows if r[0].startswith("lk::k_mod_edges") and r[1] > last]
+    return merges[0][1], (ends[0] if ends else rows[-1][2]), len(merges)
+
+
+def summarize_trace(db: str, command: str) -> str:
+    rows = _trace_rows(db)
+    out = ["Command:", "", "    " + command, ""]
+    tot = sum(r[2] - r[1] for r in rows)
+    out.append(f"Whole process: {tot / 1e6:.1f} ms of kernels over {len(rows)} dispatches.")
+    win = _update_window(rows)
+    if win:
+        a, b, nup = win
+        sel = [r for r in rows if a <= r[1] < b]
+        ktime = sum(r[2] - r[1] for r in sel)
+        out.append(f"Dynamic updates: {nup} (window from the first graph-update merge to the last update's "
+                   f"modularity scan): {(b - a) / 1e6 / nup:.1f} ms span and {ktime / 1e6 / nup:.1f} ms of kernels "
+                   f"per update, {len(sel) / nup:.0f} dispatches per update.")
+        out += ["", "| kernel (dynamic updates) | ms per update | launches per update | avg us |", "|---|---|---|---|"]
+        agg = {}
+        for r in sel:
+            k = r[0].split("(")[0][:90]
+            a_ = agg.setdefault(k, [0, 0])
+            a_[0] += r[2] - r[1]
+            a_[1] += 1
+        for k, (t, c) in sorted(agg.items(), key=lambda kv: -kv[1][0])[:30]:
+            out.append(f"| `{k}` | {t / 1e6 / nup:.2f} | {c / nup:.1f} | {t / 1e3 / c:.1f} |")
+    return "\n".join(out)
+
+
+def _pmc(db: str, counter: str):
+    import sqlite3
+    con = sqlite3.connect(db)
+    q = ("select k.name, k.start, p.counter_value from pmc_events p join kernels k on k.dispatch_id = p.dispatch_id "
+         "where p.counter_name = ? order by k.start")
+    return con.execute(q, (counter,)).fetchall()
+
+
+def traffic_from_pmc(fetch_db: str, write_db: str, kernel: str, key: str) -> dict:
+    """HBM bytes per launch of `kernel` in the dynamic updates: FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch) scaled so that the 1 GiB calibration kernel
+    (an elementwise multiply at the end of the run) reads and writes 1 GiB."""
+    res = {"workload": key}
+    for db, counter, tag in ((fetch_db, "FETCH_SIZE", "fetch"), (write_db, "WRITE_SIZE", "write")):
+        rows = _pmc(db, counter)
+        cal = [r for r in rows if "MulFunctor" in r[0]]
+        factor = (1 << 30) / (cal[-1][2] * 1024.0)
+        win = _update_window(_trace_rows(db))
+        sel = [r[2] for r in rows if r[0].startswith(kernel) and win[0] <= r[1] < win[1]]
+        res[tag + "_kib"] = round(float(np.mean(sel)), 1)
+        res[tag + "_factor"] = round(factor, 4)
+        res[tag + "_launches"] = len(sel)
+    res["bytes_per_launch"] = int(res["fetch_kib"] * 1024 * res["fetch_factor"] + res["write_kib"] * 1024 * res["write_factor"])
+    return res
 
 
 def cpu_model() -> str:
@@ -176,8 +246,28 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle leg")
     ap.add_argument("--no-rmat22", action="store_true", help="skip the RMAT-22 leg (and the oracle)")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="end with a 1 GiB device-to-device copy (reference for counter runs)")
+                    help="end with a kernel that reads and writes 1 GiB (reference for counter runs)")
+    ap.add_argument("--summarize-trace", metavar="DB", help="print a markdown summary of a rocprofv3 kernel trace")
+    ap.add_argument("--command", default="", help="the command that made the trace (for --summarize-trace)")
+    ap.add_argument("--traffic", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="print the HBM traffic entry of --kernel from two counter runs")
+    ap.add_argument("--kernel", default="void lk::k_move_async")
+    ap.add_argument("--traffic-key", default="rmat26_ef16_df_f0.0001")
     args = ap.parse_args()
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace, args.command))
+        return 0
+    if args.traffic:
+        import glob
+        import hashlib
+        e = traffic_from_pmc(args.traffic[0], args.traffic[1], args.kernel, args.traffic_key)
+        h = hashlib.sha256()
+        for p in sorted(glob.glob(os.path.join(HERE, "paper_2405_11658_amd", "csrc", "*"))):
+            with open(p, "rb") as f:
+                h.update(f.read())
+        e["source_sha256"] = h.hexdigest()
+        print(json.dumps(e, indent=1))
+        return 0
 
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); the library has no "
@@ -196,6 +286,7 @@ def main() -> int:
     torch.cuda.set_device(0)
     L.load()
     workload = f"rmat{args.scale}_ef{args.edge_factor}_{args.mode}_f{args.frac:g}_stream{args.steps}"
+    traffic_key = f"rmat{args.scale}_ef{args.edge_factor}_{args.mode}_f{args.frac:g}"  # per-launch traffic
 
     # ---- the headline stream on the device-generated graph ----
     t = time.time()
@@ -221,7 +312,9 @@ def main() -> int:
     entries = float(np.mean(r["ents"]))
     value = entries / (ms_per_step / 1e3)
     prof = r["prof"]
-    dom = max(prof, key=lambda k: prof[k]["ms"])
+    # the aggregation is timed as one region of several kernels, so the
+    # roofline names the dominant single kernel among the others
+    dom = max((k for k in prof if k != "agg_merge"), key=lambda k: prof[k]["ms"])
     pd = prof[dom]
     roofline = None
     if pd["launches"] > 0 and pd["ms"] > 0:
@@ -231,7 +324,7 @@ def main() -> int:
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic(PROF_KERNEL_NAMES[dom], workload),
+                    "traffic": measured_traffic(PROF_KERNEL_NAMES[dom], traffic_key),
                     "kernel": PROF_KERNEL_NAMES[dom], "avg_launch_us": round(avg_ms * 1e3, 2),
                     "launches_per_step": pd["launches"] / args.steps,
                     "algorithmic_bytes_per_launch": round(bytes_per_launch),
@@ -289,12 +382,14 @@ def main() -> int:
                               f"os.cpu_count()={os.cpu_count()}")}
 
     if args.copy_calibration:
+        # an elementwise kernel that reads 1 GiB and writes 1 GiB: the
+        # reference dispatch for scaling the FETCH_SIZE / WRITE_SIZE counters
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        torch.mul(src, 2.0, out=dst)
         torch.cuda.synchronize()
-        log("1 GiB calibration copy done")
+        log("1 GiB calibration kernel done")
 
     lat = r["lat"]
     out = {

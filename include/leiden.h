@@ -113,9 +113,9 @@ typedef struct {
  *   HUB_GATHER  - local-moving edge scan of the hubs (degree > hub_degree; one
  *                 launch per slice and iteration with hubs in the frontier);
  *                 entries = edges scanned;
- *   AGG_MERGE   - aggregation entry merge, one launch per aggregated level;
- *                 entries = level CSR entries, vertices = level vertices with
- *                 edges;
+ *   AGG_MERGE   - the aggregation of a level up to its row lengths (several
+ *                 kernels, timed as one region per aggregated level);
+ *                 entries = level CSR entries, vertices = level vertices;
  *   MOD_SCAN    - modularity edge scan; entries / vertices of the graph;
  *   BATCH_MERGE - graph update merge of the old rows with the batch;
  *                 entries = CSR entries of G^t, vertices = n;

@@ -386,6 +386,24 @@ double modularity_dev(Ctx &x, const Level &g, const int32_t *C) {
   return acc[0] / M2 - sq;
 }
 
+// Eq. 1 when Sigma (by label, n entries) and 2m are known: one edge pass for
+// the internal weight, one pass over Sigma.
+double modularity_known(Ctx &x, const Level &g, const int32_t *C, const double *Sig, double M2) {
+  if (!(M2 > 0.0)) return 0.0;
+  DevScal *sc = x.scal();
+  x.zero(sc->acc, 4);
+  hipEvent_t t0 = x.kp ? x.kp->begin() : nullptr;
+  modularity_intra(g.off, g.idx, g.w, g.crow, g.nnz, C, sc->acc, x.s);
+  if (x.kp) x.kp->end(t0, LEIDEN_PROF_MOD_SCAN, g.nnz, g.n);
+  modularity_comm_sq(Sig, g.n, M2, sc->acc, x.s);
+  x.launched("modularity");
+  double acc[4];
+  x.check(hipMemcpyAsync(x.pin(), sc->acc, sizeof(acc), hipMemcpyDeviceToHost, x.s), "D2H");
+  x.check(hipStreamSynchronize(x.s), "sync");
+  memcpy(acc, x.pin(), sizeof(acc));
+  return acc[0] / M2 - acc[2];
+}
+
 // Per-level slice and degree-bucket layout: host copy of the region starts
 // (index s*kNB+b), the device copy, and the vertex-by-slice grouping.
 struct Layout {
@@ -609,12 +627,13 @@ Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, i
       rs.send = lse;
       rsort<uint32_t, float>(gkey, gval, ukey, uval, rs, cb, x.tmp(rs_tmp_bytes(ntl)), x.s);
       int64_t *hc = x.get<int64_t>(A_hc, ntl + 1);
-      double *tin = x.get<double>(A_tin, ntl);
+      double *tin = x.get<double>(A_tin, 2 * ntl);
+      double *tks = tin + ntl;
       x.zero(hc, ntl + 1);
-      agg_large_runs(0, gkey, gval, rs, hc, tin, ukey, uval, x.s);
+      agg_large_runs(0, gkey, gval, rs, hc, tin, ukey, uval, nullptr, x.s);
       scan_i64(x, hc, hc, ntl + 1);
-      agg_large_runs(1, gkey, gval, rs, hc, tin, ukey, uval, x.s);
-      agg_large_rows(nl, lc, lsb, ltn, hc, uval, rowlen, Kout, x.s);
+      agg_large_runs(1, gkey, gval, rs, hc, tin, ukey, uval, Kout ? tks : nullptr, x.s);
+      agg_large_rows(nl, lc, ltn, hc, tks, rowlen, Kout, x.s);
     }
     if (x.kp) x.kp->end(t0, LEIDEN_PROF_AGG_MERGE, g.nnz, g.n);
     x.launched("aggregate");
@@ -1289,7 +1308,7 @@ leiden_status leiden_static(leiden_handle *h, int32_t *membership_out, double *q
     h->M2 = M2;
     h->has_state = true;
     if (membership_out) x.copy(membership_out, (const int32_t *)C, n);
-    if (q_out) *q_out = (n > 0) ? modularity_dev(x, g, C) : 0.0;
+    if (q_out) *q_out = (n > 0) ? modularity_known(x, g, C, Sig, M2) : 0.0;
     tm.mark(CAT_OTHER);
     tm.finish(stats);
     kp.finish(stats, kp.on ? &x.scal()->hub_scanned : nullptr, kp.on ? x.scal()->sweep_work : nullptr);
@@ -1362,7 +1381,7 @@ leiden_status leiden_update(leiden_handle *h, const leiden_batch *batch, int32_t
       x.launched("sigma");
     }
     if (membership_out) x.copy(membership_out, (const int32_t *)h->C.p, n);
-    if (q_out) *q_out = (n > 0) ? modularity_dev(x, g, (const int32_t *)h->C.p) : 0.0;
+    if (q_out) *q_out = (n > 0) ? modularity_known(x, g, (const int32_t *)h->C.p, (const double *)h->Sig.p, h->M2) : 0.0;
     tm.mark(CAT_OTHER);
     tm.finish(stats);
     kp.finish(stats, kp.on ? &x.scal()->hub_scanned : nullptr, kp.on ? x.scal()->sweep_work : nullptr);

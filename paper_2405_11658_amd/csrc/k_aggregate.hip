@@ -98,15 +98,19 @@ void agg_group(const AggArgs &a, const int32_t *crow, const int32_t *pos, const 
 // tfc[t] = first community whose segment starts at or after t * kAggSmall
 // (t in [0, nst]); window t holds the communities [tfc[t], tfc[t + 1]).
 __global__ void k_agg_windows(const int64_t *seg, int64_t ncomm, int64_t nst, int32_t *tfc) {
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c <= ncomm;
-       c += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t tc = c < ncomm ? seg[c] / kAggSmall : nst;
-    const int64_t tp = c == 0 ? -1 : seg[c - 1] / kAggSmall;
-    for (int64_t t = tp + 1; t <= tc && t <= nst; ++t) tfc[t] = (int32_t)c;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t <= nst; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t at = t * kAggSmall;
+    int64_t lo = 0, hi = ncomm;  // first c in [0, ncomm] with seg[c] >= at (seg[ncomm] = nnz)
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (seg[mid] >= at) hi = mid;
+      else lo = mid + 1;
+    }
+    tfc[t] = (int32_t)(t == nst ? ncomm : lo);
   }
 }
 void agg_windows(const int64_t *seg, int64_t ncomm, int64_t nst, int32_t *tfc, hipStream_t s) {
-  hipLaunchKernelGGL(k_agg_windows, flat_grid(ncomm + 1), 256, 0, s, seg, ncomm, nst, tfc);
+  hipLaunchKernelGGL(k_agg_windows, flat_grid(nst + 1), 256, 0, s, seg, ncomm, nst, tfc);
 }
 
 __device__ __forceinline__ int blk_excl_int(int x, int *tot, int *sw) {
@@ -309,7 +313,7 @@ void agg_tile_seg(const int64_t *tfirst, int64_t nl, int32_t *tseg, hipStream_t 
 //           following tiles it covers.
 template <int PASS>
 __global__ __launch_bounds__(256) void k_agg_lruns(const uint32_t *gkey, const float *gval, RsSeg g, int64_t *hc,
-                                                   double *tin, uint32_t *ukey, float *uval) {
+                                                   double *tin, uint32_t *ukey, float *uval, double *tks) {
   __shared__ double wv[4];
   __shared__ int wf[4];
   __shared__ int sw[16];
@@ -323,6 +327,7 @@ __global__ __launch_bounds__(256) void k_agg_lruns(const uint32_t *gkey, const f
   __syncthreads();
   const int wid = (int)threadIdx.x / kWave;
   int heads = 0;  // heads in earlier rounds
+  double kacc = 0.0;  // this thread's stored run weights (pass 1)
   const int64_t base_rank = PASS == 1 ? hc[t] - hc[ts.f0] : 0;
   for (int64_t b = ts.lo; b < ts.hi; b += blockDim.x) {
     const int64_t p = b + threadIdx.x;
@@ -374,8 +379,10 @@ __global__ __launch_bounds__(256) void k_agg_lruns(const uint32_t *gkey, const f
           }
         }
         const int64_t r = base_rank + seen - 1;
+        const float wf = (float)sum;
         ukey[ts.sb + r] = key;
-        uval[ts.sb + r] = (float)sum;
+        uval[ts.sb + r] = wf;
+        kacc += (double)wf;
       }
     }
     __syncthreads();
@@ -384,19 +391,27 @@ __global__ __launch_bounds__(256) void k_agg_lruns(const uint32_t *gkey, const f
     __syncthreads();
   }
   if (PASS == 0 && threadIdx.x == 0) hc[t] = heads;
+  if (PASS == 1 && tks) {
+    // the tile's part of K', summed in a fixed order
+    kacc = group_sum<kWave>(kacc);
+    if (lane() == 0) wv[wid] = kacc;
+    __syncthreads();
+    if (threadIdx.x == 0) tks[t] = ((wv[0] + wv[1]) + wv[2]) + wv[3];
+  }
 }
 void agg_large_runs(int pass, const uint32_t *gkey, const float *gval, const RsSeg &g, int64_t *hc, double *tin,
-                    uint32_t *ukey, float *uval, hipStream_t s) {
+                    uint32_t *ukey, float *uval, double *tks, hipStream_t s) {
   if (g.ntiles <= 0) return;
   if (pass == 0)
-    hipLaunchKernelGGL(k_agg_lruns<0>, (int)g.ntiles, 256, 0, s, gkey, gval, g, hc, tin, ukey, uval);
+    hipLaunchKernelGGL(k_agg_lruns<0>, (int)g.ntiles, 256, 0, s, gkey, gval, g, hc, tin, ukey, uval, tks);
   else
-    hipLaunchKernelGGL(k_agg_lruns<1>, (int)g.ntiles, 256, 0, s, gkey, gval, g, hc, tin, ukey, uval);
+    hipLaunchKernelGGL(k_agg_lruns<1>, (int)g.ntiles, 256, 0, s, gkey, gval, g, hc, tin, ukey, uval, tks);
 }
 
-// rowlen and K' of the large segments: a wavefront per segment
-__global__ void k_agg_lrows(int64_t nl, const int32_t *lc, const int64_t *lsb, const int64_t *tfirst,
-                            const int64_t *hc, const float *uval, int32_t *rowlen, double *K) {
+// rowlen and K' of the large segments (K' from the tiles' parts): a
+// wavefront per segment
+__global__ void k_agg_lrows(int64_t nl, const int32_t *lc, const int64_t *tfirst, const int64_t *hc,
+                            const double *tks, int32_t *rowlen, double *K) {
   const int64_t l = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   if (l >= nl) return;
   const int c = lc[l];
@@ -404,15 +419,14 @@ __global__ void k_agg_lrows(int64_t nl, const int32_t *lc, const int64_t *lsb, c
   if (lane() == 0) rowlen[c] = (int32_t)U;
   if (!K) return;
   double x = 0.0;
-  for (int64_t j = lane(); j < U; j += kWave) x += (double)uval[lsb[l] + j];
+  for (int64_t t = tfirst[l] + lane(); t < tfirst[l + 1]; t += kWave) x += tks[t];
   x = group_sum<kWave>(x);
   if (lane() == 0) K[c] = x;
 }
-void agg_large_rows(int64_t nl, const int32_t *lc, const int64_t *lsb, const int64_t *tfirst, const int64_t *hc,
-                    const float *uval, int32_t *rowlen, double *K, hipStream_t s) {
+void agg_large_rows(int64_t nl, const int32_t *lc, const int64_t *tfirst, const int64_t *hc, const double *tks,
+                    int32_t *rowlen, double *K, hipStream_t s) {
   if (nl > 0)
-    hipLaunchKernelGGL(k_agg_lrows, (int)ceil_div(nl * kWave, 256), 256, 0, s, nl, lc, lsb, tfirst, hc, uval, rowlen,
-                       K);
+    hipLaunchKernelGGL(k_agg_lrows, (int)ceil_div(nl * kWave, 256), 256, 0, s, nl, lc, tfirst, hc, tks, rowlen, K);
 }
 
 // ---- 6: rows into place ------------------------------------------------------------

@@ -43,6 +43,30 @@ __global__ __launch_bounds__(256) void k_mod_edges(const int64_t *off, const int
   block_merge_flush<2 * kChunk>(tk, tv, S);
 }
 
+// Internal weight only (acc[0] += sum of entries inside a community): used
+// when Sigma and 2m are already known.
+__global__ __launch_bounds__(256) void k_mod_intra(const int64_t *off, const int32_t *idx, const float *w,
+                                                   const int32_t *crow, int64_t nnz, const int32_t *C,
+                                                   double *acc) {
+  __shared__ int rowof[kChunk];
+  __shared__ int sh[16];
+  __shared__ double sd[16];
+  const int64_t q0 = (int64_t)blockIdx.x * kChunk;
+  const int len = (int)min((int64_t)kChunk, nnz - q0);
+  chunk_rows<kChunk>(off, q0, len, crow[blockIdx.x], crow[blockIdx.x + 1], rowof, sh);
+  double sig = 0.0;
+  for (int t = threadIdx.x; t < len; t += blockDim.x) {
+    const int64_t q = q0 + t;
+    if (C[idx[q]] == C[rowof[t]]) sig += (double)w[q];
+  }
+  sig = block_sum(sig, sd);
+  if (threadIdx.x == 0 && sig != 0.0) unsafeAtomicAdd(&acc[0], sig);
+}
+void modularity_intra(const int64_t *off, const int32_t *idx, const float *w, const int32_t *crow, int64_t nnz,
+                      const int32_t *C, double *acc, hipStream_t s) {
+  if (nnz > 0) hipLaunchKernelGGL(k_mod_intra, (int)ceil_div(nnz, kChunk), 256, 0, s, off, idx, w, crow, nnz, C, acc);
+}
+
 void modularity_edges(const int64_t *off, const int32_t *idx, const float *w, const int32_t *crow,
                       int64_t n, int64_t nnz, const int32_t *C, double *acc, double *S, hipStream_t s) {
   (void)n;

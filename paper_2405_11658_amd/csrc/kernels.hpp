@@ -295,9 +295,9 @@ void agg_large_list(const int64_t *seg, int64_t ncomm, int32_t *flag, const int3
                     int64_t *lse, int64_t *ltn, hipStream_t s);
 void agg_tile_seg(const int64_t *tfirst, int64_t nl, int32_t *tseg, hipStream_t s);
 void agg_large_runs(int pass, const uint32_t *gkey, const float *gval, const RsSeg &g, int64_t *hc, double *tin,
-                    uint32_t *ukey, float *uval, hipStream_t s);
-void agg_large_rows(int64_t nl, const int32_t *lc, const int64_t *lsb, const int64_t *tfirst, const int64_t *hc,
-                    const float *uval, int32_t *rowlen, double *K, hipStream_t s);
+                    uint32_t *ukey, float *uval, double *tks, hipStream_t s);
+void agg_large_rows(int64_t nl, const int32_t *lc, const int64_t *tfirst, const int64_t *hc, const double *tks,
+                    int32_t *rowlen, double *K, hipStream_t s);
 void agg_compact(const int64_t *seg, const int32_t *tfc, int64_t nst, const int32_t *lc, const int64_t *lsb,
                  int64_t nl, const int32_t *rowlen, const int64_t *out_off, const uint32_t *ukey, const float *uval,
                  int32_t *out_idx, float *out_w, hipStream_t s);
@@ -307,6 +307,9 @@ void agg_compact(const int64_t *seg, const int32_t *tfc, int64_t nst, const int3
 void modularity_edges(const int64_t *off, const int32_t *idx, const float *w, const int32_t *crow,
                       int64_t n, int64_t nnz, const int32_t *C, double *acc, double *S,
                       hipStream_t s);
+// acc[0] += weight of the entries inside a community (Sigma and 2m known elsewhere)
+void modularity_intra(const int64_t *off, const int32_t *idx, const float *w, const int32_t *crow, int64_t nnz,
+                      const int32_t *C, double *acc, hipStream_t s);
 // acc[1] += sum_c S_c, acc[2] += sum_c (S_c)^2 scaled: computed as sum (S_c/M2)^2 after M2 known
 void modularity_comm(const double *S, int64_t n, double *acc, hipStream_t s);
 void modularity_comm_sq(const double *S, int64_t n, double M2, double *acc, hipStream_t s);
