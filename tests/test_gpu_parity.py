@@ -179,12 +179,11 @@ def test_default_mode_quality_vs_oracle_async():
     """Default mode against the oracle's serial asynchronous run (the paper's
     order) on id-permuted planted-partition graphs (no id locality to favour
     either order): static runs, and DF updates started from the same installed
-    state on both sides.  The mean gap Q_gpu - Q_oracle must be >= -1e-3 and
-    no instance may fall more than 5e-3 below the oracle (modularity is
-    maximised: a result above the oracle's is not a parity failure); every
-    community connected.  (The two orders
-    are different heuristics: relabelling the vertices alone moves the
-    oracle's result by about 2.5e-3 on these graphs.)"""
+    state on both sides.  The mean gap Q_gpu - Q_oracle over the nine results
+    must lie within 1e-3 either way and no single result more than 5e-3 away;
+    every community connected.  (The two orders are different heuristics:
+    relabelling the vertices alone moves the oracle's result by about 2.5e-3
+    on these graphs, so single results are held to the coarser bound.)"""
     gaps = []
     for seed in (1, 2, 3):
         g = gen.planted_partition(4096, 64, 0.1, 0.001, seed=seed, permute=True)
@@ -208,8 +207,8 @@ def test_default_mode_quality_vs_oracle_async():
             assert communities_connected(state.g, to_np(C))
     gaps = np.array(gaps)
     say("Q_gpu - Q_oracle_async:", np.round(gaps, 5).tolist(), "mean", round(float(gaps.mean()), 5))
-    assert gaps.mean() >= -1e-3
-    assert gaps.min() >= -5e-3
+    assert abs(gaps.mean()) <= 1e-3, gaps
+    assert np.abs(gaps).max() <= 5e-3, gaps
 
 
 def test_empty_batch_and_errors():
