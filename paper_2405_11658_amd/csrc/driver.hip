@@ -32,11 +32,11 @@ namespace {
 enum Slot {
   // level arrays (size n of level 0)
   L_C, L_K, L_S, L_S2, L_dC, L_dC2, L_U, L_rng, L_CB, L_Ctop, L_prop, L_from, L_gp, L_gi, L_Sz,
-  L_rep, L_lists, L_region, L_tiles, L_flags, L_map, L_scnt, L_vbs, L_soff, L_sfill,
+  L_rep, L_lists, L_region, L_tiles, L_flags, L_map, L_scnt, L_vbs, L_soff, L_sfill, L_CP,
   // level graphs (ping-pong)
   G0_off, G0_idx, G0_w, G0_crow, G1_off, G1_idx, G1_w, G1_crow,
   // aggregation
-  A_vk, A_vk2, A_vv, A_vv2, A_eoff, A_pos, A_seg, A_hpos, A_gkey, A_gval, A_ukey, A_uval, A_tfc, A_lflag,
+  A_vk, A_vk2, A_vv, A_vv2, A_eoff, A_pos, A_seg, A_hpos, A_gkey, A_gval, A_ukey, A_uval, A_lflag,
   A_lidx, A_lc, A_lsb, A_lse, A_ltn, A_tseg, A_hc, A_tin, A_rowlen,
   // hubs
   H_v, H_cnt, H_ch, H_tab, H_sg, H_chub, H_shub, H_tk, H_tv, H_own, H_pg, H_pc, H_soff,
@@ -566,12 +566,12 @@ Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, i
   x.zero(rowlen, ncomm + 1);
   if (Kout) x.zero(Kout, ncomm);
   const int cb = key_bits((unsigned long long)std::max<int64_t>(ncomm - 1, 0));
-  int64_t nst = 0, nl = 0;
+  int64_t nl = 0;
   int64_t *seg = nullptr;
-  int32_t *tfc = nullptr, *lc = nullptr;
+  int32_t *lc = nullptr;
   int64_t *lsb = nullptr;
-  uint32_t *ukey = nullptr;
-  float *uval = nullptr;
+  uint32_t *ukey = nullptr, *lkey = nullptr;
+  float *uval = nullptr, *lval = nullptr;
   if (g.nnz > 0) {
     const int64_t n = g.n, nnz = g.nnz;
     hipEvent_t t0 = x.kp ? x.kp->begin() : nullptr;
@@ -580,7 +580,10 @@ Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, i
     int32_t *vv = x.get<int32_t>(A_vv, n), *vv2 = x.get<int32_t>(A_vv2, n);
     agg_vkeys(n, C, vk, vv, x.s);
     const RsSeg vseg = rs_plain(n);
-    rsort<uint32_t, int32_t>(vk, vv, vk2, vv2, vseg, cb, x.tmp(rs_tmp_bytes(vseg.ntiles)), x.s);
+    if (rsort<uint32_t, int32_t>(vk, vv, vk2, vv2, vseg, cb, x.tmp(rs_tmp_bytes(vseg.ntiles)), x.s)) {
+      std::swap(vk, vk2);
+      std::swap(vv, vv2);
+    }
     // 2. places of the vertices' entries and the communities' segments
     int64_t *eoff = x.get<int64_t>(A_eoff, n + 1);
     int32_t *pos = x.get<int32_t>(A_pos, n);
@@ -598,10 +601,7 @@ Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, i
     uval = x.get<float>(A_uval, nnz);
     agg_group(a, g.crow, pos, eoff, gkey, gval, x.s);
     // 4. small segments
-    nst = ceil_div(nnz, (int64_t)kAggSmall);
-    tfc = x.get<int32_t>(A_tfc, nst + 1);
-    agg_windows(seg, ncomm, nst, tfc, x.s);
-    agg_small(seg, tfc, nst, cb, gkey, gval, ukey, uval, rowlen, Kout, x.s);
+    agg_small(seg, ncomm, gkey, gval, ukey, uval, rowlen, Kout, x.s);
     // 5. large segments
     int32_t *lflag = x.get<int32_t>(A_lflag, ncomm + 1);
     int32_t *lidx = x.get<int32_t>(A_lidx, ncomm + 1);
@@ -625,14 +625,19 @@ Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, i
       rs.tfirst = ltn;
       rs.sbeg = lsb;
       rs.send = lse;
-      rsort<uint32_t, float>(gkey, gval, ukey, uval, rs, cb, x.tmp(rs_tmp_bytes(ntl)), x.s);
+      // sorted segments in (skey, sval); their rows go to the other pair
+      const int r = rsort<uint32_t, float>(gkey, gval, ukey, uval, rs, cb, x.tmp(rs_tmp_bytes(ntl)), x.s);
+      uint32_t *skey = r ? ukey : gkey;
+      float *sval = r ? uval : gval;
+      lkey = r ? gkey : ukey;
+      lval = r ? gval : uval;
       int64_t *hc = x.get<int64_t>(A_hc, ntl + 1);
       double *tin = x.get<double>(A_tin, 2 * ntl);
       double *tks = tin + ntl;
       x.zero(hc, ntl + 1);
-      agg_large_runs(0, gkey, gval, rs, hc, tin, ukey, uval, nullptr, x.s);
+      agg_large_runs(0, skey, sval, rs, hc, tin, lkey, lval, nullptr, x.s);
       scan_i64(x, hc, hc, ntl + 1);
-      agg_large_runs(1, gkey, gval, rs, hc, tin, ukey, uval, Kout ? tks : nullptr, x.s);
+      agg_large_runs(1, skey, sval, rs, hc, tin, lkey, lval, Kout ? tks : nullptr, x.s);
       agg_large_rows(nl, lc, ltn, hc, tks, rowlen, Kout, x.s);
     }
     if (x.kp) x.kp->end(t0, LEIDEN_PROF_AGG_MERGE, g.nnz, g.n);
@@ -642,7 +647,7 @@ Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, i
   const int64_t nu = g.nnz > 0 ? x.read(&out_off[ncomm]) : 0;
   int32_t *out_idx = x.get<int32_t>(si, nu);
   float *out_w = x.get<float>(sw, nu);
-  if (g.nnz > 0) agg_compact(seg, tfc, nst, lc, lsb, nl, rowlen, out_off, ukey, uval, out_idx, out_w, x.s);
+  if (g.nnz > 0) agg_compact(seg, ncomm, lc, lsb, nl, rowlen, out_off, ukey, uval, lkey, lval, out_idx, out_w, x.s);
   int32_t *out_crow = x.get<int32_t>(sc, ceil_div(std::max<int64_t>(nu, 1), kChunk) + 2);
   chunk_start_rows(out_off, ncomm, nu, out_crow, x.s);
   x.launched("agg_rows");
@@ -848,6 +853,12 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     x.launched("break");
     ra.hp = hh.p;
     ra.act = act;
+    if (async) {
+      // communities and bounds packed for the hub slices and the sweep (the
+      // accept kernel and the sweep keep them with C)
+      ra.CP = x.get<unsigned long long>(L_CP, nl);
+      pack_cb(C, CB, nl, ra.CP, x.s);
+    }
     for (int sl = 0; sl < NS; ++sl) {
       ra.s = sl;
       ra.hbeg = hh.hs[sl]; ra.hend = hh.hs[sl + 1];
@@ -1401,15 +1412,17 @@ leiden_status leiden_update(leiden_handle *h, const leiden_batch *batch, int32_t
 leiden_status leiden_update_bytes(const leiden_handle *h, int64_t n_del, int64_t n_ins, int64_t *bytes) {
   if (!h || !bytes || n_del < 0 || n_ins < 0) return LEIDEN_EINVAL;
   // working set of an update (per vertex: level state, flags, lists, batch
-  // rows, aggregation relabelling; per entry: the graph and its spare copy,
-  // two level graphs, the aggregation keys and sums, hub tables; per directed
-  // batch entry: keys, values and their sorted copies; plus the per-wavefront
-  // tables of the asynchronous sweeps) minus what the handle already holds
+  // rows, the aggregation's community order; per entry: the graph and its
+  // spare copy, two level graphs, the aggregation's grouped entries and
+  // results (16 bytes), room for the hub tables; per directed batch entry:
+  // keys, values and their sorted copies; plus the per-wavefront tables of the
+  // asynchronous sweeps) minus what the handle already holds.  At RMAT scale
+  // 26 (67M vertices, 2.1e9 entries) this is ~148 GB, the measured peak.
   const int64_t n = h->n;
   const int64_t nnz = h->nnz + 2 * n_ins;
   const int64_t E = 2 * (n_del + n_ins);
   const int64_t async_tables = (int64_t)kDefaultAsyncWaves * 2 * kHubDeg * 12;
-  const int64_t need = 203 * n + 104 * nnz + 68 * E + async_tables;
+  const int64_t need = 203 * n + 64 * nnz + 68 * E + async_tables;
   int64_t held = (int64_t)h->w.held();
   for (const DBuf *b : {&h->g_off, &h->g_idx, &h->g_w, &h->g_crow, &h->t_off, &h->t_idx, &h->t_w, &h->C, &h->K,
                         &h->Sig})

@@ -9,14 +9,13 @@
 //   2. a scan of the degrees in that order gives every vertex's place in the
 //      grouped entry array, and every community's segment [seg[c], seg[c+1]);
 //   3. one streaming pass writes (C[v], w) of every entry to its place;
-//   4. segments of at most kAggSmall entries: a workgroup takes the segments
-//      that start in one kAggSmall-entry window (at most 2 * kAggSmall
-//      entries), sorts them in LDS by (segment, neighbour) with a bitonic
-//      network, and sums the runs of equal keys;
+//   4. segments of at most kAggSmall entries: a wavefront per segment sorts
+//      it by neighbour with a bitonic network (in registers up to 64 entries,
+//      else in the wavefront's LDS area) and sums the runs of equal keys;
 //   5. larger segments: a segmented radix sort by neighbour (tiles of 4096
-//      entries that never cross a segment), then the runs are summed with a
-//      segmented scan per tile plus the continuation pieces of the following
-//      tiles, all in a fixed order;
+//      entries that never cross a segment, digits of up to 9 bits), then the
+//      runs are summed with a segmented scan per tile plus the continuation
+//      pieces of the following tiles, all in a fixed order;
 //   6. a scan of the row lengths gives the offsets, and the rows are copied
 //      into place.
 // Weights are summed in FP64 and stored rounded to float32; the next level's
@@ -26,8 +25,6 @@
 #include "kernels.hpp"
 
 namespace lk {
-
-constexpr int kSmallCap = 2 * kAggSmall;  // entries of one small-segment window
 
 // ---- 1-3: community order and grouped entries ---------------------------------
 __global__ void k_agg_vkeys(int64_t n, const int32_t *C, uint32_t *keys, int32_t *vals) {
@@ -95,22 +92,20 @@ void agg_group(const AggArgs &a, const int32_t *crow, const int32_t *pos, const 
 }
 
 // ---- 4: small segments -------------------------------------------------------
-// tfc[t] = first community whose segment starts at or after t * kAggSmall
-// (t in [0, nst]); window t holds the communities [tfc[t], tfc[t + 1]).
-__global__ void k_agg_windows(const int64_t *seg, int64_t ncomm, int64_t nst, int32_t *tfc) {
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t <= nst; t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t at = t * kAggSmall;
-    int64_t lo = 0, hi = ncomm;  // first c in [0, ncomm] with seg[c] >= at (seg[ncomm] = nnz)
-    while (lo < hi) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (seg[mid] >= at) hi = mid;
-      else lo = mid + 1;
-    }
-    tfc[t] = (int32_t)(t == nst ? ncomm : lo);
-  }
-}
-void agg_windows(const int64_t *seg, int64_t ncomm, int64_t nst, int32_t *tfc, hipStream_t s) {
-  hipLaunchKernelGGL(k_agg_windows, flat_grid(nst + 1), 256, 0, s, seg, ncomm, nst, tfc);
+// A wavefront per segment of at most kAggSmall entries (the wavefronts take
+// 64 communities at a time): up to 64 entries are sorted in registers with a
+// bitonic network over the lanes, larger ones in the wavefront's LDS area.
+// The network is data-oblivious and exchanges only strictly ordered pairs,
+// so equal keys end in an order fixed by the input.  Runs of equal keys are
+// summed with a segmented scan (fixed tree), each run written at its rank in
+// the row; K' is the sum of the stored row weights (fixed tree).
+constexpr uint32_t kKeyPad = 0xffffffffu;  // above every community id
+
+// Orders a wavefront's own LDS accesses (one wavefront's LDS operations
+// execute in issue order; this keeps the compiler from reordering them).
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 
 __device__ __forceinline__ int blk_excl_int(int x, int *tot, int *sw) {
@@ -133,135 +128,155 @@ __device__ __forceinline__ int blk_excl_int(int x, int *tot, int *sw) {
   return pre + incl - x;
 }
 
-__global__ __launch_bounds__(256) void k_agg_small(const int64_t *seg, const int32_t *tfc, int cb,
-                                                   const uint32_t *gkey, const float *gval, uint32_t *ukey,
-                                                   float *uval, int32_t *rowlen, double *K) {
-  __shared__ unsigned long long ck[kSmallCap];
-  __shared__ float cv[kSmallCap];
-  __shared__ int lo[kSmallCap + 1];   // window place of each small segment, then the end
-  __shared__ int com[kSmallCap];      // community of each small segment
-  __shared__ int hr[kSmallCap + 1];   // exclusive rank of each run head
-  __shared__ int sw[16];
-  __shared__ int tot_s, tot_m;
-  const int64_t t = blockIdx.x;
-  const int c0 = tfc[t], c1 = tfc[t + 1];
-  if (threadIdx.x == 0) { tot_s = 0; tot_m = 0; }
-  __syncthreads();
-  // the window's small, non-empty segments, in community order
-  for (int b = c0; b < c1; b += blockDim.x) {
-    const int c = b + (int)threadIdx.x;
-    int64_t len = 0;
-    if (c < c1) len = seg[c + 1] - seg[c];
-    const bool small = len > 0 && len <= kAggSmall;
-    int ts, tm;
-    const int is = blk_excl_int(small ? 1 : 0, &ts, sw);
-    const int im = blk_excl_int(small ? (int)len : 0, &tm, sw);
-    const int s0 = tot_s, m0 = tot_m;
-    if (small) {
-      com[s0 + is] = c;
-      lo[s0 + is] = m0 + im;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) { tot_s = s0 + ts; tot_m = m0 + tm; }
-    __syncthreads();
-  }
-  const int ns = tot_s, m = tot_m;
-  if (ns == 0) return;  // uniform
-  if (threadIdx.x == 0) lo[ns] = m;
-  __syncthreads();
-  int P = 2;
-  while (P < m) P <<= 1;
-  const uint32_t kmask = cb >= 32 ? 0xffffffffu : ((1u << cb) - 1u);
-  for (int p = threadIdx.x; p < P; p += blockDim.x) {
-    if (p >= m) {
-      ck[p] = ~0ull;
-      cv[p] = 0.0f;
-      continue;
-    }
-    int l = 0, h = ns;  // lo[l] <= p < lo[h]
-    while (h - l > 1) {
-      const int mid = (l + h) >> 1;
-      if (lo[mid] <= p) l = mid;
-      else h = mid;
-    }
-    const int64_t src = seg[com[l]] + (p - lo[l]);
-    ck[p] = ((unsigned long long)l << cb) | (unsigned long long)(gkey[src] & kmask);
-    cv[p] = gval[src];
-  }
-  __syncthreads();
-  // bitonic sort of the window by (segment, neighbour): a fixed network, so
-  // equal keys end in an order fixed by the input
-  for (int k = 2; k <= P; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < P; i += blockDim.x) {
-        const int ix = i ^ j;
-        if (ix > i) {
-          const unsigned long long a = ck[i], bk = ck[ix];
-          const bool up = (i & k) == 0;
-          if ((a > bk) == up) {
-            ck[i] = bk;
-            ck[ix] = a;
-            const float va = cv[i];
-            cv[i] = cv[ix];
-            cv[ix] = va;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-  // run heads and their ranks
-  int carry = 0;
-  for (int b = 0; b < m; b += blockDim.x) {
-    const int p = b + (int)threadIdx.x;
-    const bool head = p < m && (p == 0 || ck[p] != ck[p - 1]);
-    int tt;
-    const int r = blk_excl_int(head ? 1 : 0, &tt, sw);
-    if (p < m) hr[p] = carry + r;
-    carry += tt;
-  }
-  if (threadIdx.x == 0) hr[m] = carry;
-  __syncthreads();
-  // run sums (sequential within the run) ...
-  double rs[kSmallCap / 256];
-  int rp[kSmallCap / 256];
-  int nr = 0;
-  for (int p = threadIdx.x; p < m; p += blockDim.x) {
-    if (!(p == 0 || ck[p] != ck[p - 1])) continue;
-    double x = 0.0;
-    for (int q = p; q < m && ck[q] == ck[p]; ++q) x += (double)cv[q];
-    rs[nr] = x;
-    rp[nr] = p;
-    ++nr;
-  }
-  __syncthreads();
-  // ... stored at the run's rank in the segment's row, and kept in LDS for K'
-  for (int k = 0; k < nr; ++k) {
-    const int p = rp[k];
-    const int l = (int)(ck[p] >> cb);
-    const int c = com[l];
-    const int j = hr[p] - hr[lo[l]];
-    const float wf = (float)rs[k];
-    ukey[seg[c] + j] = (uint32_t)(ck[p] & kmask);
-    uval[seg[c] + j] = wf;
-    cv[hr[p]] = wf;
-  }
-  __syncthreads();
-  for (int l = threadIdx.x; l < ns; l += blockDim.x) {
-    const int c = com[l];
-    const int r0 = hr[lo[l]], r1 = hr[lo[l + 1]];
-    rowlen[c] = r1 - r0;
-    if (K) {
-      double x = 0.0;
-      for (int r = r0; r < r1; ++r) x += (double)cv[r];
-      K[c] = x;
+__device__ __forceinline__ void seg_scan(double &x, int &f) {
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const double yx = __shfl_up(x, o);
+    const int yf = __shfl_up(f, o);
+    if (lane() >= o) {
+      if (!f) x += yx;
+      f |= yf;
     }
   }
 }
-void agg_small(const int64_t *seg, const int32_t *tfc, int64_t nst, int cb, const uint32_t *gkey, const float *gval,
-               uint32_t *ukey, float *uval, int32_t *rowlen, double *K, hipStream_t s) {
-  if (nst > 0)
-    hipLaunchKernelGGL(k_agg_small, (int)nst, 256, 0, s, seg, tfc, cb, gkey, gval, ukey, uval, rowlen, K);
+
+__device__ __forceinline__ void small_regs(const uint32_t *gkey, const float *gval, int64_t sb, int sl, int c,
+                                           uint32_t *ukey, float *uval, int32_t *rowlen, double *K) {
+  uint32_t key = kKeyPad;
+  float v = 0.0f;
+  if (lane() < sl) {
+    key = gkey[sb + lane()];
+    v = gval[sb + lane()];
+  }
+#pragma unroll
+  for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const uint32_t ok = __shfl_xor(key, j);
+      const float ov = __shfl_xor(v, j);
+      const bool up = (lane() & k) == 0;
+      const bool low = (lane() & j) == 0;
+      // ascending pairs: the lower lane keeps the smaller key
+      const bool take = (low == up) ? ok < key : ok > key;
+      if (take) {
+        key = ok;
+        v = ov;
+      }
+    }
+  }
+  const bool act = lane() < sl;
+  const uint32_t pk = __shfl_up(key, 1), nk = __shfl_down(key, 1);
+  const bool head = act && (lane() == 0 || pk != key);
+  const bool rend = act && (lane() == sl - 1 || nk != key);
+  double x = act ? (double)v : 0.0;
+  int f = head ? 1 : 0;
+  seg_scan(x, f);
+  const unsigned long long hm = __ballot(head);
+  const int rank = __popcll(hm & ((2ull << lane()) - 1ull)) - 1;
+  double kx = 0.0;
+  if (rend) {
+    const float wf = (float)x;
+    ukey[sb + rank] = key;
+    uval[sb + rank] = wf;
+    kx = (double)wf;
+  }
+  kx = group_sum<kWave>(kx);
+  if (lane() == 0) {
+    rowlen[c] = __popcll(hm);
+    if (K) K[c] = kx;
+  }
+}
+
+__device__ __forceinline__ void small_lds(const uint32_t *gkey, const float *gval, int64_t sb, int sl, int c,
+                                          uint32_t *sk, float *sv, uint32_t *ukey, float *uval, int32_t *rowlen,
+                                          double *K) {
+  int P = 2 * kWave;
+  while (P < sl) P <<= 1;
+  wave_lds_fence();  // the previous segment's reads of this area are done
+  for (int p = lane(); p < P; p += kWave) {
+    sk[p] = p < sl ? gkey[sb + p] : kKeyPad;
+    sv[p] = p < sl ? gval[sb + p] : 0.0f;
+  }
+  wave_lds_fence();
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = lane(); i < P; i += kWave) {
+        const int ix = i ^ j;
+        if (ix <= i) continue;
+        const uint32_t a = sk[i], b = sk[ix];
+        const bool up = (i & k) == 0;
+        if (up ? a > b : a < b) {
+          sk[i] = b;
+          sk[ix] = a;
+          const float t = sv[i];
+          sv[i] = sv[ix];
+          sv[ix] = t;
+        }
+      }
+      wave_lds_fence();
+    }
+  }
+  double carry = 0.0, kx = 0.0;
+  int heads = 0;
+  for (int base = 0; base < sl; base += kWave) {
+    const int p = base + lane();
+    const bool act = p < sl;
+    const uint32_t key = act ? sk[p] : kKeyPad;
+    const bool head = act && (p == 0 || sk[p - 1] != key);
+    const bool rend = act && (p == sl - 1 || sk[p + 1] != key);
+    double x = act ? (double)sv[p] : 0.0;
+    int f = head ? 1 : 0;
+    seg_scan(x, f);
+    if (!f) x += carry;  // the run open at the end of the previous chunk
+    const unsigned long long hm = __ballot(head);
+    const int rank = heads + __popcll(hm & ((2ull << lane()) - 1ull)) - 1;
+    if (rend) {
+      const float wf = (float)x;
+      ukey[sb + rank] = key;
+      uval[sb + rank] = wf;
+      kx += (double)wf;
+    }
+    carry = __shfl(x, kWave - 1);
+    heads += __popcll(hm);
+  }
+  kx = group_sum<kWave>(kx);
+  if (lane() == 0) {
+    rowlen[c] = heads;
+    if (K) K[c] = kx;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_agg_small(const int64_t *seg, int64_t ncomm, const uint32_t *gkey,
+                                                   const float *gval, uint32_t *ukey, float *uval, int32_t *rowlen,
+                                                   double *K) {
+  constexpr int W = 256 / kWave;
+  __shared__ uint32_t sk[W][kAggSmall];
+  __shared__ float sv[W][kAggSmall];
+  const int wid = (int)threadIdx.x / kWave;
+  const int64_t stride = (int64_t)gridDim.x * W * kWave;
+  for (int64_t c0 = ((int64_t)blockIdx.x * W + wid) * kWave; c0 < ncomm; c0 += stride) {
+    const int64_t c = c0 + lane();
+    int64_t b = 0, len = 0;
+    if (c < ncomm) {
+      b = seg[c];
+      len = seg[c + 1] - b;
+    }
+    unsigned long long todo = __ballot(len > 0 && len <= kAggSmall);
+    while (todo) {
+      const int k = __ffsll(todo) - 1;
+      todo &= todo - 1ull;
+      const int64_t sb = __shfl(b, k);
+      const int sl = (int)__shfl(len, k);
+      if (sl <= kWave) small_regs(gkey, gval, sb, sl, (int)(c0 + k), ukey, uval, rowlen, K);
+      else small_lds(gkey, gval, sb, sl, (int)(c0 + k), sk[wid], sv[wid], ukey, uval, rowlen, K);
+    }
+  }
+}
+void agg_small(const int64_t *seg, int64_t ncomm, const uint32_t *gkey, const float *gval, uint32_t *ukey,
+               float *uval, int32_t *rowlen, double *K, hipStream_t s) {
+  if (ncomm > 0)
+    hipLaunchKernelGGL(k_agg_small, flat_grid(ceil_div(ncomm, kWave), 4, 8192), 256, 0, s, seg, ncomm, gkey, gval,
+                       ukey, uval, rowlen, K);
 }
 
 // ---- 5: large segments ----------------------------------------------------------
@@ -430,19 +445,30 @@ void agg_large_rows(int64_t nl, const int32_t *lc, const int64_t *tfirst, const 
 }
 
 // ---- 6: rows into place ------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_agg_csmall(const int64_t *seg, const int32_t *tfc, const int32_t *rowlen,
+__global__ __launch_bounds__(256) void k_agg_csmall(const int64_t *seg, int64_t ncomm, const int32_t *rowlen,
                                                     const int64_t *out_off, const uint32_t *ukey, const float *uval,
                                                     int32_t *out_idx, float *out_w) {
-  const int64_t t = blockIdx.x;
-  const int c0 = tfc[t], c1 = tfc[t + 1];
-  for (int c = c0 + (int)threadIdx.x; c < c1; c += blockDim.x) {
-    const int64_t len = seg[c + 1] - seg[c];
-    if (len <= 0 || len > kAggSmall) continue;
-    const int64_t s0 = seg[c], d0 = out_off[c];
-    const int r = rowlen[c];
-    for (int j = 0; j < r; ++j) {
-      out_idx[d0 + j] = (int32_t)ukey[s0 + j];
-      out_w[d0 + j] = uval[s0 + j];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t c0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave * kWave; c0 < ncomm; c0 += stride) {
+    const int64_t c = c0 + lane();
+    int64_t s0 = 0, d0 = 0, len = 0;
+    int r = 0;
+    if (c < ncomm) {
+      s0 = seg[c];
+      len = seg[c + 1] - s0;
+      r = rowlen[c];
+      d0 = out_off[c];
+    }
+    unsigned long long todo = __ballot(len > 0 && len <= kAggSmall && r > 0);
+    while (todo) {
+      const int k = __ffsll(todo) - 1;
+      todo &= todo - 1ull;
+      const int64_t src = __shfl(s0, k), dst = __shfl(d0, k);
+      const int rk = __shfl(r, k);
+      for (int j = lane(); j < rk; j += kWave) {
+        out_idx[dst + j] = (int32_t)ukey[src + j];
+        out_w[dst + j] = uval[src + j];
+      }
     }
   }
 }
@@ -458,13 +484,14 @@ __global__ __launch_bounds__(256) void k_agg_clarge(const int32_t *lc, const int
     out_w[d0 + j] = uval[s0 + j];
   }
 }
-void agg_compact(const int64_t *seg, const int32_t *tfc, int64_t nst, const int32_t *lc, const int64_t *lsb,
-                 int64_t nl, const int32_t *rowlen, const int64_t *out_off, const uint32_t *ukey, const float *uval,
-                 int32_t *out_idx, float *out_w, hipStream_t s) {
-  if (nst > 0)
-    hipLaunchKernelGGL(k_agg_csmall, (int)nst, 256, 0, s, seg, tfc, rowlen, out_off, ukey, uval, out_idx, out_w);
+void agg_compact(const int64_t *seg, int64_t ncomm, const int32_t *lc, const int64_t *lsb, int64_t nl,
+                 const int32_t *rowlen, const int64_t *out_off, const uint32_t *ukey, const float *uval,
+                 const uint32_t *lkey, const float *lval, int32_t *out_idx, float *out_w, hipStream_t s) {
+  if (ncomm > 0)
+    hipLaunchKernelGGL(k_agg_csmall, flat_grid(ncomm, 256, 8192), 256, 0, s, seg, ncomm, rowlen, out_off, ukey, uval,
+                       out_idx, out_w);
   if (nl > 0)
-    hipLaunchKernelGGL(k_agg_clarge, (int)nl, 256, 0, s, lc, lsb, rowlen, out_off, ukey, uval, out_idx, out_w);
+    hipLaunchKernelGGL(k_agg_clarge, (int)nl, 256, 0, s, lc, lsb, rowlen, out_off, lkey, lval, out_idx, out_w);
 }
 
 }  // namespace lk

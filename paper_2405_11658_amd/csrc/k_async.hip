@@ -205,12 +205,26 @@ __device__ __forceinline__ void batch_comms(EdgeBatch &eb, const int32_t *C, con
     if (bj[u] != cb) eb.c[u] = kEmpty;
 }
 
+// Refinement: communities and bounds of the batch's neighbours from the
+// packed words (bound << 32 | community), one 8-byte load per neighbour.
+__device__ __forceinline__ void batch_comms_packed(EdgeBatch &eb, const unsigned long long *CP, int cb, int i) {
+  unsigned long long pk[kUnroll];
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u)
+    pk[u] = eb.j[u] != i ? __hip_atomic_load(&CP[eb.j[u]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                         : ~0ull;
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u)
+    eb.c[u] = (eb.j[u] != i && (int)(pk[u] >> 32) == cb) ? (int)(uint32_t)pk[u] : kEmpty;
+}
+
 // Adds the edges [e0, e1) of vertex i to table t, keyed by the neighbour's
 // current community: the first kUnroll * kWave from the loaded batch, the
 // rest loaded here.  Returns (in all lanes) the weight to community d.
 __device__ __forceinline__ double table_edges(const WaveTable &t, const EdgeBatch &eb, const int32_t *idx,
                                               const float *w, const int32_t *C, const int32_t *CB, int cb,
-                                              int i, int d, int64_t e0, int64_t e1) {
+                                              int i, int d, int64_t e0, int64_t e1,
+                                              const unsigned long long *CP = nullptr) {
   double own = 0.0;
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) {
@@ -221,7 +235,8 @@ __device__ __forceinline__ double table_edges(const WaveTable &t, const EdgeBatc
   for (int64_t base = e0 + kUnroll * kWave; base < e1; base += kUnroll * kWave) {
     EdgeBatch r;
     batch_ids(r, idx, w, i, base, e1);
-    batch_comms(r, C, CB, cb, i);
+    if (CP) batch_comms_packed(r, CP, cb, i);
+    else batch_comms(r, C, CB, cb, i);
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       if (r.c[u] == kEmpty) continue;
@@ -292,12 +307,28 @@ __device__ __forceinline__ void best_move(const WaveTable &t, double M2, int d, 
   group_argmax<kWave>(bg, bc);
 }
 
-// First position of the next chunk of kAsyncChunk list positions for the
-// calling wavefront (uniform value); chunks are taken in ascending order.
-__device__ __forceinline__ int64_t grab(unsigned long long *next) {
-  unsigned long long base = 0;
-  if (lane() == 0) base = atomicAdd(next, (unsigned long long)kAsyncChunk);
-  return (int64_t)__shfl(base, 0);
+// A wavefront takes kGrabChunks chunks of kAsyncChunk list positions at a
+// time from the global counter (one atomic per 256 vertices: every wavefront
+// of the sweep takes its work from this one address, so its atomics must stay
+// rare) and handles them in order.  Returns the first position of the
+// calling wavefront's next chunk (uniform value); chunks are taken in
+// ascending order.
+constexpr int kGrabChunks = 4;
+struct Grab {
+  int64_t base = 0;
+  int left = 0;
+};
+__device__ __forceinline__ int64_t grab(unsigned long long *next, Grab &g) {
+  if (g.left == 0) {
+    unsigned long long b = 0;
+    if (lane() == 0) b = atomicAdd(next, (unsigned long long)kAsyncChunk * kGrabChunks);
+    g.base = (int64_t)__shfl(b, 0);
+    g.left = kGrabChunks;
+  }
+  const int64_t r = g.base;
+  g.base += kAsyncChunk;
+  --g.left;
+  return r;
 }
 
 template <int WPB, int LDSCAP>
@@ -311,8 +342,9 @@ __global__ __launch_bounds__(256) void k_move_async(MoveArgs a) {
   double gsum = 0.0;
   long long mv = 0;
   unsigned long long nv = 0, ne = 0;  // vertices evaluated, edges scanned
+  Grab gr;
   for (;;) {
-    const int64_t base = grab(a.anext);
+    const int64_t base = grab(a.anext, gr);
     if (base >= a.alen) break;
     // each lane fetches the state of one vertex of the chunk; the chunk's
     // unprocessed vertices are then handled one after another by the whole
@@ -418,8 +450,9 @@ __global__ __launch_bounds__(256) void k_refine_async(RefineArgs a) {
   const int64_t gw = (int64_t)blockIdx.x * WPB + wv;
   int *gk = a.akeys + gw * kHubDeg * 2;
   double *gv = a.avals + gw * kHubDeg * 2;
+  Grab gr;
   for (;;) {
-    const int64_t base = grab(a.anext);
+    const int64_t base = grab(a.anext, gr);
     if (base >= a.alen) break;
     // each lane fetches one vertex of the chunk: isolated vertices of a
     // changed bound are candidates (their isolation is confirmed again by the
@@ -456,9 +489,9 @@ __global__ __launch_bounds__(256) void k_refine_async(RefineArgs a) {
       for (int attempt = 0; attempt < kRefineTries; ++attempt) {
         EdgeBatch eb;
         batch_ids(eb, a.idx, a.w, i, e0, e1);
-        batch_comms(eb, a.C, a.CB, cb, i);
+        batch_comms_packed(eb, a.CP, cb, i);
         WaveTable t = wave_table(lds[wv], gk, gv, e1 - e0);
-        const double b = table_edges(t, eb, a.idx, a.w, a.C, a.CB, cb, i, c, e0, e1);
+        const double b = table_edges(t, eb, a.idx, a.w, a.C, a.CB, cb, i, c, e0, e1, a.CP);
         tab_sync(t);
         double bg;
         int bc;
@@ -476,6 +509,8 @@ __global__ __launch_bounds__(256) void k_refine_async(RefineArgs a) {
             if (atomicCAS(sc, want, 0ull) == want) {
               if (join_nonempty(&a.Sig[bc], Ki)) {
                 st_int(&a.C[i], bc);
+                __hip_atomic_store(&a.CP[i], ((unsigned long long)(uint32_t)cb << 32) | (uint32_t)bc,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
               } else {
                 unsafeAtomicAdd(&a.Sig[c], Ki);  // the target emptied meanwhile: stay, look again
                 again = 1;
@@ -487,6 +522,14 @@ __global__ __launch_bounds__(256) void k_refine_async(RefineArgs a) {
       }
     }
   }
+}
+
+__global__ void k_pack_cb(const int32_t *C, const int32_t *CB, int64_t n, unsigned long long *CP) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    CP[i] = ((unsigned long long)(uint32_t)CB[i] << 32) | (uint32_t)C[i];
+}
+void pack_cb(const int32_t *C, const int32_t *CB, int64_t n, unsigned long long *CP, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_pack_cb, flat_grid(n), 256, 0, s, C, CB, n, CP);
 }
 
 void refine_async(const RefineArgs &a, int waves, bool wide, hipStream_t s) {

@@ -7,14 +7,13 @@
 // routine, recursively), then each tile scans its items in 16 rounds of 256
 // with the tile's prefix as carry.  In-place use (in == out) is allowed.
 //
-// Radix sort: per pass (digits of at most 8 bits) a digit histogram per tile,
+// Radix sort: per pass (digits of at most 9 bits) a digit histogram per tile,
 // an exclusive scan of the histograms laid out segment-major, digit-major,
 // tile-minor (so the scanned value of (segment, digit, tile) is where the
 // tile's items of that digit go), and a stable scatter that ranks the items of
 // each 256-item round with wavefront ballots (lanes with the same digit) plus
 // per-wavefront counts into a digit-sorted copy of the tile in LDS, written
-// out in order (coalesced runs per digit).  Tiles never cross a segment; the number of passes is
-// even, so the result ends in the buffers it started in.
+// out in order (coalesced runs per digit).  Tiles never cross a segment.
 #include <algorithm>
 
 #include "device.hpp"
@@ -120,20 +119,26 @@ size_t scan_excl_i32_to_i64(void *temp, size_t tbytes, const int32_t *in, int64_
 }
 
 // ---- radix sort ------------------------------------------------------------------
+constexpr int kRadixBits = 9;            // digits of at most 9 bits
+constexpr int kDig = 1 << kRadixBits;    // 512 digit values
+constexpr int kDPT = kDig / kPT;         // digits per thread
+
 // hist: scan layout (segment, digit, tile); tcnt: the tile's own digit counts.
 template <class K>
 __global__ __launch_bounds__(kPT) void k_rs_hist(const K *keys, RsSeg g, int shift, int bits, int64_t *hist,
                                                  int32_t *tcnt) {
-  __shared__ int h[256];
+  __shared__ int h[kDig];
   const int64_t t = blockIdx.x;
   const TileSpan ts = tile_span(g, t);
-  h[threadIdx.x] = 0;
+  for (int d = threadIdx.x; d < kDig; d += kPT) h[d] = 0;
   __syncthreads();
   const K mask = (K)((1u << bits) - 1u);
   for (int64_t p = ts.lo + threadIdx.x; p < ts.hi; p += kPT) atomicAdd(&h[(int)((keys[p] >> shift) & mask)], 1);
   __syncthreads();
-  hist[256 * ts.f0 + (int64_t)threadIdx.x * ts.nt + (t - ts.f0)] = h[threadIdx.x];
-  tcnt[t * 256 + threadIdx.x] = h[threadIdx.x];
+  for (int d = threadIdx.x; d < kDig; d += kPT) {
+    hist[kDig * ts.f0 + (int64_t)d * ts.nt + (t - ts.f0)] = h[d];
+    tcnt[t * kDig + d] = h[d];
+  }
 }
 
 // Each tile ranks its items stably by digit into a local digit-sorted copy in
@@ -145,22 +150,35 @@ __global__ __launch_bounds__(kPT) void k_rs_scatter(const K *ki, const V *vi, K 
   constexpr int W = kPT / kWave;
   __shared__ K sk[kPTile];
   __shared__ V sv[kPTile];
-  __shared__ int64_t gbase[256];
-  __shared__ int loff[256];
-  __shared__ int run[256];
-  __shared__ int wcnt[W][256];
+  __shared__ int64_t gbase[kDig];
+  __shared__ int loff[kDig];
+  __shared__ int run[kDig];
+  __shared__ int wcnt[W][kDig];
   __shared__ int sw[W];
   const int64_t t = blockIdx.x;
   const TileSpan ts = tile_span(g, t);
-  const int64_t seg0 = hs[256 * ts.f0];
-  const int d0 = (int)threadIdx.x;
-  const int cnt = tcnt[t * 256 + d0];
-  int tot;
-  loff[d0] = blk_excl<int>(cnt, &tot, sw);
-  gbase[d0] = ts.sb + (hs[256 * ts.f0 + (int64_t)d0 * ts.nt + (t - ts.f0)] - seg0) - loff[d0];
-  run[d0] = 0;
+  const int64_t seg0 = hs[kDig * ts.f0];
+  {
+    // tile-local digit offsets: each thread owns kDPT consecutive digits
+    int c[kDPT], sum = 0;
 #pragma unroll
-  for (int w = 0; w < W; ++w) wcnt[w][d0] = 0;
+    for (int k = 0; k < kDPT; ++k) {
+      c[k] = tcnt[t * kDig + threadIdx.x * kDPT + k];
+      sum += c[k];
+    }
+    int tot;
+    int pre = blk_excl<int>(sum, &tot, sw);
+#pragma unroll
+    for (int k = 0; k < kDPT; ++k) {
+      const int d = threadIdx.x * kDPT + k;
+      loff[d] = pre;
+      gbase[d] = ts.sb + (hs[kDig * ts.f0 + (int64_t)d * ts.nt + (t - ts.f0)] - seg0) - pre;
+      run[d] = 0;
+      pre += c[k];
+#pragma unroll
+      for (int w = 0; w < W; ++w) wcnt[w][d] = 0;
+    }
+  }
   __syncthreads();
   const K mask = (K)((1u << bits) - 1u);
   const int wid = (int)threadIdx.x / kWave;
@@ -192,14 +210,14 @@ __global__ __launch_bounds__(kPT) void k_rs_scatter(const K *ki, const V *vi, K 
       sv[q] = val;
     }
     __syncthreads();
-    {
+    for (int d = threadIdx.x; d < kDig; d += kPT) {
       int sum = 0;
 #pragma unroll
       for (int w = 0; w < W; ++w) {
-        sum += wcnt[w][d0];
-        wcnt[w][d0] = 0;
+        sum += wcnt[w][d];
+        wcnt[w][d] = 0;
       }
-      run[d0] += sum;
+      run[d] += sum;
     }
     __syncthreads();
   }
@@ -213,23 +231,19 @@ __global__ __launch_bounds__(kPT) void k_rs_scatter(const K *ki, const V *vi, K 
   }
 }
 
-int rs_passes(int bits) {
-  if (bits <= 0) return 0;
-  int np = (bits + 7) / 8;
-  return np + (np & 1);
-}
+int rs_passes(int bits) { return bits <= 0 ? 0 : (bits + kRadixBits - 1) / kRadixBits; }
 
 size_t rs_tmp_bytes(int64_t ntiles) {
-  const int64_t nh = 256 * std::max<int64_t>(ntiles, 1);
+  const int64_t nh = (int64_t)kDig * std::max<int64_t>(ntiles, 1);
   return (size_t)nh * (sizeof(int64_t) + sizeof(int32_t)) + scan_bytes(nh, sizeof(int64_t));
 }
 
 template <class K, class V>
-void rsort(K *k0, V *v0, K *k1, V *v1, const RsSeg &g, int bits, void *tmp, hipStream_t s) {
+int rsort(K *k0, V *v0, K *k1, V *v1, const RsSeg &g, int bits, void *tmp, hipStream_t s) {
   const int np = rs_passes(bits);
-  if (np == 0 || g.ntiles <= 0) return;
+  if (np == 0 || g.ntiles <= 0) return 0;
   const int wd = (bits + np - 1) / np;
-  const int64_t nh = 256 * g.ntiles;
+  const int64_t nh = (int64_t)kDig * g.ntiles;
   int64_t *hist = (int64_t *)tmp;
   int32_t *tcnt = (int32_t *)(hist + nh);
   int64_t *stmp = (int64_t *)(tcnt + nh);
@@ -237,7 +251,7 @@ void rsort(K *k0, V *v0, K *k1, V *v1, const RsSeg &g, int bits, void *tmp, hipS
   V *vs = v0, *vd = v1;
   int shift = 0;
   for (int p = 0; p < np; ++p) {
-    const int b = std::max(0, std::min(wd, bits - shift));
+    const int b = std::min(wd, bits - shift);
     hipLaunchKernelGGL((k_rs_hist<K>), (int)g.ntiles, kPT, 0, s, (const K *)ks, g, shift, b, hist, tcnt);
     scan_rec<int64_t, int64_t>(hist, hist, nh, stmp, s);
     hipLaunchKernelGGL((k_rs_scatter<K, V>), (int)g.ntiles, kPT, 0, s, (const K *)ks, (const V *)vs, kd, vd, g,
@@ -246,12 +260,13 @@ void rsort(K *k0, V *v0, K *k1, V *v1, const RsSeg &g, int bits, void *tmp, hipS
     std::swap(vs, vd);
     shift += b;
   }
+  return np & 1;
 }
 
-template void rsort<uint32_t, int32_t>(uint32_t *, int32_t *, uint32_t *, int32_t *, const RsSeg &, int, void *,
-                                       hipStream_t);
-template void rsort<uint32_t, float>(uint32_t *, float *, uint32_t *, float *, const RsSeg &, int, void *,
-                                     hipStream_t);
+template int rsort<uint32_t, int32_t>(uint32_t *, int32_t *, uint32_t *, int32_t *, const RsSeg &, int, void *,
+                                      hipStream_t);
+template int rsort<uint32_t, float>(uint32_t *, float *, uint32_t *, float *, const RsSeg &, int, void *,
+                                    hipStream_t);
 
 RsSeg rs_plain(int64_t n) {
   RsSeg g;
@@ -281,17 +296,22 @@ static size_t sort_copy(void *temp, size_t tbytes, const K *kin, K *kout, const 
   const size_t vb = ((size_t)std::max<int64_t>(n, 1) * sizeof(V) + 255) & ~(size_t)255;
   const size_t need = kb + vb + rs_tmp_bytes(g.ntiles);
   if (!temp || tbytes < need || n <= 0) return need;
-  (void)hipMemcpyAsync(kout, kin, sizeof(K) * n, hipMemcpyDeviceToDevice, s);
-  (void)hipMemcpyAsync(vout, vin, sizeof(V) * n, hipMemcpyDeviceToDevice, s);
   char *t = (char *)temp;
-  rsort<K, V>(kout, vout, (K *)t, (V *)(t + kb), g, bits, t + kb + vb, s);
+  K *tk = (K *)t;
+  V *tv = (V *)(t + kb);
+  // an odd number of passes ends in the second buffers: start there
+  const bool odd = rs_passes(bits) & 1;
+  (void)hipMemcpyAsync(odd ? tk : kout, kin, sizeof(K) * n, hipMemcpyDeviceToDevice, s);
+  (void)hipMemcpyAsync(odd ? tv : vout, vin, sizeof(V) * n, hipMemcpyDeviceToDevice, s);
+  if (odd) rsort<K, V>(tk, tv, kout, vout, g, bits, t + kb + vb, s);
+  else rsort<K, V>(kout, vout, tk, tv, g, bits, t + kb + vb, s);
   return need;
 }
-template void rsort<unsigned long long, int32_t>(unsigned long long *, int32_t *, unsigned long long *, int32_t *,
+template int rsort<unsigned long long, int32_t>(unsigned long long *, int32_t *, unsigned long long *, int32_t *,
                                                  const RsSeg &, int, void *, hipStream_t);
-template void rsort<unsigned long long, double>(unsigned long long *, double *, unsigned long long *, double *,
+template int rsort<unsigned long long, double>(unsigned long long *, double *, unsigned long long *, double *,
                                                 const RsSeg &, int, void *, hipStream_t);
-template void rsort<unsigned long long, float>(unsigned long long *, float *, unsigned long long *, float *,
+template int rsort<unsigned long long, float>(unsigned long long *, float *, unsigned long long *, float *,
                                                const RsSeg &, int, void *, hipStream_t);
 
 size_t sort_pairs_u64_i32(void *temp, size_t tbytes, const unsigned long long *kin, unsigned long long *kout,
@@ -324,10 +344,12 @@ size_t seg_sort_i32_f32(void *temp, size_t tbytes, const int32_t *kin, int32_t *
   unsigned long long *k0 = (unsigned long long *)t, *k1 = (unsigned long long *)(t + kb);
   float *v1 = (float *)(t + 2 * kb);
   hipLaunchKernelGGL(k_row_keys, flat_grid(nseg), 256, 0, s, off, nseg, kin, k0);
-  (void)hipMemcpyAsync(vout, vin, sizeof(float) * nnz, hipMemcpyDeviceToDevice, s);
-  rsort<unsigned long long, float>(k0, vout, k1, v1, g, 32 + key_bits((unsigned long long)std::max<int64_t>(nseg - 1, 0)),
-                                   t + 2 * kb + vb, s);
-  hipLaunchKernelGGL(k_low_words, flat_grid(nnz), 256, 0, s, k0, nnz, kout);
+  const int bits = 32 + key_bits((unsigned long long)std::max<int64_t>(nseg - 1, 0));
+  const bool odd = rs_passes(bits) & 1;  // values end in vout either way
+  (void)hipMemcpyAsync(odd ? v1 : vout, vin, sizeof(float) * nnz, hipMemcpyDeviceToDevice, s);
+  const int r = odd ? rsort<unsigned long long, float>(k0, v1, k1, vout, g, bits, t + 2 * kb + vb, s)
+                    : rsort<unsigned long long, float>(k0, vout, k1, v1, g, bits, t + 2 * kb + vb, s);
+  hipLaunchKernelGGL(k_low_words, flat_grid(nnz), 256, 0, s, r ? k1 : k0, nnz, kout);
   return need;
 }
 

@@ -266,12 +266,24 @@ __global__ __launch_bounds__(256) void k_rhub_gather(RefineArgs a) {
     x[u] = 0.0f;
     if (e < e1) { j[u] = a.idx[e]; x[u] = a.w[e]; }
   }
+  if (a.CP) {
+    // packed (bound << 32 | community): one load per neighbour
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    c[u] = kEmpty;
-    if (j[u] != i) {
-      const int cj = a.C[j[u]];
-      if (a.CB[j[u]] == cbi) c[u] = cj;
+    for (int u = 0; u < PER; ++u) {
+      c[u] = kEmpty;
+      if (j[u] != i) {
+        const unsigned long long pk = a.CP[j[u]];
+        if ((int)(pk >> 32) == cbi) c[u] = (int)(uint32_t)pk;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      c[u] = kEmpty;
+      if (j[u] != i) {
+        const int cj = a.C[j[u]];
+        if (a.CB[j[u]] == cbi) c[u] = cj;
+      }
     }
   }
   __syncthreads();
@@ -382,6 +394,7 @@ __global__ void k_raccept(RefineArgs a, int64_t beg, int64_t end) {
     const bool ok = pp < 0 || (pp == i && better(a.gp[i], i, a.gp[p], p));
     if (!ok) continue;
     a.C[i] = p;
+    if (a.CP) a.CP[i] = ((unsigned long long)(uint32_t)a.CB[i] << 32) | (uint32_t)p;
     const double k = a.K[i];
     unsafeAtomicAdd(&a.Sig[i], -k);
     unsafeAtomicAdd(&a.Sig[p], k);

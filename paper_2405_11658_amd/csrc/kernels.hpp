@@ -115,11 +115,12 @@ RsSeg rs_plain(int64_t n);
 int rs_passes(int bits);
 size_t rs_tmp_bytes(int64_t ntiles);
 int key_bits(unsigned long long x);  // bits needed for x (0 for 0)
-// Stable sort of every segment by the low `bits` key bits; (k1, v1) are
-// scratch buffers covering the same items; the result is in (k0, v0).  tmp:
+// Stable sort of every segment by the low `bits` key bits (rs_passes(bits)
+// passes); (k1, v1) are second buffers covering the same items.  Returns 0 if
+// the result is in (k0, v0), 1 if in (k1, v1) (odd pass count).  tmp:
 // rs_tmp_bytes(g.ntiles) bytes.
 template <class K, class V>
-void rsort(K *k0, V *v0, K *k1, V *v1, const RsSeg &g, int bits, void *tmp, hipStream_t s);
+int rsort(K *k0, V *v0, K *k1, V *v1, const RsSeg &g, int bits, void *tmp, hipStream_t s);
 
 // ---- k_move.hip -------------------------------------------------------------
 // Hub plan of a level: the vertices of the largest degree bucket grouped by
@@ -231,6 +232,7 @@ struct RefineArgs {
   const float *w;
   int32_t *C;
   int32_t *CB;
+  unsigned long long *CP;   // asynchronous sweep: CB << 32 | C per vertex, kept with C
   const double *K;
   double *Sig;
   const uint8_t *dC;
@@ -271,6 +273,7 @@ void move_async(const MoveArgs &a, int waves, bool wide, hipStream_t s);
 void edge_flags(const int64_t *off, int64_t n, int32_t *flags, hipStream_t s);
 void edge_list(const int64_t *off, int64_t n, const int32_t *pos, int32_t *list, hipStream_t s);
 void refine_async(const RefineArgs &a, int waves, bool wide, hipStream_t s);
+void pack_cb(const int32_t *C, const int32_t *CB, int64_t n, unsigned long long *CP, hipStream_t s);
 // hub frontier of slice a.s (a.hbeg..a.hend of the hub plan) for the hub-only sliced phase
 
 // ---- k_aggregate.hip -----------------------------------------------------------
@@ -287,9 +290,8 @@ void agg_vdeg(int64_t n, const int64_t *off, const int32_t *vs, int64_t *deg, in
 void agg_cdeg(int64_t n, const uint32_t *Cs, const int64_t *eoff, int64_t *hpos, int64_t *cdeg, hipStream_t s);
 void agg_group(const AggArgs &a, const int32_t *crow, const int32_t *pos, const int64_t *eoff, uint32_t *gkey,
                float *gval, hipStream_t s);
-void agg_windows(const int64_t *seg, int64_t ncomm, int64_t nst, int32_t *tfc, hipStream_t s);
-void agg_small(const int64_t *seg, const int32_t *tfc, int64_t nst, int cb, const uint32_t *gkey, const float *gval,
-               uint32_t *ukey, float *uval, int32_t *rowlen, double *K, hipStream_t s);
+void agg_small(const int64_t *seg, int64_t ncomm, const uint32_t *gkey, const float *gval, uint32_t *ukey,
+               float *uval, int32_t *rowlen, double *K, hipStream_t s);
 void agg_large_flags(const int64_t *seg, int64_t ncomm, int32_t *flag, hipStream_t s);
 void agg_large_list(const int64_t *seg, int64_t ncomm, int32_t *flag, const int32_t *lidx, int32_t *lc, int64_t *lsb,
                     int64_t *lse, int64_t *ltn, hipStream_t s);
@@ -298,9 +300,10 @@ void agg_large_runs(int pass, const uint32_t *gkey, const float *gval, const RsS
                     uint32_t *ukey, float *uval, double *tks, hipStream_t s);
 void agg_large_rows(int64_t nl, const int32_t *lc, const int64_t *tfirst, const int64_t *hc, const double *tks,
                     int32_t *rowlen, double *K, hipStream_t s);
-void agg_compact(const int64_t *seg, const int32_t *tfc, int64_t nst, const int32_t *lc, const int64_t *lsb,
-                 int64_t nl, const int32_t *rowlen, const int64_t *out_off, const uint32_t *ukey, const float *uval,
-                 int32_t *out_idx, float *out_w, hipStream_t s);
+// rows of the small segments from (ukey, uval), of the large ones from (lkey, lval)
+void agg_compact(const int64_t *seg, int64_t ncomm, const int32_t *lc, const int64_t *lsb, int64_t nl,
+                 const int32_t *rowlen, const int64_t *out_off, const uint32_t *ukey, const float *uval,
+                 const uint32_t *lkey, const float *lval, int32_t *out_idx, float *out_w, hipStream_t s);
 
 // ---- k_modularity.hip --------------------------------------------------------
 // acc[0] += sigma total, S[c] += K-contributions (S zeroed, ncomm = n)
