@@ -36,8 +36,8 @@ events around each launch, on the call's stream) with the largest share of the
 timed steps (the aggregation, timed as one region of several kernels, is
 reported beside it); achieved = algorithmic bytes per launch / average launch
 time.  Algorithmic bytes per unit: hub gather 12 B per scanned entry (id,
-weight, community of the neighbour); modularity scan 12 B per entry plus 4 B
-per vertex; graph update merge 16 B per entry plus 16 B per vertex;
+weight, community of the neighbour); modularity scan 12 B per entry (id,
+weight, community of the neighbour; the row's community is reused); graph update merge 16 B per entry plus 16 B per vertex;
 asynchronous local-moving sweep 12 B per scanned edge plus 34 B per evaluated
 vertex (Sigma reads and neighbour marks not counted: a lower bound).  traffic = HBM bytes per launch
 from the committed counter runs (profiles/traffic.json) when they were taken
@@ -61,14 +61,14 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_UNIT = {  # (per entry, per vertex)
     "hub_gather": (12.0, 0.0),
     "agg_merge": (12.0, 12.0),
-    "mod_scan": (12.0, 4.0),
+    "mod_scan": (12.0, 0.0),
     "batch_merge": (16.0, 16.0),
     "move_sweep": (12.0, 34.0),
 }
 PROF_KERNEL_NAMES = {  # symbol of each timed kernel, as rocprofv3 lists it
     "hub_gather": "lk::k_hub_gather(lk::MoveArgs)",
     "agg_merge": "aggregation region (k_agg_*, k_rs_*, k_scan_*)",
-    "mod_scan": "lk::k_mod_edges",
+    "mod_scan": "lk::k_mod_intra",
     "batch_merge": "lk::k_batch_apply_old(lk::BatchArgs)",
     "move_sweep": "lk::k_move_async",  # both launch shapes, <4, 512> and <2, 2048>
 }
@@ -121,7 +121,7 @@ def _update_window(rows):
     if not merges:
         return None
     last = merges[-1][1]
-    ends = [r[2] for r in rows if r[0].startswith("lk::k_mod_edges") and r[1] > last]
+    ends = [r[2] for r in rows if r[0].startswith(("lk::k_mod_intra", "lk::k_mod_edges")) and r[1] > last]
     return merges[0][1], (ends[0] if ends else rows[-1][2]), len(merges)
 
 
@@ -156,6 +156,49 @@ def _pmc(db: str, counter: str):
     q = ("select k.name, k.start, p.counter_value from pmc_events p join kernels k on k.dispatch_id = p.dispatch_id "
          "where p.counter_name = ? order by k.start")
     return con.execute(q, (counter,)).fetchall()
+
+
+def summarize_counters(db: str, command: str, kernels=("lk::k_move_async", "void lk::k_move_async",
+                                                       "void lk::k_refine_async", "lk::k_agg_small",
+                                                       "void lk::k_rs_scatter", "lk::k_agg_group")) -> str:
+    """Per-kernel sums of every counter of a counter run over the dynamic
+    updates, with the derived ratios used in the design notes."""
+    import sqlite3
+    con = sqlite3.connect(db)
+    win = _update_window(_trace_rows(db))
+    q = ("select k.name, p.counter_name, sum(p.counter_value), count(*) from pmc_events p join kernels k "
+         "on k.dispatch_id = p.dispatch_id where k.start >= ? and k.start < ? group by k.name, p.counter_name")
+    agg = {}
+    for name, cn, v, c in con.execute(q, (win[0], win[1])).fetchall():
+        for pre in kernels:
+            if name.startswith(pre):
+                agg.setdefault(pre, {})[cn] = (v, c)
+    out = ["Command:", "", "    " + command, "", f"Dynamic updates: {win[2]}; counter sums per update.", ""]
+    for k, cs in agg.items():
+        out.append(f"### `{k}`")
+        out.append("")
+        out.append("| counter | per update |")
+        out.append("|---|---|")
+        for cn in sorted(cs):
+            out.append(f"| {cn} | {cs[cn][0] / win[2]:.4g} |")
+        g = {cn: cs[cn][0] for cn in cs}
+        if "SQ_LDS_BANK_CONFLICT" in g and g.get("SQ_LDS_IDX_ACTIVE"):
+            out.append(f"| LDS bank-conflict cycles / LDS active cycles | "
+                       f"{g['SQ_LDS_BANK_CONFLICT'] / g['SQ_LDS_IDX_ACTIVE']:.3f} |")
+        if g.get("SQ_WAVE_CYCLES") and "SQ_WAIT_INST_ANY" in g:
+            out.append(f"| wave cycles waiting for an instruction to issue (SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES) | "
+                       f"{g['SQ_WAIT_INST_ANY'] / g['SQ_WAVE_CYCLES']:.3f} |")
+        if g.get("SQ_WAVE_CYCLES") and "SQ_WAIT_ANY" in g:
+            out.append(f"| wave cycles waiting (SQ_WAIT_ANY / SQ_WAVE_CYCLES) | "
+                       f"{g['SQ_WAIT_ANY'] / g['SQ_WAVE_CYCLES']:.3f} |")
+        if g.get("SQ_WAVE_CYCLES") and "SQ_ACTIVE_INST_ANY" in g:
+            out.append(f"| wave cycles issuing (SQ_ACTIVE_INST_ANY / SQ_WAVE_CYCLES) | "
+                       f"{g['SQ_ACTIVE_INST_ANY'] / g['SQ_WAVE_CYCLES']:.3f} |")
+        if g.get("TCP_TCC_READ_REQ_sum"):
+            out.append(f"| mean L2 read latency (cycles) | "
+                       f"{g.get('TCP_TCC_READ_REQ_LATENCY_sum', 0) / g['TCP_TCC_READ_REQ_sum']:.0f} |")
+        out.append("")
+    return "\n".join(out)
 
 
 def traffic_from_pmc(fetch_db: str, write_db: str, kernel: str, key: str) -> dict:
@@ -249,6 +292,7 @@ def main() -> int:
                     help="end with a kernel that reads and writes 1 GiB (reference for counter runs)")
     ap.add_argument("--summarize-trace", metavar="DB", help="print a markdown summary of a rocprofv3 kernel trace")
     ap.add_argument("--command", default="", help="the command that made the trace (for --summarize-trace)")
+    ap.add_argument("--summarize-counters", metavar="DB", help="print per-kernel counter sums of a counter run")
     ap.add_argument("--traffic", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="print the HBM traffic entry of --kernel from two counter runs")
     ap.add_argument("--kernel", default="void lk::k_move_async")
@@ -256,6 +300,9 @@ def main() -> int:
     args = ap.parse_args()
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace, args.command))
+        return 0
+    if args.summarize_counters:
+        print(summarize_counters(args.summarize_counters, args.command))
         return 0
     if args.traffic:
         import glob

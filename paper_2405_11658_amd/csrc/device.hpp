@@ -248,10 +248,13 @@ __device__ __forceinline__ void chunk_rows(const int64_t *off, int64_t q0, int l
                                            int *rowof, int *sh) {
   for (int t = threadIdx.x; t < CH; t += blockDim.x) rowof[t] = -1;
   __syncthreads();
+  // the start of every non-empty row (an empty row starts where the next
+  // non-empty one does, and that one owns the slot): one plain store per
+  // slot, no atomics
   for (int r = lo + (int)threadIdx.x; r <= hi; r += blockDim.x) {
     int64_t s = off[r] - q0;
     if (s < 0) s = 0;
-    if (s < len) atomicMax(&rowof[s], r);
+    if (s < len && (r == hi || off[r + 1] > off[r])) rowof[s] = r;
   }
   __syncthreads();
   const int per = CH / (int)blockDim.x;

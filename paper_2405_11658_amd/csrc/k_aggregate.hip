@@ -77,12 +77,46 @@ __global__ __launch_bounds__(256) void k_agg_group(AggArgs a, const int32_t *cro
   const int64_t q0 = (int64_t)blockIdx.x * kChunk;
   const int len = (int)min((int64_t)kChunk, a.nnz - q0);
   chunk_rows<kChunk>(a.off, q0, len, crow[blockIdx.x], crow[blockIdx.x + 1], rowof, sh);
-  for (int t = threadIdx.x; t < len; t += blockDim.x) {
-    const int64_t e = q0 + t;
-    const int u = rowof[t];
-    const int64_t dst = eoff[pos[u]] + (e - a.off[u]);
-    gkey[dst] = (uint32_t)a.C[a.idx[e]];
-    gval[dst] = a.w[e];
+  // the thread's entries in three rounds of loads, each round's loads issued
+  // together: ids, weights and row data; then communities and places; then
+  // the stores
+  constexpr int PER = kChunk / 256;
+  int j[PER], pu[PER];
+  float x[PER];
+  int64_t ru[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int t = threadIdx.x + k * 256;
+    j[k] = 0;
+    pu[k] = 0;
+    x[k] = 0.0f;
+    ru[k] = 0;
+    if (t < len) {
+      const int u = rowof[t];
+      j[k] = a.idx[q0 + t];
+      x[k] = a.w[q0 + t];
+      pu[k] = pos[u];
+      ru[k] = a.off[u];
+    }
+  }
+  int c[PER];
+  int64_t d[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int t = threadIdx.x + k * 256;
+    c[k] = 0;
+    d[k] = 0;
+    if (t < len) {
+      c[k] = a.C[j[k]];
+      d[k] = eoff[pu[k]] + (q0 + t - ru[k]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    if (threadIdx.x + k * 256 < len) {
+      gkey[d[k]] = (uint32_t)c[k];
+      gval[d[k]] = x[k];
+    }
   }
 }
 void agg_group(const AggArgs &a, const int32_t *crow, const int32_t *pos, const int64_t *eoff, uint32_t *gkey,

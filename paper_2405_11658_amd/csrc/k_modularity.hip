@@ -54,11 +54,27 @@ __global__ __launch_bounds__(256) void k_mod_intra(const int64_t *off, const int
   const int64_t q0 = (int64_t)blockIdx.x * kChunk;
   const int len = (int)min((int64_t)kChunk, nnz - q0);
   chunk_rows<kChunk>(off, q0, len, crow[blockIdx.x], crow[blockIdx.x + 1], rowof, sh);
-  double sig = 0.0;
-  for (int t = threadIdx.x; t < len; t += blockDim.x) {
-    const int64_t q = q0 + t;
-    if (C[idx[q]] == C[rowof[t]]) sig += (double)w[q];
+  // loads in two rounds, each issued together: ids, weights and row ids;
+  // then both communities
+  constexpr int PER = kChunk / 256;
+  int j[PER], r[PER];
+  float x[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int t = threadIdx.x + k * 256;
+    j[k] = 0;
+    r[k] = 0;
+    x[k] = 0.0f;
+    if (t < len) {
+      j[k] = idx[q0 + t];
+      x[k] = w[q0 + t];
+      r[k] = rowof[t];
+    }
   }
+  double sig = 0.0;
+#pragma unroll
+  for (int k = 0; k < PER; ++k)
+    if (threadIdx.x + k * 256 < len && C[j[k]] == C[r[k]]) sig += (double)x[k];
   sig = block_sum(sig, sd);
   if (threadIdx.x == 0 && sig != 0.0) unsafeAtomicAdd(&acc[0], sig);
 }

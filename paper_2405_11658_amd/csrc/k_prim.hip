@@ -133,7 +133,16 @@ __global__ __launch_bounds__(kPT) void k_rs_hist(const K *keys, RsSeg g, int shi
   for (int d = threadIdx.x; d < kDig; d += kPT) h[d] = 0;
   __syncthreads();
   const K mask = (K)((1u << bits) - 1u);
-  for (int64_t p = ts.lo + threadIdx.x; p < ts.hi; p += kPT) atomicAdd(&h[(int)((keys[p] >> shift) & mask)], 1);
+  // all of the thread's loads issued together, then the counts
+  K kr[kPR];
+#pragma unroll
+  for (int r = 0; r < kPR; ++r) {
+    const int64_t p = ts.lo + r * kPT + threadIdx.x;
+    kr[r] = p < ts.hi ? keys[p] : (K)0;
+  }
+#pragma unroll
+  for (int r = 0; r < kPR; ++r)
+    if (ts.lo + r * kPT + threadIdx.x < ts.hi) atomicAdd(&h[(int)((kr[r] >> shift) & mask)], 1);
   __syncthreads();
   for (int d = threadIdx.x; d < kDig; d += kPT) {
     hist[kDig * ts.f0 + (int64_t)d * ts.nt + (t - ts.f0)] = h[d];
@@ -183,17 +192,27 @@ __global__ __launch_bounds__(kPT) void k_rs_scatter(const K *ki, const V *vi, K 
   const K mask = (K)((1u << bits) - 1u);
   const int wid = (int)threadIdx.x / kWave;
   const unsigned long long below = lane() == 0 ? 0ull : (~0ull >> (64 - lane()));
-  for (int64_t b = ts.lo; b < ts.hi; b += kPT) {
-    const int64_t p = b + threadIdx.x;
-    const bool act = p < ts.hi;
-    K key = 0;
-    V val = V();
-    int dg = 0;
-    if (act) {
-      key = ki[p];
-      val = vi[p];
-      dg = (int)((key >> shift) & mask);
+  // the tile's items in registers first (all loads in flight together)
+  K kr[kPR];
+  V vr[kPR];
+#pragma unroll
+  for (int r = 0; r < kPR; ++r) {
+    const int64_t p = ts.lo + r * kPT + threadIdx.x;
+    kr[r] = (K)0;
+    vr[r] = V();
+    if (p < ts.hi) {
+      kr[r] = ki[p];
+      vr[r] = vi[p];
     }
+  }
+#pragma unroll
+  for (int r = 0; r < kPR; ++r) {
+    const int64_t p = ts.lo + r * kPT + threadIdx.x;
+    if (ts.lo + r * kPT >= ts.hi) break;  // uniform
+    const bool act = p < ts.hi;
+    const K key = kr[r];
+    const V val = vr[r];
+    const int dg = act ? (int)((key >> shift) & mask) : 0;
     unsigned long long same = __ballot(act);
     for (int bit = 0; bit < bits; ++bit) {
       const unsigned long long on = __ballot(act && ((dg >> bit) & 1));
