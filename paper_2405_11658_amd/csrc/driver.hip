@@ -146,6 +146,10 @@ constexpr double kStallKeep = 0.8;
 // table does not fit a wavefront's 512-slot LDS table (degree > 256) moves in
 // the multi-workgroup hub slices.
 constexpr int kDefaultHubDeg = 256;
+// Levels of at least this many vertices (C alone 64 MB, 16x an XCD's L2)
+// read neighbour communities and community totals through the caches in the
+// asynchronous sweeps.
+constexpr int64_t kCachedLevel = 16 << 20;
 constexpr int kDefaultAsyncWaves = 2048;  // wavefronts of the asynchronous sweeps, at most
 constexpr int kMaxAsyncWaves = 65536;
 constexpr int64_t kVertsPerWave = 1024;  // level-0 vertices with edges per sweeping wavefront, at least
@@ -752,6 +756,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     ma.anext = &sc->anext; ma.akeys = akeys; ma.avals = avals;
     ma.alist = alist; ma.alen = alen;
     ma.hubdeg = hubdeg;
+    ma.cached = async && nl >= kCachedLevel;
     int li = 0;
     int64_t moves_total = 0;
     unsigned long long min_moves = ~0ull;
@@ -848,6 +853,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     ra.anext = &sc->anext; ra.akeys = akeys; ra.avals = avals;
     ra.alist = alist; ra.alen = alen;
     ra.hubdeg = hubdeg;
+    ra.cached = async && nl >= kCachedLevel;
     reset_iter(counts, NS * kNB, nullptr, &sc->refined, async ? &sc->anext : nullptr, x.s);
     refine_break(ra, x.s);
     x.launched("break");

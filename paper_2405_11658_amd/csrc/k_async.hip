@@ -34,6 +34,29 @@ __device__ __forceinline__ int ld_int(const int32_t *p) {
 __device__ __forceinline__ double ld_dbl(const double *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Reads of neighbour communities and community totals.  CA = false:
+// agent-scope loads, which always see the latest value of any wavefront on
+// the device.  CA = true (levels whose state is many times the size of an
+// XCD's L2): workgroup-scope loads, which may be served by this XCD's
+// caches; a line there is evicted within microseconds by the level's random
+// traffic, so a value is at most that stale - the same order as the
+// staleness the vertices in flight already see - and the loads avoid the
+// memory-side round trip that bounds the sweep.
+template <bool CA>
+__device__ __forceinline__ int ld_c(const int32_t *p) {
+  if (CA) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <bool CA>
+__device__ __forceinline__ double ld_s(const double *p) {
+  if (CA) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <bool CA>
+__device__ __forceinline__ unsigned long long ld_p(const unsigned long long *p) {
+  if (CA) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ uint8_t ld_u8(const uint8_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -189,6 +212,7 @@ __device__ __forceinline__ void batch_ids(EdgeBatch &eb, const int32_t *idx, con
 
 // Communities of the batch's neighbours; with CB given only neighbours whose
 // CB equals cb count (both loads issued together).
+template <bool CA>
 __device__ __forceinline__ void batch_comms(EdgeBatch &eb, const int32_t *C, const int32_t *CB, int cb, int i) {
   int bj[kUnroll];
 #pragma unroll
@@ -196,7 +220,7 @@ __device__ __forceinline__ void batch_comms(EdgeBatch &eb, const int32_t *C, con
     eb.c[u] = kEmpty;
     bj[u] = cb;
     if (eb.j[u] != i) {
-      eb.c[u] = ld_int(&C[eb.j[u]]);
+      eb.c[u] = ld_c<CA>(&C[eb.j[u]]);
       if (CB) bj[u] = CB[eb.j[u]];
     }
   }
@@ -207,12 +231,11 @@ __device__ __forceinline__ void batch_comms(EdgeBatch &eb, const int32_t *C, con
 
 // Refinement: communities and bounds of the batch's neighbours from the
 // packed words (bound << 32 | community), one 8-byte load per neighbour.
+template <bool CA>
 __device__ __forceinline__ void batch_comms_packed(EdgeBatch &eb, const unsigned long long *CP, int cb, int i) {
   unsigned long long pk[kUnroll];
 #pragma unroll
-  for (int u = 0; u < kUnroll; ++u)
-    pk[u] = eb.j[u] != i ? __hip_atomic_load(&CP[eb.j[u]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                         : ~0ull;
+  for (int u = 0; u < kUnroll; ++u) pk[u] = eb.j[u] != i ? ld_p<CA>(&CP[eb.j[u]]) : ~0ull;
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u)
     eb.c[u] = (eb.j[u] != i && (int)(pk[u] >> 32) == cb) ? (int)(uint32_t)pk[u] : kEmpty;
@@ -221,6 +244,7 @@ __device__ __forceinline__ void batch_comms_packed(EdgeBatch &eb, const unsigned
 // Adds the edges [e0, e1) of vertex i to table t, keyed by the neighbour's
 // current community: the first kUnroll * kWave from the loaded batch, the
 // rest loaded here.  Returns (in all lanes) the weight to community d.
+template <bool CA>
 __device__ __forceinline__ double table_edges(const WaveTable &t, const EdgeBatch &eb, const int32_t *idx,
                                               const float *w, const int32_t *C, const int32_t *CB, int cb,
                                               int i, int d, int64_t e0, int64_t e1,
@@ -235,8 +259,8 @@ __device__ __forceinline__ double table_edges(const WaveTable &t, const EdgeBatc
   for (int64_t base = e0 + kUnroll * kWave; base < e1; base += kUnroll * kWave) {
     EdgeBatch r;
     batch_ids(r, idx, w, i, base, e1);
-    if (CP) batch_comms_packed(r, CP, cb, i);
-    else batch_comms(r, C, CB, cb, i);
+    if (CP) batch_comms_packed<CA>(r, CP, cb, i);
+    else batch_comms<CA>(r, C, CB, cb, i);
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       if (r.c[u] == kEmpty) continue;
@@ -261,12 +285,13 @@ __device__ __forceinline__ void mark_edges(uint8_t *U, const int32_t *idx, int i
 
 // Scores up to kUnroll (community, weight) pairs per lane with their Sigma
 // loads in flight together, keeping the best positive gain.
+template <bool CA>
 __device__ __forceinline__ void score_batch(const int (&c)[kUnroll], const double (&x)[kUnroll], double M2,
                                             double b, double Ki, double Sd, const double *Sig, double &bg,
                                             int &bc) {
   double S[kUnroll];
 #pragma unroll
-  for (int u = 0; u < kUnroll; ++u) S[u] = c[u] != kEmpty ? ld_dbl(&Sig[c[u]]) : 0.0;
+  for (int u = 0; u < kUnroll; ++u) S[u] = c[u] != kEmpty ? ld_s<CA>(&Sig[c[u]]) : 0.0;
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) {
     if (c[u] == kEmpty) continue;
@@ -277,6 +302,7 @@ __device__ __forceinline__ void score_batch(const int (&c)[kUnroll], const doubl
 
 // Best positive-gain community other than d; (0, kNoComm) if none.  An LDS
 // table is read through its list of taken slots, a global one slot by slot.
+template <bool CA>
 __device__ __forceinline__ void best_move(const WaveTable &t, double M2, int d, double b, double Ki, double Sd,
                                           const double *Sig, double &bg, int &bc) {
   bg = 0.0;
@@ -302,7 +328,7 @@ __device__ __forceinline__ void best_move(const WaveTable &t, double M2, int d, 
         if (c[u] == d) c[u] = kEmpty;
       }
     }
-    score_batch(c, x, M2, b, Ki, Sd, Sig, bg, bc);
+    score_batch<CA>(c, x, M2, b, Ki, Sd, Sig, bg, bc);
   }
   group_argmax<kWave>(bg, bc);
 }
@@ -331,7 +357,7 @@ __device__ __forceinline__ int64_t grab(unsigned long long *next, Grab &g) {
   return r;
 }
 
-template <int WPB, int LDSCAP>
+template <int WPB, int LDSCAP, bool CA>
 __global__ __launch_bounds__(256) void k_move_async(MoveArgs a) {
   __shared__ WaveLds<LDSCAP> lds[WPB];
   const int wv = threadIdx.x / kWave;
@@ -380,13 +406,13 @@ __global__ __launch_bounds__(256) void k_move_async(MoveArgs a) {
       ne += (unsigned long long)(e1 - e0);
       EdgeBatch eb;
       batch_ids(eb, a.idx, a.w, i, e0, e1);
-      batch_comms(eb, a.C, nullptr, 0, i);
+      batch_comms<CA>(eb, a.C, nullptr, 0, i);
       WaveTable t = wave_table(lds[wv], gk, gv, e1 - e0);
-      const double b = table_edges(t, eb, a.idx, a.w, a.C, nullptr, 0, i, d, e0, e1);
+      const double b = table_edges<CA>(t, eb, a.idx, a.w, a.C, nullptr, 0, i, d, e0, e1);
       tab_sync(t);
       double bg;
       int bc;
-      best_move(t, a.M2, d, b, Ki, ld_dbl(&a.Sig[d]), a.Sig, bg, bc);
+      best_move<CA>(t, a.M2, d, b, Ki, ld_s<CA>(&a.Sig[d]), a.Sig, bg, bc);
       tab_release(t);
       if (bc == kNoComm) continue;
       if (lane() == 0) {
@@ -426,7 +452,8 @@ static void launch_async(K4 k4, K2 k2, const Args &a, int waves, bool wide, hipS
 }
 
 void move_async(const MoveArgs &a, int waves, bool wide, hipStream_t s) {
-  launch_async(k_move_async<4, 512>, k_move_async<2, 2048>, a, waves, wide, s);
+  if (a.cached) launch_async(k_move_async<4, 512, true>, k_move_async<2, 2048, true>, a, waves, wide, s);
+  else launch_async(k_move_async<4, 512, false>, k_move_async<2, 2048, false>, a, waves, wide, s);
 }
 
 constexpr int kRefineTries = 4;  // evaluations of a refinement candidate whose target emptied
@@ -442,7 +469,7 @@ __device__ __forceinline__ bool join_nonempty(double *sig, double x) {
   return false;
 }
 
-template <int WPB, int LDSCAP>
+template <int WPB, int LDSCAP, bool CA>
 __global__ __launch_bounds__(256) void k_refine_async(RefineArgs a) {
   __shared__ WaveLds<LDSCAP> lds[WPB];
   const int wv = threadIdx.x / kWave;
@@ -489,13 +516,13 @@ __global__ __launch_bounds__(256) void k_refine_async(RefineArgs a) {
       for (int attempt = 0; attempt < kRefineTries; ++attempt) {
         EdgeBatch eb;
         batch_ids(eb, a.idx, a.w, i, e0, e1);
-        batch_comms_packed(eb, a.CP, cb, i);
+        batch_comms_packed<CA>(eb, a.CP, cb, i);
         WaveTable t = wave_table(lds[wv], gk, gv, e1 - e0);
-        const double b = table_edges(t, eb, a.idx, a.w, a.C, a.CB, cb, i, c, e0, e1, a.CP);
+        const double b = table_edges<CA>(t, eb, a.idx, a.w, a.C, a.CB, cb, i, c, e0, e1, a.CP);
         tab_sync(t);
         double bg;
         int bc;
-        best_move(t, a.M2, c, b, Ki, Ki, a.Sig, bg, bc);
+        best_move<CA>(t, a.M2, c, b, Ki, Ki, a.Sig, bg, bc);
         tab_release(t);
         if (bc == kNoComm) break;
         int again = 0;
@@ -533,7 +560,8 @@ void pack_cb(const int32_t *C, const int32_t *CB, int64_t n, unsigned long long 
 }
 
 void refine_async(const RefineArgs &a, int waves, bool wide, hipStream_t s) {
-  launch_async(k_refine_async<4, 512>, k_refine_async<2, 2048>, a, waves, wide, s);
+  if (a.cached) launch_async(k_refine_async<4, 512, true>, k_refine_async<2, 2048, true>, a, waves, wide, s);
+  else launch_async(k_refine_async<4, 512, false>, k_refine_async<2, 2048, false>, a, waves, wide, s);
 }
 
 __global__ void k_edge_flags(const int64_t *off, int64_t n, int32_t *flags) {

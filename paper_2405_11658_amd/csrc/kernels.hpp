@@ -192,6 +192,7 @@ struct MoveArgs {
   int *akeys;                 // per-wavefront global tables, 2*kHubDeg slots each
   double *avals;
   int64_t hubdeg;             // degree above which a vertex takes the hub path (<= kHubDeg)
+  int32_t cached;             // asynchronous sweep: cache-served reads of C and Sigma (large levels)
 };
 // Per level: counts[s*kNB+b] of vertices with edges, slice sizes, and the
 // vertex-by-slice grouping (slice_fill zeroed, slice_off = starts of slices).
@@ -233,6 +234,7 @@ struct RefineArgs {
   int32_t *C;
   int32_t *CB;
   unsigned long long *CP;   // asynchronous sweep: CB << 32 | C per vertex, kept with C
+  int32_t cached;           // asynchronous sweep: cache-served reads (large levels)
   const double *K;
   double *Sig;
   const uint8_t *dC;
