@@ -375,6 +375,8 @@ def main() -> int:
                     "kernel": PROF_KERNEL_NAMES[dom], "avg_launch_us": round(avg_ms * 1e3, 2),
                     "launches_per_step": pd["launches"] / args.steps,
                     "algorithmic_bytes_per_launch": round(bytes_per_launch),
+                    "entries_per_launch": round(pd["entries"] / pd["launches"]),
+                    "vertices_per_launch": round(pd["vertices"] / pd["launches"]),
                     "share_of_step": round(pd["ms"] / args.steps / ms_per_step, 4)}
     kernels = {name: {"ms_per_step": round(v["ms"] / args.steps, 3), "launches_per_step": v["launches"] / args.steps}
                for name, v in prof.items() if v["launches"]}

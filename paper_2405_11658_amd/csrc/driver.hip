@@ -757,6 +757,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     ma.alist = alist; ma.alen = alen;
     ma.hubdeg = hubdeg;
     ma.cached = async && nl >= kCachedLevel;
+    ma.defer = async && NW > 1;
     int li = 0;
     int64_t moves_total = 0;
     unsigned long long min_moves = ~0ull;
@@ -854,6 +855,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     ra.alist = alist; ra.alen = alen;
     ra.hubdeg = hubdeg;
     ra.cached = async && nl >= kCachedLevel;
+    ra.defer = async && NW > 1;
     reset_iter(counts, NS * kNB, nullptr, &sc->refined, async ? &sc->anext : nullptr, x.s);
     refine_break(ra, x.s);
     x.launched("break");

@@ -10,14 +10,17 @@
 // Sigma (agent-scope loads, not a stale L1 line), builds its neighbour
 // community table in LDS (degree <= 256) or in a global-memory region of the
 // wavefront (degree <= 2048), and applies its best move immediately: C store,
-// Sigma atomics, neighbours marked unprocessed.  Vertices of higher degree are
-// handled before the sweep by the multi-workgroup hub kernels.
+// Sigma atomics, neighbours marked unprocessed.  Changes to the Sigma of the
+// few communities holding a large share of the weight are summed per
+// wavefront and added every few chunks (Pend below).  Vertices of higher
+// degree are handled before the sweep by the multi-workgroup hub kernels.
 //
 // Refinement follows the same scheme: an isolated vertex of a changed bound
 // (Sigma of its community equal to its own K) looks for the best community
 // inside its bound, claims its own community with a compare-and-swap of
 // Sigma from K_i to 0, and joins the target if the target's representative
-// still holds its label.
+// still holds its label (checked only while the target may still be a
+// singleton).
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -101,6 +104,26 @@ struct WaveTable {
   int *cnt;        // LDS only: length of list
 };
 
+// Sigma updates of popular communities held back by one wavefront.  Every
+// wavefront adds into the few communities that hold a large share of the
+// level's weight (on RMAT graphs most moves and joins involve them), and
+// device-scope atomics on one address are performed one after another at
+// the memory side; a wavefront waits for its own before its next load, so
+// the sweep would run at the pace of that one address.  A wavefront
+// therefore sums its changes to such a community here while the sum stays
+// below kHotEps / W of the community's Sigma (W wavefronts in the sweep, so
+// all held-back changes together stay below kHotEps of it), and adds it
+// with one atomic when it would exceed that, every kGrabChunks chunks, and
+// when the list is full.
+constexpr int kPend = 16;
+constexpr double kHotShare = 1.0 / 4096;  // popular: Sigma >= this share of 2m
+constexpr double kHotEps = 1.0 / 64;
+struct Pend {
+  int c[kPend];
+  double d[kPend];
+  int n;
+};
+
 // LDS area of one wavefront for capacity LDSCAP.
 template <int LDSCAP>
 struct WaveLds {
@@ -108,12 +131,56 @@ struct WaveLds {
   double vals[LDSCAP];
   uint16_t list[LDSCAP / 2];
   int cnt;
+  Pend pend;
 };
 
 template <int LDSCAP>
 __device__ __forceinline__ void lds_table_init(WaveLds<LDSCAP> &l) {
   for (int s = lane(); s < LDSCAP; s += kWave) { l.keys[s] = kEmpty; l.vals[s] = 0.0; }
-  if (lane() == 0) l.cnt = 0;
+  if (lane() == 0) { l.cnt = 0; l.pend.n = 0; }
+  lds_fence();
+}
+
+// Adds the held-back deltas to Sigma (one atomic per community, from
+// different lanes) and empties the list.
+__device__ __forceinline__ void pend_flush(Pend &p, double *Sig) {
+  const int n = p.n;
+  if (lane() < n) unsafeAtomicAdd(&Sig[p.c[lane()]], p.d[lane()]);
+  lds_fence();
+  if (lane() == 0) p.n = 0;
+  lds_fence();
+}
+
+// Holds back Sigma[c] += x (c, x and lim uniform over the wavefront): the
+// community's held-back sum is added at once when its magnitude would
+// exceed lim.
+__device__ __forceinline__ void pend_add(Pend &p, double *Sig, int c, double x, double lim) {
+  int n = p.n;
+  const unsigned long long hit = __ballot(lane() < n && p.c[lane()] == c);
+  if (hit) {
+    if (lane() == 0) {
+      const int h = __ffsll(hit) - 1;
+      const double d = p.d[h] + x;
+      if (fabs(d) > lim) {
+        unsafeAtomicAdd(&Sig[c], d);
+        p.d[h] = 0.0;
+      } else {
+        p.d[h] = d;
+      }
+    }
+  } else if (fabs(x) > lim) {
+    if (lane() == 0) unsafeAtomicAdd(&Sig[c], x);
+  } else {
+    if (n == kPend) {
+      pend_flush(p, Sig);
+      n = 0;
+    }
+    if (lane() == 0) {
+      p.c[n] = c;
+      p.d[n] = x;
+      p.n = n + 1;
+    }
+  }
   lds_fence();
 }
 
@@ -284,11 +351,12 @@ __device__ __forceinline__ void mark_edges(uint8_t *U, const int32_t *idx, int i
 }
 
 // Scores up to kUnroll (community, weight) pairs per lane with their Sigma
-// loads in flight together, keeping the best positive gain.
+// loads in flight together, keeping the best positive gain and the Sigma it
+// was scored with.
 template <bool CA>
 __device__ __forceinline__ void score_batch(const int (&c)[kUnroll], const double (&x)[kUnroll], double M2,
                                             double b, double Ki, double Sd, const double *Sig, double &bg,
-                                            int &bc) {
+                                            int &bc, double &bs) {
   double S[kUnroll];
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) S[u] = c[u] != kEmpty ? ld_s<CA>(&Sig[c[u]]) : 0.0;
@@ -296,17 +364,19 @@ __device__ __forceinline__ void score_batch(const int (&c)[kUnroll], const doubl
   for (int u = 0; u < kUnroll; ++u) {
     if (c[u] == kEmpty) continue;
     const double g = move_score(M2, x[u], b, Ki, S[u], Sd);
-    if (g > 0.0 && better(g, c[u], bg, bc)) { bg = g; bc = c[u]; }
+    if (g > 0.0 && better(g, c[u], bg, bc)) { bg = g; bc = c[u]; bs = S[u]; }
   }
 }
 
-// Best positive-gain community other than d; (0, kNoComm) if none.  An LDS
-// table is read through its list of taken slots, a global one slot by slot.
+// Best positive-gain community other than d; (0, kNoComm) if none, with the
+// Sigma of the best as read for its score (bs).  An LDS table is read
+// through its list of taken slots, a global one slot by slot.
 template <bool CA>
 __device__ __forceinline__ void best_move(const WaveTable &t, double M2, int d, double b, double Ki, double Sd,
-                                          const double *Sig, double &bg, int &bc) {
+                                          const double *Sig, double &bg, int &bc, double &bs) {
   bg = 0.0;
   bc = kNoComm;
+  bs = 0.0;
   const uint32_t n = t.global ? t.mask + 1 : (uint32_t)*t.cnt;
   for (uint32_t q0 = 0; q0 < n; q0 += kUnroll * kWave) {
     int c[kUnroll];
@@ -328,9 +398,13 @@ __device__ __forceinline__ void best_move(const WaveTable &t, double M2, int d, 
         if (c[u] == d) c[u] = kEmpty;
       }
     }
-    score_batch<CA>(c, x, M2, b, Ki, Sd, Sig, bg, bc);
+    score_batch<CA>(c, x, M2, b, Ki, Sd, Sig, bg, bc, bs);
   }
+  const int lc = bc;
   group_argmax<kWave>(bg, bc);
+  // table keys are distinct, so exactly one lane scored the winner
+  const unsigned long long wl = __ballot(bc != kNoComm && lc == bc);
+  bs = __shfl(bs, wl ? __ffsll(wl) - 1 : 0);
 }
 
 // A wavefront takes kGrabChunks chunks of kAsyncChunk list positions at a
@@ -368,8 +442,12 @@ __global__ __launch_bounds__(256) void k_move_async(MoveArgs a) {
   double gsum = 0.0;
   long long mv = 0;
   unsigned long long nv = 0, ne = 0;  // vertices evaluated, edges scanned
+  Pend &pd = lds[wv].pend;
+  const double hot = a.defer ? a.M2 * kHotShare : __builtin_inf();
+  const double eps = kHotEps / ((double)gridDim.x * (blockDim.x / kWave));
   Grab gr;
   for (;;) {
+    if (gr.left == 0) pend_flush(pd, a.Sig);
     const int64_t base = grab(a.anext, gr);
     if (base >= a.alen) break;
     // each lane fetches the state of one vertex of the chunk; the chunk's
@@ -410,19 +488,22 @@ __global__ __launch_bounds__(256) void k_move_async(MoveArgs a) {
       WaveTable t = wave_table(lds[wv], gk, gv, e1 - e0);
       const double b = table_edges<CA>(t, eb, a.idx, a.w, a.C, nullptr, 0, i, d, e0, e1);
       tab_sync(t);
-      double bg;
+      double bg, bs;
       int bc;
-      best_move<CA>(t, a.M2, d, b, Ki, ld_s<CA>(&a.Sig[d]), a.Sig, bg, bc);
+      const double Sd = ld_s<CA>(&a.Sig[d]);
+      best_move<CA>(t, a.M2, d, b, Ki, Sd, a.Sig, bg, bc, bs);
       tab_release(t);
       if (bc == kNoComm) continue;
       if (lane() == 0) {
         st_int(&a.C[i], bc);
-        unsafeAtomicAdd(&a.Sig[d], -Ki);
-        unsafeAtomicAdd(&a.Sig[bc], Ki);
+        if (Sd < hot) unsafeAtomicAdd(&a.Sig[d], -Ki);
+        if (bs < hot) unsafeAtomicAdd(&a.Sig[bc], Ki);
         if (a.track) { st_u8(&a.dC[d], 1); st_u8(&a.dC[bc], 1); }
         gsum += bg;
         mv += 1;
       }
+      if (Sd >= hot) pend_add(pd, a.Sig, d, -Ki, Sd * eps);
+      if (bs >= hot) pend_add(pd, a.Sig, bc, Ki, bs * eps);
       if (lane() == k) dv = bc;
       mark_edges(a.U, a.idx, i, e0, e1, eb);
       // the move may have marked later vertices of the chunk unprocessed
@@ -430,6 +511,7 @@ __global__ __launch_bounds__(256) void k_move_async(MoveArgs a) {
       m = __ballot(lane() > k && elig && ld_u8(&a.U[v]));
     }
   }
+  pend_flush(pd, a.Sig);
   if (lane() == 0) {
     if (gsum != 0.0) unsafeAtomicAdd(a.gain, gsum);
     if (mv) atomicAdd(a.moves, (unsigned long long)mv);
@@ -477,8 +559,12 @@ __global__ __launch_bounds__(256) void k_refine_async(RefineArgs a) {
   const int64_t gw = (int64_t)blockIdx.x * WPB + wv;
   int *gk = a.akeys + gw * kHubDeg * 2;
   double *gv = a.avals + gw * kHubDeg * 2;
+  Pend &pd = lds[wv].pend;
+  const double hot = a.defer ? a.M2 * kHotShare : __builtin_inf();
+  const double eps = kHotEps / ((double)gridDim.x * (blockDim.x / kWave));
   Grab gr;
   for (;;) {
+    if (gr.left == 0) pend_flush(pd, a.Sig);
     const int64_t base = grab(a.anext, gr);
     if (base >= a.alen) break;
     // each lane fetches one vertex of the chunk: isolated vertices of a
@@ -520,35 +606,51 @@ __global__ __launch_bounds__(256) void k_refine_async(RefineArgs a) {
         WaveTable t = wave_table(lds[wv], gk, gv, e1 - e0);
         const double b = table_edges<CA>(t, eb, a.idx, a.w, a.C, a.CB, cb, i, c, e0, e1, a.CP);
         tab_sync(t);
-        double bg;
+        double bg, bs;
         int bc;
-        best_move<CA>(t, a.M2, c, b, Ki, Ki, a.Sig, bg, bc);
+        best_move<CA>(t, a.M2, c, b, Ki, Ki, a.Sig, bg, bc, bs);
         tab_release(t);
         if (bc == kNoComm) break;
-        int again = 0;
+        // Every vertex of a changed bound starts alone, so a neighbour other
+        // than bc itself seen in bc has joined bc; then bc's representative
+        // is no longer isolated, can never leave, and bc can never empty: the
+        // join needs neither the representative check nor the old total.
+        bool seen = false;
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) seen |= eb.c[u] == bc && eb.j[u] != bc;
+        const bool held = __ballot(seen) != 0;
+        int again = 0, joined = 0;
         if (lane() == 0) {
-          if (ld_int(&a.C[bc]) != bc) {
+          if (!held && ld_int(&a.C[bc]) != bc) {
             again = 1;
           } else {
             // claim the singleton: Sigma[c] K_i -> 0 fails if someone joined it
             unsigned long long *sc = (unsigned long long *)&a.Sig[c];
             const unsigned long long want = __double_as_longlong(Ki);
             if (atomicCAS(sc, want, 0ull) == want) {
-              if (join_nonempty(&a.Sig[bc], Ki)) {
-                st_int(&a.C[i], bc);
-                __hip_atomic_store(&a.CP[i], ((unsigned long long)(uint32_t)cb << 32) | (uint32_t)bc,
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              if (held) {
+                if (bs < hot) unsafeAtomicAdd(&a.Sig[bc], Ki);
+                joined = 1;
+              } else if (join_nonempty(&a.Sig[bc], Ki)) {
+                joined = 1;
               } else {
                 unsafeAtomicAdd(&a.Sig[c], Ki);  // the target emptied meanwhile: stay, look again
                 again = 1;
               }
+              if (joined) {
+                st_int(&a.C[i], bc);
+                __hip_atomic_store(&a.CP[i], ((unsigned long long)(uint32_t)cb << 32) | (uint32_t)bc,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              }
             }
           }
         }
+        if (held && bs >= hot && __shfl(joined, 0)) pend_add(pd, a.Sig, bc, Ki, bs * eps);
         if (!__shfl(again, 0)) break;
       }
     }
   }
+  pend_flush(pd, a.Sig);
 }
 
 __global__ void k_pack_cb(const int32_t *C, const int32_t *CB, int64_t n, unsigned long long *CP) {

@@ -193,6 +193,7 @@ struct MoveArgs {
   double *avals;
   int64_t hubdeg;             // degree above which a vertex takes the hub path (<= kHubDeg)
   int32_t cached;             // asynchronous sweep: cache-served reads of C and Sigma (large levels)
+  int32_t defer;              // asynchronous sweep: batch the Sigma updates of popular communities
 };
 // Per level: counts[s*kNB+b] of vertices with edges, slice sizes, and the
 // vertex-by-slice grouping (slice_fill zeroed, slice_off = starts of slices).
@@ -235,6 +236,7 @@ struct RefineArgs {
   int32_t *CB;
   unsigned long long *CP;   // asynchronous sweep: CB << 32 | C per vertex, kept with C
   int32_t cached;           // asynchronous sweep: cache-served reads (large levels)
+  int32_t defer;            // asynchronous sweep: batch the joins of popular communities
   const double *K;
   double *Sig;
   const uint8_t *dC;
