@@ -180,21 +180,25 @@ def test_default_mode_quality_vs_oracle_async():
     order) on id-permuted planted-partition graphs (no id locality to favour
     either order): static runs, and DF updates started from the same installed
     state on both sides.  The mean gap Q_gpu - Q_oracle of the six DF
-    updates (same membership on both sides) must lie within 1e-3 either way;
-    each static run (from singletons, so a different order from the start)
-    may fall at most 5e-3 below the oracle's; every community connected.
-    (The two orders are different heuristics: relabelling the vertices alone
-    moves the oracle's result by about 2.5e-3 on these graphs.)"""
+    updates (same membership on both sides) must lie within 1e-3 either way.
+    Static runs start from singletons, so the two orders differ from the
+    start: relabelling the vertices alone moves the oracle's result by about
+    2.5e-3 on these graphs, and single GPU runs of one graph spread by timing
+    (12 runs per seed: standard deviation about 1.5e-3, lowest -6.5e-3).  So
+    the static gate is on the mean of three runs per seed (nine runs,
+    measured means -1.7e-3 to -2.1e-3, standard error about 5e-4): at least
+    -3e-3.  Every community connected."""
     gaps, sgaps = [], []
     for seed in (1, 2, 3):
         g = gen.planted_partition(4096, 64, 0.1, 0.001, seed=seed, permute=True)
-        h = L.leiden_create(g.off, g.idx, g.w)
-        say("default mode static, planted 4096 permuted, seed", seed)
-        C, q, st = L.leiden_static(h)
         ost, _ = oracle.static(og(g))
         qo = oracle.modularity(og(g), ost.C)
-        sgaps.append(q - qo)
-        assert communities_connected(og(g), to_np(C))
+        for r in range(3):
+            h = L.leiden_create(g.off, g.idx, g.w)
+            say("default mode static, planted 4096 permuted, seed", seed, "run", r)
+            C, q, st = L.leiden_static(h)
+            sgaps.append(q - qo)
+            assert communities_connected(og(g), to_np(C))
         state = ost
         for k in range(2):
             L.leiden_set_state(h, state.C)
@@ -210,7 +214,7 @@ def test_default_mode_quality_vs_oracle_async():
     say("static Q_gpu - Q_oracle:", np.round(sgaps, 5).tolist(), "DF (same state):", np.round(gaps, 5).tolist(),
         "mean", round(float(gaps.mean()), 5))
     assert abs(gaps.mean()) <= 1e-3, gaps
-    assert sgaps.min() >= -5e-3, sgaps
+    assert sgaps.mean() >= -3e-3, sgaps
 
 
 def test_empty_batch_and_errors():
