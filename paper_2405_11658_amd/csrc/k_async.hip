@@ -338,15 +338,34 @@ __device__ __forceinline__ double table_edges(const WaveTable &t, const EdgeBatc
   return group_sum<kWave>(own);
 }
 
-// Marks the neighbours of vertex i unprocessed after it moved.
+// A flag set by many wavefronts (a neighbour of many moving vertices; on
+// RMAT graphs the hubs are neighbours of nearly all): with WG the store
+// stays in this XCD's L2 until the line is written back (at the latest when
+// the sweep ends), instead of a device-scope store that goes through to
+// memory, where stores to one line are performed one after another and
+// every wavefront waits for its own.  The flag is only ever set to one
+// value, so a late write-back can only make a vertex be evaluated once more.
+template <bool WG>
+__device__ __forceinline__ void set_flag(uint8_t *p) {
+  if (WG) __hip_atomic_store(p, (uint8_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  else st_u8(p, 1);
+}
+
+// Marks the neighbours of vertex i unprocessed after it moved.  WG: as in
+// set_flag, for sweeps of many wavefronts (a mark then reaches the other
+// XCDs by the end of the sweep at the latest, so a vertex marked after it
+// was passed over is evaluated in the next iteration, as it would be if
+// marked after its turn); one wavefront alone keeps device-scope stores and
+// so the serial sweep's order exactly.
+template <bool WG>
 __device__ __forceinline__ void mark_edges(uint8_t *U, const int32_t *idx, int i, int64_t e0, int64_t e1,
                                            const EdgeBatch &eb) {
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u)
-    if (eb.j[u] != i) st_u8(&U[eb.j[u]], 1);
+    if (eb.j[u] != i) set_flag<WG>(&U[eb.j[u]]);
   for (int64_t e = e0 + kUnroll * kWave + lane(); e < e1; e += kWave) {
     const int j = idx[e];
-    if (j != i) st_u8(&U[j], 1);
+    if (j != i) set_flag<WG>(&U[j]);
   }
 }
 
@@ -498,14 +517,18 @@ __global__ __launch_bounds__(256) void k_move_async(MoveArgs a) {
         st_int(&a.C[i], bc);
         if (Sd < hot) unsafeAtomicAdd(&a.Sig[d], -Ki);
         if (bs < hot) unsafeAtomicAdd(&a.Sig[bc], Ki);
-        if (a.track) { st_u8(&a.dC[d], 1); st_u8(&a.dC[bc], 1); }
+        if (a.track) {
+          if (a.defer) { set_flag<true>(&a.dC[d]); set_flag<true>(&a.dC[bc]); }
+          else { st_u8(&a.dC[d], 1); st_u8(&a.dC[bc], 1); }
+        }
         gsum += bg;
         mv += 1;
       }
       if (Sd >= hot) pend_add(pd, a.Sig, d, -Ki, Sd * eps);
       if (bs >= hot) pend_add(pd, a.Sig, bc, Ki, bs * eps);
       if (lane() == k) dv = bc;
-      mark_edges(a.U, a.idx, i, e0, e1, eb);
+      if (a.defer) mark_edges<true>(a.U, a.idx, i, e0, e1, eb);
+      else mark_edges<false>(a.U, a.idx, i, e0, e1, eb);
       // the move may have marked later vertices of the chunk unprocessed
       wave_fence();
       m = __ballot(lane() > k && elig && ld_u8(&a.U[v]));
