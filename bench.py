@@ -64,6 +64,7 @@ BYTES_PER_UNIT = {  # (per entry, per vertex)
     "mod_scan": (12.0, 0.0),
     "batch_merge": (16.0, 16.0),
     "move_sweep": (12.0, 34.0),
+    "refine_sweep": (16.0, 45.0),
 }
 PROF_KERNEL_NAMES = {  # symbol of each timed kernel, as rocprofv3 lists it
     "hub_gather": "lk::k_hub_gather(lk::MoveArgs)",
@@ -71,6 +72,7 @@ PROF_KERNEL_NAMES = {  # symbol of each timed kernel, as rocprofv3 lists it
     "mod_scan": "lk::k_mod_intra",
     "batch_merge": "lk::k_batch_apply_old(lk::BatchArgs)",
     "move_sweep": "lk::k_move_async",  # both launch shapes, <4, 512> and <2, 2048>
+    "refine_sweep": "lk::k_refine_async",
 }
 
 

@@ -120,14 +120,17 @@ typedef struct {
  *   BATCH_MERGE - graph update merge of the old rows with the batch;
  *                 entries = CSR entries of G^t, vertices = n;
  *   MOVE_SWEEP  - asynchronous local-moving sweep, one launch per iteration;
- *                 entries = edges scanned, vertices = vertices evaluated. */
+ *                 entries = edges scanned, vertices = vertices evaluated;
+ *   REFINE_SWEEP - asynchronous refinement sweep, one launch per pass;
+ *                 entries = edges scanned, vertices = candidates evaluated. */
 enum {
   LEIDEN_PROF_HUB_GATHER = 0,
   LEIDEN_PROF_AGG_MERGE = 1,
   LEIDEN_PROF_MOD_SCAN = 2,
   LEIDEN_PROF_BATCH_MERGE = 3,
   LEIDEN_PROF_MOVE_SWEEP = 4,
-  LEIDEN_PROF_N = 5
+  LEIDEN_PROF_REFINE_SWEEP = 5,
+  LEIDEN_PROF_N = 6
 };
 
 /* Per-call statistics (host struct). */

@@ -66,7 +66,7 @@ struct DevScal {
   int32_t pad;
   unsigned long long nz;
   unsigned long long hub_scanned;
-  unsigned long long sweep_work[2];
+  unsigned long long sweep_work[4];  // [vertices, edges] of the move sweeps, then of the refine sweeps
   unsigned long long anext;
 };
 
@@ -349,6 +349,8 @@ struct KProf {
     if (sweep_work) {
       st->prof_vertices[LEIDEN_PROF_MOVE_SWEEP] = (int64_t)x.read(&sweep_work[0]);
       st->prof_entries[LEIDEN_PROF_MOVE_SWEEP] = (int64_t)x.read(&sweep_work[1]);
+      st->prof_vertices[LEIDEN_PROF_REFINE_SWEEP] = (int64_t)x.read(&sweep_work[2]);
+      st->prof_entries[LEIDEN_PROF_REFINE_SWEEP] = (int64_t)x.read(&sweep_work[3]);
     }
   }
 };
@@ -574,6 +576,9 @@ Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, i
   int64_t *seg = nullptr;
   int32_t *lc = nullptr;
   int64_t *lsb = nullptr;
+  int32_t *tseg = nullptr;  // large segments' input tiles: owning segment, first tile per segment
+  int64_t *ltn = nullptr;
+  int64_t ntl = 0;
   uint32_t *ukey = nullptr, *lkey = nullptr;
   float *uval = nullptr, *lval = nullptr;
   if (g.nnz > 0) {
@@ -616,11 +621,11 @@ Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, i
       lc = x.get<int32_t>(A_lc, nl);
       lsb = x.get<int64_t>(A_lsb, nl);
       int64_t *lse = x.get<int64_t>(A_lse, nl);
-      int64_t *ltn = x.get<int64_t>(A_ltn, nl + 1);
+      ltn = x.get<int64_t>(A_ltn, nl + 1);
       agg_large_list(seg, ncomm, lflag, lidx, lc, lsb, lse, ltn, x.s);
       scan_i64(x, ltn, ltn, nl + 1);
-      const int64_t ntl = x.read(&ltn[nl]);
-      int32_t *tseg = x.get<int32_t>(A_tseg, ntl);
+      ntl = x.read(&ltn[nl]);
+      tseg = x.get<int32_t>(A_tseg, ntl);
       agg_tile_seg(ltn, nl, tseg, x.s);
       RsSeg rs;
       rs.ntiles = ntl;
@@ -651,7 +656,8 @@ Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, i
   const int64_t nu = g.nnz > 0 ? x.read(&out_off[ncomm]) : 0;
   int32_t *out_idx = x.get<int32_t>(si, nu);
   float *out_w = x.get<float>(sw, nu);
-  if (g.nnz > 0) agg_compact(seg, ncomm, lc, lsb, nl, rowlen, out_off, ukey, uval, lkey, lval, out_idx, out_w, x.s);
+  if (g.nnz > 0)
+    agg_compact(seg, ncomm, lc, lsb, tseg, ltn, ntl, rowlen, out_off, ukey, uval, lkey, lval, out_idx, out_w, x.s);
   int32_t *out_crow = x.get<int32_t>(sc, ceil_div(std::max<int64_t>(nu, 1), kChunk) + 2);
   chunk_start_rows(out_off, ncomm, nu, out_crow, x.s);
   x.launched("agg_rows");
@@ -856,6 +862,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     ra.hubdeg = hubdeg;
     ra.cached = async && nl >= kCachedLevel;
     ra.defer = async && NW > 1;
+    ra.sweep_work = x.kp && x.kp->on ? sc->sweep_work + 2 : nullptr;
     reset_iter(counts, NS * kNB, nullptr, &sc->refined, async ? &sc->anext : nullptr, x.s);
     refine_break(ra, x.s);
     x.launched("break");
@@ -882,7 +889,9 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
       refine_accept(ra, B.region.data(), x.s);
     }
     if (async) {
+      hipEvent_t t0 = x.kp ? x.kp->begin() : nullptr;
       refine_async(ra, level_waves(p, NW, alen, pass), wide_tables(g.nnz, alen), x.s);
+      if (x.kp) x.kp->end(t0, LEIDEN_PROF_REFINE_SWEEP, 0, 0);
     }
     x.launched("refine sweep");
     const int rounds = 1;
@@ -1293,7 +1302,7 @@ leiden_status leiden_static(leiden_handle *h, int32_t *membership_out, double *q
     x.kp = &kp;
     if (kp.on) {
       x.zero(&x.scal()->hub_scanned, 1);
-      x.zero(x.scal()->sweep_work, 2);
+      x.zero(x.scal()->sweep_work, 4);
     }
     tm.mark(CAT_OTHER);
     const int64_t n = h->n;
@@ -1353,7 +1362,7 @@ leiden_status leiden_update(leiden_handle *h, const leiden_batch *batch, int32_t
     x.kp = &kp;
     if (kp.on) {
       x.zero(&x.scal()->hub_scanned, 1);
-      x.zero(x.scal()->sweep_work, 2);
+      x.zero(x.scal()->sweep_work, 4);
     }
     tm.mark(CAT_OTHER);
     const int64_t n = h->n;

@@ -127,7 +127,8 @@ void agg_group(const AggArgs &a, const int32_t *crow, const int32_t *pos, const 
 
 // ---- 4: small segments -------------------------------------------------------
 // A wavefront per segment of at most kAggSmall entries (the wavefronts take
-// 64 communities at a time): up to 64 entries are sorted in registers with a
+// 64 communities at a time, spread over the whole id range, since costly
+// segments cluster in id order): up to 64 entries are sorted in registers with a
 // bitonic network over the lanes, larger ones in the wavefront's LDS area.
 // The network is data-oblivious and exchanges only strictly ordered pairs,
 // so equal keys end in an order fixed by the input.  Runs of equal keys are
@@ -287,9 +288,11 @@ __global__ __launch_bounds__(256) void k_agg_small(const int64_t *seg, int64_t n
   __shared__ uint32_t sk[W][kAggSmall];
   __shared__ float sv[W][kAggSmall];
   const int wid = (int)threadIdx.x / kWave;
-  const int64_t stride = (int64_t)gridDim.x * W * kWave;
-  for (int64_t c0 = ((int64_t)blockIdx.x * W + wid) * kWave; c0 < ncomm; c0 += stride) {
-    const int64_t c = c0 + lane();
+  // round r, wavefront w, lane q: community r * 64 * nw + q * nw + w
+  const int64_t nw = (int64_t)gridDim.x * W;
+  const int64_t w = (int64_t)blockIdx.x * W + wid;
+  for (int64_t base = 0; base < ncomm; base += nw * kWave) {
+    const int64_t c = base + (int64_t)lane() * nw + w;
     int64_t b = 0, len = 0;
     if (c < ncomm) {
       b = seg[c];
@@ -301,8 +304,9 @@ __global__ __launch_bounds__(256) void k_agg_small(const int64_t *seg, int64_t n
       todo &= todo - 1ull;
       const int64_t sb = __shfl(b, k);
       const int sl = (int)__shfl(len, k);
-      if (sl <= kWave) small_regs(gkey, gval, sb, sl, (int)(c0 + k), ukey, uval, rowlen, K);
-      else small_lds(gkey, gval, sb, sl, (int)(c0 + k), sk[wid], sv[wid], ukey, uval, rowlen, K);
+      const int ck = (int)__shfl(c, k);
+      if (sl <= kWave) small_regs(gkey, gval, sb, sl, ck, ukey, uval, rowlen, K);
+      else small_lds(gkey, gval, sb, sl, ck, sk[wid], sv[wid], ukey, uval, rowlen, K);
     }
   }
 }
@@ -506,26 +510,35 @@ __global__ __launch_bounds__(256) void k_agg_csmall(const int64_t *seg, int64_t 
     }
   }
 }
-__global__ __launch_bounds__(256) void k_agg_clarge(const int32_t *lc, const int64_t *lsb, const int32_t *rowlen,
+// One workgroup per input tile of the large segments: tile k of segment l
+// copies row entries [k * kPTile, (k + 1) * kPTile) of the segment's row (a
+// row is never longer than its segment, so the tiles cover it and no
+// workgroup copies more than one tile's worth, however large the segment).
+__global__ __launch_bounds__(256) void k_agg_clarge(const int32_t *lc, const int64_t *lsb, const int32_t *tseg,
+                                                    const int64_t *tfirst, const int32_t *rowlen,
                                                     const int64_t *out_off, const uint32_t *ukey, const float *uval,
                                                     int32_t *out_idx, float *out_w) {
-  const int64_t l = blockIdx.x;
+  const int64_t t = blockIdx.x;
+  const int l = tseg[t];
   const int c = lc[l];
   const int64_t s0 = lsb[l], d0 = out_off[c];
-  const int r = rowlen[c];
-  for (int j = threadIdx.x; j < r; j += blockDim.x) {
+  const int64_t j0 = (t - tfirst[l]) * kPTile;
+  const int64_t j1 = min(j0 + kPTile, (int64_t)rowlen[c]);
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
     out_idx[d0 + j] = (int32_t)ukey[s0 + j];
     out_w[d0 + j] = uval[s0 + j];
   }
 }
-void agg_compact(const int64_t *seg, int64_t ncomm, const int32_t *lc, const int64_t *lsb, int64_t nl,
-                 const int32_t *rowlen, const int64_t *out_off, const uint32_t *ukey, const float *uval,
-                 const uint32_t *lkey, const float *lval, int32_t *out_idx, float *out_w, hipStream_t s) {
+void agg_compact(const int64_t *seg, int64_t ncomm, const int32_t *lc, const int64_t *lsb, const int32_t *tseg,
+                 const int64_t *tfirst, int64_t ntl, const int32_t *rowlen, const int64_t *out_off,
+                 const uint32_t *ukey, const float *uval, const uint32_t *lkey, const float *lval, int32_t *out_idx,
+                 float *out_w, hipStream_t s) {
   if (ncomm > 0)
     hipLaunchKernelGGL(k_agg_csmall, flat_grid(ncomm, 256, 8192), 256, 0, s, seg, ncomm, rowlen, out_off, ukey, uval,
                        out_idx, out_w);
-  if (nl > 0)
-    hipLaunchKernelGGL(k_agg_clarge, (int)nl, 256, 0, s, lc, lsb, rowlen, out_off, lkey, lval, out_idx, out_w);
+  if (ntl > 0)
+    hipLaunchKernelGGL(k_agg_clarge, (int)ntl, 256, 0, s, lc, lsb, tseg, tfirst, rowlen, out_off, lkey, lval,
+                       out_idx, out_w);
 }
 
 }  // namespace lk

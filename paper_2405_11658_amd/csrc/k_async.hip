@@ -585,6 +585,7 @@ __global__ __launch_bounds__(256) void k_refine_async(RefineArgs a) {
   Pend &pd = lds[wv].pend;
   const double hot = a.defer ? a.M2 * kHotShare : __builtin_inf();
   const double eps = kHotEps / ((double)gridDim.x * (blockDim.x / kWave));
+  unsigned long long nv = 0, ne = 0;  // candidate evaluations, edges scanned
   Grab gr;
   for (;;) {
     if (gr.left == 0) pend_flush(pd, a.Sig);
@@ -623,6 +624,8 @@ __global__ __launch_bounds__(256) void k_refine_async(RefineArgs a) {
       // staying alone.  Alone (one wavefront) this never happens: a table
       // only holds communities that have members.
       for (int attempt = 0; attempt < kRefineTries; ++attempt) {
+        nv += 1;
+        ne += (unsigned long long)(e1 - e0);
         EdgeBatch eb;
         batch_ids(eb, a.idx, a.w, i, e0, e1);
         batch_comms_packed<CA>(eb, a.CP, cb, i);
@@ -674,6 +677,10 @@ __global__ __launch_bounds__(256) void k_refine_async(RefineArgs a) {
     }
   }
   pend_flush(pd, a.Sig);
+  if (lane() == 0 && a.sweep_work && nv) {
+    atomicAdd(&a.sweep_work[0], nv);
+    atomicAdd(&a.sweep_work[1], ne);
+  }
 }
 
 __global__ void k_pack_cb(const int32_t *C, const int32_t *CB, int64_t n, unsigned long long *CP) {

@@ -237,6 +237,7 @@ struct RefineArgs {
   unsigned long long *CP;   // asynchronous sweep: CB << 32 | C per vertex, kept with C
   int32_t cached;           // asynchronous sweep: cache-served reads (large levels)
   int32_t defer;            // asynchronous sweep: batch the joins of popular communities
+  unsigned long long *sweep_work;  // nullable: [candidates evaluated, edges scanned] by the async sweep
   const double *K;
   double *Sig;
   const uint8_t *dC;
@@ -305,8 +306,8 @@ void agg_large_runs(int pass, const uint32_t *gkey, const float *gval, const RsS
 void agg_large_rows(int64_t nl, const int32_t *lc, const int64_t *tfirst, const int64_t *hc, const double *tks,
                     int32_t *rowlen, double *K, hipStream_t s);
 // rows of the small segments from (ukey, uval), of the large ones from (lkey, lval)
-void agg_compact(const int64_t *seg, int64_t ncomm, const int32_t *lc, const int64_t *lsb, int64_t nl,
-                 const int32_t *rowlen, const int64_t *out_off, const uint32_t *ukey, const float *uval,
+void agg_compact(const int64_t *seg, int64_t ncomm, const int32_t *lc, const int64_t *lsb, const int32_t *tseg,
+                 const int64_t *tfirst, int64_t ntl, const int32_t *rowlen, const int64_t *out_off, const uint32_t *ukey, const float *uval,
                  const uint32_t *lkey, const float *lval, int32_t *out_idx, float *out_w, hipStream_t s);
 
 // ---- k_modularity.hip --------------------------------------------------------

@@ -33,7 +33,7 @@ class LeidenError(RuntimeError):
 
 
 # kernels timed with leiden_params.profile = 1, in LEIDEN_PROF_* order
-PROF_KERNELS = ("hub_gather", "agg_merge", "mod_scan", "batch_merge", "move_sweep")
+PROF_KERNELS = ("hub_gather", "agg_merge", "mod_scan", "batch_merge", "move_sweep", "refine_sweep")
 PROF_N = len(PROF_KERNELS)
 
 
