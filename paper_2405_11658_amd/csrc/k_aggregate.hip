@@ -129,7 +129,9 @@ void agg_group(const AggArgs &a, const int32_t *crow, const int32_t *pos, const 
 // A wavefront per segment of at most kAggSmall entries (the wavefronts take
 // 64 communities at a time, spread over the whole id range, since costly
 // segments cluster in id order): up to 64 entries are sorted in registers with a
-// bitonic network over the lanes, larger ones in the wavefront's LDS area.
+// bitonic network over the lanes, up to 256 with the same network over R = 2
+// or 4 registers per lane, larger ones (up to 1024) in the wavefront's LDS
+// area (more registers per lane would spill).
 // The network is data-oblivious and exchanges only strictly ordered pairs,
 // so equal keys end in an order fixed by the input.  Runs of equal keys are
 // summed with a segmented scan (fixed tree), each run written at its rank in
@@ -222,6 +224,130 @@ __device__ __forceinline__ void small_regs(const uint32_t *gkey, const float *gv
   }
 }
 
+// One exchange step (block size K, distance J) of the bitonic network over
+// the blocked layout of small_wide, then the following steps of the block.
+template <int R, int K, int J>
+__device__ __forceinline__ void bitonic_step(uint32_t (&key)[R], float (&v)[R]) {
+  if constexpr (J >= R) {
+    constexpr int LJ = J / R;
+    const bool low = (lane() & LJ) == 0;
+    const bool up = ((lane() * R) & K) == 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t ok = __shfl_xor(key[r], LJ);
+      const float ov = __shfl_xor(v[r], LJ);
+      const bool take = (low == up) ? ok < key[r] : ok > key[r];
+      if (take) {
+        key[r] = ok;
+        v[r] = ov;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (r & J) continue;
+      const int q = r | J;
+      const bool up = K < R ? (r & K) == 0 : ((lane() * R) & K) == 0;
+      if (up ? key[r] > key[q] : key[r] < key[q]) {
+        const uint32_t tk = key[r];
+        key[r] = key[q];
+        key[q] = tk;
+        const float tv = v[r];
+        v[r] = v[q];
+        v[q] = tv;
+      }
+    }
+  }
+  if constexpr (J > 1) bitonic_step<R, K, J / 2>(key, v);
+}
+// Blocks of size K, 2K, ... up to the whole 64 * R positions.
+template <int R, int K>
+__device__ __forceinline__ void bitonic_regs(uint32_t (&key)[R], float (&v)[R]) {
+  bitonic_step<R, K, K / 2>(key, v);
+  if constexpr (K < kWave * R) bitonic_regs<R, 2 * K>(key, v);
+}
+
+// Segments of 65 .. 64 * R entries in registers: lane L holds the R
+// consecutive positions L * R .. L * R + R - 1 (keys padded with kKeyPad).
+// The bitonic network's exchanges at distance j < R stay inside a lane (the
+// register indices are compile-time constants once the loops are unrolled);
+// at distance j >= R the partner is lane L ^ (j / R), same register.  As
+// above, only strictly ordered pairs are exchanged.  The runs are then
+// summed in position order: each lane in order over its registers, the run
+// open at a lane's start taken from the lanes before it by a segmented scan
+// over the lanes (fixed tree).
+template <int R>
+__device__ __forceinline__ void small_wide(const uint32_t *gkey, const float *gval, int64_t sb, int sl, int c,
+                                           uint32_t *ukey, float *uval, int32_t *rowlen, double *K) {
+  uint32_t key[R];
+  float v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int e = lane() * R + r;
+    key[r] = kKeyPad;
+    v[r] = 0.0f;
+    if (e < sl) {
+      key[r] = gkey[sb + e];
+      v[r] = gval[sb + e];
+    }
+  }
+  bitonic_regs<R, 2>(key, v);
+  // heads and run ends; position e = lane * R + r is valid below sl
+  const uint32_t prevk = __shfl_up(key[R - 1], 1);
+  const uint32_t nextk = __shfl_down(key[0], 1);
+  bool head[R], rend[R];
+  int nh = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int e = lane() * R + r;
+    const bool act = e < sl;
+    const uint32_t pk = r == 0 ? prevk : key[r - 1];
+    const uint32_t nk = r == R - 1 ? nextk : key[r + 1];
+    head[r] = act && (e == 0 || pk != key[r]);
+    rend[r] = act && (e == sl - 1 || nk != key[r]);
+    nh += head[r] ? 1 : 0;
+  }
+  // the lane's open run: sum after its last head (all of it without a head)
+  double tail = 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const double x = lane() * R + r < sl ? (double)v[r] : 0.0;
+    tail = head[r] ? x : tail + x;
+  }
+  double t = tail;
+  int f = nh > 0 ? 1 : 0;
+  seg_scan(t, f);  // t: run open at the end of this lane
+  double carry = __shfl_up(t, 1);
+  if (lane() == 0) carry = 0.0;
+  // ranks: heads before this lane, then in register order
+  int hb = nh;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(hb, o);
+    if (lane() >= o) hb += y;
+  }
+  const int total = __shfl(hb, kWave - 1);
+  hb -= nh;
+  double acc = carry, kx = 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const double x = lane() * R + r < sl ? (double)v[r] : 0.0;
+    acc = head[r] ? x : acc + x;
+    hb += head[r] ? 1 : 0;
+    if (rend[r]) {
+      const float wf = (float)acc;
+      ukey[sb + hb - 1] = key[r];
+      uval[sb + hb - 1] = wf;
+      kx += (double)wf;
+    }
+  }
+  kx = group_sum<kWave>(kx);
+  if (lane() == 0) {
+    rowlen[c] = total;
+    if (K) K[c] = kx;
+  }
+}
+
 __device__ __forceinline__ void small_lds(const uint32_t *gkey, const float *gval, int64_t sb, int sl, int c,
                                           uint32_t *sk, float *sv, uint32_t *ukey, float *uval, int32_t *rowlen,
                                           double *K) {
@@ -235,9 +361,11 @@ __device__ __forceinline__ void small_lds(const uint32_t *gkey, const float *gva
   wave_lds_fence();
   for (int k = 2; k <= P; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = lane(); i < P; i += kWave) {
-        const int ix = i ^ j;
-        if (ix <= i) continue;
+      // pair p: lower position i (bit j clear), upper i + j; every lane
+      // takes a pair in every round
+      for (int p = lane(); p < P / 2; p += kWave) {
+        const int i = ((p & ~(j - 1)) << 1) | (p & (j - 1));
+        const int ix = i + j;
         const uint32_t a = sk[i], b = sk[ix];
         const bool up = (i & k) == 0;
         if (up ? a > b : a < b) {
@@ -306,6 +434,8 @@ __global__ __launch_bounds__(256) void k_agg_small(const int64_t *seg, int64_t n
       const int sl = (int)__shfl(len, k);
       const int ck = (int)__shfl(c, k);
       if (sl <= kWave) small_regs(gkey, gval, sb, sl, ck, ukey, uval, rowlen, K);
+      else if (sl <= 2 * kWave) small_wide<2>(gkey, gval, sb, sl, ck, ukey, uval, rowlen, K);
+      else if (sl <= 4 * kWave) small_wide<4>(gkey, gval, sb, sl, ck, ukey, uval, rowlen, K);
       else small_lds(gkey, gval, sb, sl, ck, sk[wid], sv[wid], ukey, uval, rowlen, K);
     }
   }

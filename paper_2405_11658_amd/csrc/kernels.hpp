@@ -289,7 +289,7 @@ struct AggArgs {
   const float *w;
   const int32_t *C;
 };
-constexpr int kAggSmall = 1024;  // segments up to this many entries are sorted in LDS
+constexpr int kAggSmall = 1024;  // segments up to this many entries are sorted by one wavefront
 void agg_vkeys(int64_t n, const int32_t *C, uint32_t *keys, int32_t *vals, hipStream_t s);
 void agg_vdeg(int64_t n, const int64_t *off, const int32_t *vs, int64_t *deg, int32_t *pos, hipStream_t s);
 void agg_cdeg(int64_t n, const uint32_t *Cs, const int64_t *eoff, int64_t *hpos, int64_t *cdeg, hipStream_t s);
