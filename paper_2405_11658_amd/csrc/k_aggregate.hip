@@ -497,89 +497,129 @@ void agg_tile_seg(const int64_t *tfirst, int64_t nl, int32_t *tseg, hipStream_t 
 template <int PASS>
 __global__ __launch_bounds__(256) void k_agg_lruns(const uint32_t *gkey, const float *gval, RsSeg g, int64_t *hc,
                                                    double *tin, uint32_t *ukey, float *uval, double *tks) {
-  __shared__ double wv[4];
-  __shared__ int wf[4];
-  __shared__ int sw[16];
-  __shared__ double cvv;
-  __shared__ int cff;
+  // The tile is loaded with coalesced loads into LDS (one pad word per kPR
+  // items, so that each thread then reads its kPR consecutive items without
+  // bank conflicts) and scanned in one round: each thread sums its items in
+  // order, the threads' open runs are joined by a segmented scan over the
+  // block (fixed tree), and heads are counted the same way.
+  constexpr int E = kPR;
+  constexpr int W = 256 / kWave;
+  __shared__ uint32_t sk[kPTile + kPTile / E];
+  __shared__ float sv[kPTile + kPTile / E];
+  __shared__ double wx[W];
+  __shared__ int wfl[W], wh[W];
+  __shared__ uint32_t edge[2];
   const int64_t t = blockIdx.x;
   const TileSpan ts = tile_span(g, t);
   const int64_t se = g.send[g.tseg[t]];
-  if (PASS == 0 && threadIdx.x == 0) tin[t] = 0.0;
-  if (threadIdx.x == 0) { cvv = 0.0; cff = 0; }
-  __syncthreads();
-  const int wid = (int)threadIdx.x / kWave;
-  int heads = 0;  // heads in earlier rounds
-  double kacc = 0.0;  // this thread's stored run weights (pass 1)
-  const int64_t base_rank = PASS == 1 ? hc[t] - hc[ts.f0] : 0;
-  for (int64_t b = ts.lo; b < ts.hi; b += blockDim.x) {
-    const int64_t p = b + threadIdx.x;
-    const bool act = p < ts.hi;
-    uint32_t key = 0;
-    double v = 0.0;
-    bool head = false, rend = false;
-    if (act) {
-      key = gkey[p];
-      v = (double)gval[p];
-      head = p == ts.sb || gkey[p - 1] != key;
-      rend = p + 1 == se || gkey[p + 1] != key;
-    }
-    // segmented inclusive scan: wavefront, then the earlier wavefronts and rounds
-    double x = v;
-    int f = head ? 1 : 0;
+  const int n = (int)(ts.hi - ts.lo);
+  const int tid = (int)threadIdx.x, wid = tid / kWave;
+  if (PASS == 0 && tid == 0) tin[t] = 0.0;
 #pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      const double yx = __shfl_up(x, o);
-      const int yf = __shfl_up(f, o);
-      if (lane() >= o) {
-        if (!f) x += yx;
-        f |= yf;
-      }
+  for (int r = 0; r < E; ++r) {
+    const int e = r * 256 + tid;
+    if (e < n) {
+      sk[e + e / E] = gkey[ts.lo + e];
+      sv[e + e / E] = gval[ts.lo + e];
     }
-    if (lane() == kWave - 1) { wv[wid] = x; wf[wid] = f; }
-    int ht;
-    const int hx = blk_excl_int(head ? 1 : 0, &ht, sw);  // has a barrier after the stores above
-    double ax = cvv;
-    int af = cff;
-    for (int k = 0; k < wid; ++k) {
-      if (!wf[k]) ax += wv[k];
-      else ax = wv[k];
-      af |= wf[k];
+  }
+  if (tid == 0) {
+    edge[0] = ts.lo > ts.sb ? gkey[ts.lo - 1] : 0u;  // compared only inside a segment
+    edge[1] = ts.hi < se ? gkey[ts.hi] : 0u;
+  }
+  __syncthreads();
+  const int e0 = tid * E;
+  uint32_t key[E];
+  double v[E];
+  bool head[E], rend[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int e = e0 + r;
+    key[r] = e < n ? sk[e + tid] : 0u;
+    v[r] = e < n ? (double)sv[e + tid] : 0.0;
+  }
+  const uint32_t before = e0 == 0 ? edge[0] : sk[(e0 - 1) + (e0 - 1) / E];
+  const uint32_t after = e0 + E < n ? sk[(e0 + E) + (e0 + E) / E] : edge[1];
+  int nh = 0;
+  double tail = 0.0;
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int e = e0 + r;
+    const bool act = e < n;
+    const int64_t p = ts.lo + e;
+    const uint32_t pk = r == 0 ? before : key[r - 1];
+    const uint32_t nk = r == E - 1 ? after : key[r + 1];
+    head[r] = act && (p == ts.sb || pk != key[r]);
+    rend[r] = act && (p + 1 == se || nk != key[r]);
+    nh += head[r] ? 1 : 0;
+    tail = head[r] ? v[r] : tail + v[r];
+  }
+  // open run at the end of each thread (inclusive), then exclusive carries
+  double x = tail;
+  int f = nh > 0 ? 1 : 0;
+  seg_scan(x, f);
+  int hi = nh;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(hi, o);
+    if (lane() >= o) hi += y;
+  }
+  if (lane() == kWave - 1) {
+    wx[wid] = x;
+    wfl[wid] = f;
+    wh[wid] = hi;
+  }
+  __syncthreads();
+  double ax = 0.0;
+  int hw = 0, ht = 0;
+  for (int k = 0; k < W; ++k) {
+    if (k < wid) {
+      ax = wfl[k] ? wx[k] : ax + wx[k];
+      hw += wh[k];
     }
-    if (!f) x += ax;
-    f |= af;
-    const int seen = heads + hx + (head ? 1 : 0);  // heads up to and including p in this tile
-    if (act && (rend || p == ts.hi - 1)) {
+    ht += wh[k];
+  }
+  double carry = __shfl_up(x, 1);
+  const int fprev = __shfl_up(f, 1);
+  if (lane() == 0) carry = ax;
+  else if (!fprev) carry += ax;
+  if (tid == 0) carry = 0.0;
+  int seen = hw + hi - nh;  // heads before this thread's items
+  double acc = carry, kacc = 0.0;
+  const int64_t base_rank = PASS == 1 ? hc[t] - hc[ts.f0] : 0;
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int e = e0 + r;
+    acc = head[r] ? v[r] : acc + v[r];
+    seen += head[r] ? 1 : 0;
+    if (e < n && (rend[r] || e == n - 1)) {
       if (seen == 0) {
-        if (PASS == 0) tin[t] = x;  // the leading piece ends here
+        if (PASS == 0) tin[t] = acc;  // the leading piece ends here
       } else if (PASS == 1) {
-        double sum = x;
-        if (!rend) {
+        double sum = acc;
+        if (!rend[r]) {
           // the run goes on past this tile: add the leading pieces it covers
           for (int64_t u = t + 1; u < ts.f0 + ts.nt; ++u) {
             sum += tin[u];
             if (hc[u + 1] - hc[u] > 0) break;
           }
         }
-        const int64_t r = base_rank + seen - 1;
+        const int64_t rk = base_rank + seen - 1;
         const float wf = (float)sum;
-        ukey[ts.sb + r] = key;
-        uval[ts.sb + r] = wf;
+        ukey[ts.sb + rk] = key[r];
+        uval[ts.sb + rk] = wf;
         kacc += (double)wf;
       }
     }
-    __syncthreads();
-    if (threadIdx.x == blockDim.x - 1) { cvv = x; cff = f; }
-    heads += ht;
-    __syncthreads();
   }
-  if (PASS == 0 && threadIdx.x == 0) hc[t] = heads;
+  if (PASS == 0 && tid == 0) hc[t] = ht;
   if (PASS == 1 && tks) {
     // the tile's part of K', summed in a fixed order
     kacc = group_sum<kWave>(kacc);
-    if (lane() == 0) wv[wid] = kacc;
+    __syncthreads();  // wx is reused
+    if (lane() == 0) wx[wid] = kacc;
     __syncthreads();
-    if (threadIdx.x == 0) tks[t] = ((wv[0] + wv[1]) + wv[2]) + wv[3];
+    if (tid == 0) tks[t] = ((wx[0] + wx[1]) + wx[2]) + wx[3];
   }
 }
 void agg_large_runs(int pass, const uint32_t *gkey, const float *gval, const RsSeg &g, int64_t *hc, double *tin,
