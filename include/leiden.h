@@ -69,7 +69,7 @@ typedef enum { LEIDEN_ND = 1, LEIDEN_DS = 2, LEIDEN_DF = 3 } leiden_mode;
  * values: tau0 = 0.01, tol_drop = 10, max_iter = 20; max_passes = 10 (not
  * stated in the paper); agg_tol = 1.0 (aggregation never skipped, Sec. 4.6).
  * sync_mode = 0 (default): asynchronous local moving and refinement as in
- * Sec. 4.6 - up to async_waves wavefronts (0 = 2048; at most one per 1024
+ * Sec. 4.6 - up to async_waves wavefronts (0 = 4096; at most one per 1024
  * vertices with edges on the first level, per 256 on aggregated levels) sweep
  * the vertices in ascending id order and apply each move at once; results
  * depend on timing.

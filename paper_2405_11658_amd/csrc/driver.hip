@@ -150,7 +150,7 @@ constexpr int kDefaultHubDeg = 256;
 // read neighbour communities and community totals through the caches in the
 // asynchronous sweeps.
 constexpr int64_t kCachedLevel = 16 << 20;
-constexpr int kDefaultAsyncWaves = 2048;  // wavefronts of the asynchronous sweeps, at most
+constexpr int kDefaultAsyncWaves = 4096;  // wavefronts of the asynchronous sweeps, at most
 constexpr int kMaxAsyncWaves = 65536;
 constexpr int64_t kVertsPerWave = 1024;  // level-0 vertices with edges per sweeping wavefront, at least
 constexpr int64_t kVertsPerWaveUpper = 256;  // the same for the aggregated levels
