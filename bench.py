@@ -380,7 +380,8 @@ def main() -> int:
                     "entries_per_launch": round(pd["entries"] / pd["launches"]),
                     "vertices_per_launch": round(pd["vertices"] / pd["launches"]),
                     "share_of_step": round(pd["ms"] / args.steps / ms_per_step, 4)}
-    kernels = {name: {"ms_per_step": round(v["ms"] / args.steps, 3), "launches_per_step": v["launches"] / args.steps}
+    kernels = {name: {"ms_per_step": round(v["ms"] / args.steps, 3), "launches_per_step": v["launches"] / args.steps,
+                      "entries_per_step": round(v["entries"] / args.steps), "vertices_per_step": round(v["vertices"] / args.steps)}
                for name, v in prof.items() if v["launches"]}
 
     # ---- RMAT-22: GPU stream, and the oracle (cpu_baseline, same-state gap) ----
