@@ -61,7 +61,7 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_UNIT = {  # (per entry, per vertex)
     "hub_gather": (12.0, 0.0),
     "agg_merge": (12.0, 12.0),
-    "mod_scan": (12.0, 0.0),
+    "mod_scan": (16.0, 12.0),  # first aggregated level: id, FP64 weight, label; level-0 labels carried up
     "batch_merge": (16.0, 16.0),
     "move_sweep": (12.0, 34.0),
     "refine_sweep": (16.0, 45.0),
@@ -123,7 +123,8 @@ def _update_window(rows):
     if not merges:
         return None
     last = merges[-1][1]
-    ends = [r[2] for r in rows if r[0].startswith(("lk::k_mod_intra", "lk::k_mod_edges")) and r[1] > last]
+    ends = [r[2] for r in rows if r[0].startswith(("lk::k_mod_intra", "void lk::k_mod_intra", "lk::k_mod_edges"))
+            and r[1] > last]
     return merges[0][1], (ends[0] if ends else rows[-1][2]), len(merges)
 
 

@@ -33,8 +33,10 @@ enum Slot {
   // level arrays (size n of level 0)
   L_C, L_K, L_S, L_S2, L_dC, L_dC2, L_U, L_rng, L_CB, L_Ctop, L_prop, L_from, L_gp, L_gi, L_Sz,
   L_rep, L_lists, L_region, L_tiles, L_flags, L_map, L_scnt, L_vbs, L_soff, L_sfill, L_CP,
-  // level graphs (ping-pong)
-  G0_off, G0_idx, G0_w, G0_crow, G1_off, G1_idx, G1_w, G1_crow,
+  // level graphs (ping-pong), and the first aggregated level kept for the
+  // modularity of the result (with its FP64 weights and the level-0 map)
+  G0_off, G0_idx, G0_w, G0_crow, G1_off, G1_idx, G1_w, G1_crow, L1_off, L1_idx, L1_w, L1_crow, L1_w64,
+  L1_map, L1_lab, A_v64,
   // aggregation
   A_vk, A_vk2, A_vv, A_vv2, A_eoff, A_pos, A_seg, A_hpos, A_gkey, A_gval, A_ukey, A_uval, A_lflag,
   A_lidx, A_lc, A_lsb, A_lse, A_ltn, A_tseg, A_hc, A_tin, A_rowlen,
@@ -554,8 +556,11 @@ int64_t renumber_dense(Ctx &x, int32_t *C, int64_t n, int64_t bound) {
 // Alg. "leidenAggregate": level g with dense labels C (< ncomm) -> out level.
 // Entries grouped by the community of their source (vertices in community
 // order), each community's group sorted by neighbour community and summed:
-// rows come out sorted by id, with FP64 sums rounded to float32.
-Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, int outbuf, double *Kout) {
+// rows come out sorted by id, with FP64 sums rounded to float32.  outbuf 0
+// and 1 are the ping-pong level graphs, 2 the kept first level; with w64 the
+// rows' FP64 sums are kept too (*w64, one per stored entry).
+Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, int outbuf, double *Kout,
+                      double **w64 = nullptr) {
   AggArgs a;
   memset(&a, 0, sizeof(a));
   a.n = g.n;
@@ -565,8 +570,11 @@ Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, i
   a.idx = g.idx;
   a.w = g.w;
   a.C = C;
-  const Slot so = outbuf ? G1_off : G0_off, si = outbuf ? G1_idx : G0_idx, sw = outbuf ? G1_w : G0_w,
-             sc = outbuf ? G1_crow : G0_crow;
+  const Slot so = outbuf == 2 ? L1_off : outbuf ? G1_off : G0_off;
+  const Slot si = outbuf == 2 ? L1_idx : outbuf ? G1_idx : G0_idx;
+  const Slot sw = outbuf == 2 ? L1_w : outbuf ? G1_w : G0_w;
+  const Slot sc = outbuf == 2 ? L1_crow : outbuf ? G1_crow : G0_crow;
+  double *v64 = (w64 && g.nnz > 0) ? x.get<double>(A_v64, g.nnz) : nullptr;
   int64_t *out_off = x.get<int64_t>(so, ncomm + 1);
   int32_t *rowlen = x.get<int32_t>(A_rowlen, ncomm + 1);
   x.zero(rowlen, ncomm + 1);
@@ -610,7 +618,7 @@ Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, i
     uval = x.get<float>(A_uval, nnz);
     agg_group(a, g.crow, pos, eoff, gkey, gval, x.s);
     // 4. small segments
-    agg_small(seg, ncomm, gkey, gval, ukey, uval, rowlen, Kout, x.s);
+    agg_small(seg, ncomm, gkey, gval, ukey, uval, v64, rowlen, Kout, x.s);
     // 5. large segments
     int32_t *lflag = x.get<int32_t>(A_lflag, ncomm + 1);
     int32_t *lidx = x.get<int32_t>(A_lidx, ncomm + 1);
@@ -644,9 +652,9 @@ Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, i
       double *tin = x.get<double>(A_tin, 2 * ntl);
       double *tks = tin + ntl;
       x.zero(hc, ntl + 1);
-      agg_large_runs(0, skey, sval, rs, hc, tin, lkey, lval, nullptr, x.s);
+      agg_large_runs(0, skey, sval, rs, hc, tin, lkey, lval, nullptr, nullptr, x.s);
       scan_i64(x, hc, hc, ntl + 1);
-      agg_large_runs(1, skey, sval, rs, hc, tin, lkey, lval, Kout ? tks : nullptr, x.s);
+      agg_large_runs(1, skey, sval, rs, hc, tin, lkey, lval, v64, Kout ? tks : nullptr, x.s);
       agg_large_rows(nl, lc, ltn, hc, tks, rowlen, Kout, x.s);
     }
     if (x.kp) x.kp->end(t0, LEIDEN_PROF_AGG_MERGE, g.nnz, g.n);
@@ -656,8 +664,11 @@ Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, i
   const int64_t nu = g.nnz > 0 ? x.read(&out_off[ncomm]) : 0;
   int32_t *out_idx = x.get<int32_t>(si, nu);
   float *out_w = x.get<float>(sw, nu);
+  double *out_w64 = v64 ? x.get<double>(L1_w64, nu) : nullptr;
+  if (w64) *w64 = out_w64;
   if (g.nnz > 0)
-    agg_compact(seg, ncomm, lc, lsb, tseg, ltn, ntl, rowlen, out_off, ukey, uval, lkey, lval, out_idx, out_w, x.s);
+    agg_compact(seg, ncomm, lc, lsb, tseg, ltn, ntl, rowlen, out_off, ukey, uval, lkey, lval, v64, out_idx, out_w,
+                out_w64, x.s);
   int32_t *out_crow = x.get<int32_t>(sc, ceil_div(std::max<int64_t>(nu, 1), kChunk) + 2);
   chunk_start_rows(out_off, ncomm, nu, out_crow, x.s);
   x.launched("agg_rows");
@@ -665,12 +676,46 @@ Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, i
   return o;
 }
 
+// The first aggregated level of a run, kept for the modularity of its result:
+// every level-0 vertex of one first-level vertex (a refined community of the
+// first pass) ends in the same community, so the internal weight of the
+// result is the weight of the first level's entries inside communities,
+// summed from their FP64 run sums (exact for these sums of float weights, up
+// to the order of the final additions), over ~1/7 of the entries on RMAT.
+struct Level1 {
+  bool ok = false;
+  Level g{};
+  const double *w64 = nullptr;
+  const int32_t *map = nullptr;  // level-0 vertex -> first-level vertex
+};
+
+// modularity_known from the first aggregated level: the result's labels
+// (C, n level-0 entries) carried to the first-level vertices, then one pass
+// over the first level's entries with their FP64 weights.
+double modularity_level1(Ctx &x, const Level1 &l1, const int32_t *C, int64_t n, const double *Sig, double M2) {
+  if (!(M2 > 0.0)) return 0.0;
+  DevScal *sc = x.scal();
+  x.zero(sc->acc, 4);
+  hipEvent_t t0 = x.kp ? x.kp->begin() : nullptr;
+  int32_t *lab = x.get<int32_t>(L1_lab, l1.g.n);
+  scatter_labels(l1.map, C, n, lab, x.s);
+  modularity_intra64(l1.g.off, l1.g.idx, l1.w64, l1.g.crow, l1.g.nnz, lab, sc->acc, x.s);
+  if (x.kp) x.kp->end(t0, LEIDEN_PROF_MOD_SCAN, l1.g.nnz, n);
+  modularity_comm_sq(Sig, n, M2, sc->acc, x.s);
+  x.launched("modularity");
+  double acc[4];
+  x.check(hipMemcpyAsync(x.pin(), sc->acc, sizeof(acc), hipMemcpyDeviceToHost, x.s), "D2H");
+  x.check(hipStreamSynchronize(x.s), "sync");
+  memcpy(acc, x.pin(), sizeof(acc));
+  return acc[0] / M2 - acc[2];
+}
+
 // The pass loop of Alg. "leiden".  On entry the level arrays hold the
 // previous membership (L_C), K (L_K), Sigma (L_S), changed flags (L_dC),
 // affected flags (L_U) and range flags (L_rng) for the level-0 graph g0.
 // On exit `out` (n) holds dense labels.
 void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool track, int32_t *out,
-              leiden_stats *st, Timer &tm) {
+              leiden_stats *st, Timer &tm, Level1 *l1 = nullptr) {
   const int64_t n = g0.n;
   DevScal *sc = x.scal();
   int32_t *C = x.get<int32_t>(L_C, n);
@@ -928,9 +973,22 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     gather_map(Ctop, C, n, x.s);  // dendrogram lookup
     x.launched("lookup");
     tm.mark(CAT_OTHER);
-    const int outbuf = (curbuf == 0) ? 1 : 0;
-    g = aggregate_level(x, g, C, ncomm, outbuf, K);
-    curbuf = outbuf;
+    if (l1 && pass == 0) {
+      // the first level with its FP64 weights and the level-0 map (C here)
+      int32_t *map = x.get<int32_t>(L1_map, n);
+      x.copy(map, C, n);
+      double *w64 = nullptr;
+      g = aggregate_level(x, g, C, ncomm, 2, K, &w64);
+      curbuf = 2;
+      l1->ok = w64 != nullptr;
+      l1->g = g;
+      l1->w64 = w64;
+      l1->map = map;
+    } else {
+      const int outbuf = (curbuf == 0) ? 1 : 0;
+      g = aggregate_level(x, g, C, ncomm, outbuf, K);
+      curbuf = outbuf;
+    }
     tm.mark(CAT_AGG);
     x.copy(S, K, ncomm);
     fill_u8(U, 1, ncomm, x.s);
@@ -1300,6 +1358,7 @@ leiden_status leiden_static(leiden_handle *h, int32_t *membership_out, double *q
     Timer tm(x, stats != nullptr);
     KProf kp(x, stats != nullptr && h->prm.profile != 0);
     x.kp = &kp;
+    Level1 l1;
     if (kp.on) {
       x.zero(&x.scal()->hub_scanned, 1);
       x.zero(x.scal()->sweep_work, 4);
@@ -1328,7 +1387,7 @@ leiden_status leiden_static(leiden_handle *h, int32_t *membership_out, double *q
       fill_u8(x.get<uint8_t>(L_U, n), 1, n, x.s);
       fill_u8(x.get<uint8_t>(L_rng, n), 1, n, x.s);
       x.launched("static init");
-      run_core(x, h->prm, g, M2, false, C, stats, tm);
+      run_core(x, h->prm, g, M2, false, C, stats, tm, q_out ? &l1 : nullptr);
       x.zero(Sig, n);
       scatter_add(K, C, n, Sig, x.s);
       x.launched("sigma");
@@ -1336,7 +1395,8 @@ leiden_status leiden_static(leiden_handle *h, int32_t *membership_out, double *q
     h->M2 = M2;
     h->has_state = true;
     if (membership_out) x.copy(membership_out, (const int32_t *)C, n);
-    if (q_out) *q_out = (n > 0) ? modularity_known(x, g, C, Sig, M2) : 0.0;
+    if (q_out)
+      *q_out = n <= 0 ? 0.0 : l1.ok ? modularity_level1(x, l1, C, n, Sig, M2) : modularity_known(x, g, C, Sig, M2);
     tm.mark(CAT_OTHER);
     tm.finish(stats);
     kp.finish(stats, kp.on ? &x.scal()->hub_scanned : nullptr, kp.on ? x.scal()->sweep_work : nullptr);
@@ -1360,6 +1420,7 @@ leiden_status leiden_update(leiden_handle *h, const leiden_batch *batch, int32_t
     Timer tm(x, stats != nullptr);
     KProf kp(x, stats != nullptr && h->prm.profile != 0);
     x.kp = &kp;
+    Level1 l1;
     if (kp.on) {
       x.zero(&x.scal()->hub_scanned, 1);
       x.zero(x.scal()->sweep_work, 4);
@@ -1403,13 +1464,16 @@ leiden_status leiden_update(leiden_handle *h, const leiden_batch *batch, int32_t
       x.copy(x.get<int32_t>(L_C, n), (const int32_t *)h->C.p, n);
       x.copy(x.get<double>(L_K, n), (const double *)h->K.p, n);
       x.copy(x.get<double>(L_S, n), (const double *)h->Sig.p, n);
-      run_core(x, h->prm, g, h->M2, true, (int32_t *)h->C.p, stats, tm);
+      run_core(x, h->prm, g, h->M2, true, (int32_t *)h->C.p, stats, tm, q_out ? &l1 : nullptr);
       x.zero((double *)h->Sig.p, n);
       scatter_add((const double *)h->K.p, (const int32_t *)h->C.p, n, (double *)h->Sig.p, x.s);
       x.launched("sigma");
     }
     if (membership_out) x.copy(membership_out, (const int32_t *)h->C.p, n);
-    if (q_out) *q_out = (n > 0) ? modularity_known(x, g, (const int32_t *)h->C.p, (const double *)h->Sig.p, h->M2) : 0.0;
+    if (q_out)
+      *q_out = n <= 0 ? 0.0
+               : l1.ok ? modularity_level1(x, l1, (const int32_t *)h->C.p, n, (const double *)h->Sig.p, h->M2)
+                       : modularity_known(x, g, (const int32_t *)h->C.p, (const double *)h->Sig.p, h->M2);
     tm.mark(CAT_OTHER);
     tm.finish(stats);
     kp.finish(stats, kp.on ? &x.scal()->hub_scanned : nullptr, kp.on ? x.scal()->sweep_work : nullptr);
@@ -1429,17 +1493,19 @@ leiden_status leiden_update(leiden_handle *h, const leiden_batch *batch, int32_t
 leiden_status leiden_update_bytes(const leiden_handle *h, int64_t n_del, int64_t n_ins, int64_t *bytes) {
   if (!h || !bytes || n_del < 0 || n_ins < 0) return LEIDEN_EINVAL;
   // working set of an update (per vertex: level state, flags, lists, batch
-  // rows, the aggregation's community order; per entry: the graph and its
-  // spare copy, two level graphs, the aggregation's grouped entries and
-  // results (16 bytes), room for the hub tables; per directed batch entry:
-  // keys, values and their sorted copies; plus the per-wavefront tables of the
-  // asynchronous sweeps) minus what the handle already holds.  At RMAT scale
-  // 26 (67M vertices, 2.1e9 entries) this is ~148 GB, the measured peak.
+  // rows, the aggregation's community order, the first level's map and
+  // labels; per entry: the graph and its spare copy, two level graphs, the
+  // aggregation's grouped entries and results (16 bytes), the first level's
+  // FP64 run sums and their rows (16 bytes at most), room for the hub
+  // tables; per directed batch entry: keys, values and their sorted copies;
+  // plus the per-wavefront tables of the asynchronous sweeps) minus what the
+  // handle already holds.  At RMAT scale 26 (67M vertices, 2.1e9 entries)
+  // this is ~183 GB, above the measured peak of ~170 GB.
   const int64_t n = h->n;
   const int64_t nnz = h->nnz + 2 * n_ins;
   const int64_t E = 2 * (n_del + n_ins);
   const int64_t async_tables = (int64_t)kDefaultAsyncWaves * 2 * kHubDeg * 12;
-  const int64_t need = 203 * n + 64 * nnz + 68 * E + async_tables;
+  const int64_t need = 211 * n + 80 * nnz + 68 * E + async_tables;
   int64_t held = (int64_t)h->w.held();
   for (const DBuf *b : {&h->g_off, &h->g_idx, &h->g_w, &h->g_crow, &h->t_off, &h->t_idx, &h->t_w, &h->C, &h->K,
                         &h->Sig})

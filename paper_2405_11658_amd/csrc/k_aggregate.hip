@@ -178,7 +178,7 @@ __device__ __forceinline__ void seg_scan(double &x, int &f) {
 }
 
 __device__ __forceinline__ void small_regs(const uint32_t *gkey, const float *gval, int64_t sb, int sl, int c,
-                                           uint32_t *ukey, float *uval, int32_t *rowlen, double *K) {
+                                           uint32_t *ukey, float *uval, double *u64, int32_t *rowlen, double *K) {
   uint32_t key = kKeyPad;
   float v = 0.0f;
   if (lane() < sl) {
@@ -215,6 +215,7 @@ __device__ __forceinline__ void small_regs(const uint32_t *gkey, const float *gv
     const float wf = (float)x;
     ukey[sb + rank] = key;
     uval[sb + rank] = wf;
+    if (u64) u64[sb + rank] = x;
     kx = (double)wf;
   }
   kx = group_sum<kWave>(kx);
@@ -278,7 +279,7 @@ __device__ __forceinline__ void bitonic_regs(uint32_t (&key)[R], float (&v)[R]) 
 // over the lanes (fixed tree).
 template <int R>
 __device__ __forceinline__ void small_wide(const uint32_t *gkey, const float *gval, int64_t sb, int sl, int c,
-                                           uint32_t *ukey, float *uval, int32_t *rowlen, double *K) {
+                                           uint32_t *ukey, float *uval, double *u64, int32_t *rowlen, double *K) {
   uint32_t key[R];
   float v[R];
 #pragma unroll
@@ -338,6 +339,7 @@ __device__ __forceinline__ void small_wide(const uint32_t *gkey, const float *gv
       const float wf = (float)acc;
       ukey[sb + hb - 1] = key[r];
       uval[sb + hb - 1] = wf;
+      if (u64) u64[sb + hb - 1] = acc;
       kx += (double)wf;
     }
   }
@@ -349,8 +351,8 @@ __device__ __forceinline__ void small_wide(const uint32_t *gkey, const float *gv
 }
 
 __device__ __forceinline__ void small_lds(const uint32_t *gkey, const float *gval, int64_t sb, int sl, int c,
-                                          uint32_t *sk, float *sv, uint32_t *ukey, float *uval, int32_t *rowlen,
-                                          double *K) {
+                                          uint32_t *sk, float *sv, uint32_t *ukey, float *uval, double *u64,
+                                          int32_t *rowlen, double *K) {
   int P = 2 * kWave;
   while (P < sl) P <<= 1;
   wave_lds_fence();  // the previous segment's reads of this area are done
@@ -397,6 +399,7 @@ __device__ __forceinline__ void small_lds(const uint32_t *gkey, const float *gva
       const float wf = (float)x;
       ukey[sb + rank] = key;
       uval[sb + rank] = wf;
+      if (u64) u64[sb + rank] = x;
       kx += (double)wf;
     }
     carry = __shfl(x, kWave - 1);
@@ -410,8 +413,8 @@ __device__ __forceinline__ void small_lds(const uint32_t *gkey, const float *gva
 }
 
 __global__ __launch_bounds__(256) void k_agg_small(const int64_t *seg, int64_t ncomm, const uint32_t *gkey,
-                                                   const float *gval, uint32_t *ukey, float *uval, int32_t *rowlen,
-                                                   double *K) {
+                                                   const float *gval, uint32_t *ukey, float *uval, double *u64,
+                                                   int32_t *rowlen, double *K) {
   constexpr int W = 256 / kWave;
   __shared__ uint32_t sk[W][kAggSmall];
   __shared__ float sv[W][kAggSmall];
@@ -433,18 +436,18 @@ __global__ __launch_bounds__(256) void k_agg_small(const int64_t *seg, int64_t n
       const int64_t sb = __shfl(b, k);
       const int sl = (int)__shfl(len, k);
       const int ck = (int)__shfl(c, k);
-      if (sl <= kWave) small_regs(gkey, gval, sb, sl, ck, ukey, uval, rowlen, K);
-      else if (sl <= 2 * kWave) small_wide<2>(gkey, gval, sb, sl, ck, ukey, uval, rowlen, K);
-      else if (sl <= 4 * kWave) small_wide<4>(gkey, gval, sb, sl, ck, ukey, uval, rowlen, K);
-      else small_lds(gkey, gval, sb, sl, ck, sk[wid], sv[wid], ukey, uval, rowlen, K);
+      if (sl <= kWave) small_regs(gkey, gval, sb, sl, ck, ukey, uval, u64, rowlen, K);
+      else if (sl <= 2 * kWave) small_wide<2>(gkey, gval, sb, sl, ck, ukey, uval, u64, rowlen, K);
+      else if (sl <= 4 * kWave) small_wide<4>(gkey, gval, sb, sl, ck, ukey, uval, u64, rowlen, K);
+      else small_lds(gkey, gval, sb, sl, ck, sk[wid], sv[wid], ukey, uval, u64, rowlen, K);
     }
   }
 }
 void agg_small(const int64_t *seg, int64_t ncomm, const uint32_t *gkey, const float *gval, uint32_t *ukey,
-               float *uval, int32_t *rowlen, double *K, hipStream_t s) {
+               float *uval, double *u64, int32_t *rowlen, double *K, hipStream_t s) {
   if (ncomm > 0)
     hipLaunchKernelGGL(k_agg_small, flat_grid(ceil_div(ncomm, kWave), 4, 8192), 256, 0, s, seg, ncomm, gkey, gval,
-                       ukey, uval, rowlen, K);
+                       ukey, uval, u64, rowlen, K);
 }
 
 // ---- 5: large segments ----------------------------------------------------------
@@ -496,7 +499,8 @@ void agg_tile_seg(const int64_t *tfirst, int64_t nl, int32_t *tseg, hipStream_t 
 //           following tiles it covers.
 template <int PASS>
 __global__ __launch_bounds__(256) void k_agg_lruns(const uint32_t *gkey, const float *gval, RsSeg g, int64_t *hc,
-                                                   double *tin, uint32_t *ukey, float *uval, double *tks) {
+                                                   double *tin, uint32_t *ukey, float *uval, double *l64,
+                                                   double *tks) {
   // The tile is loaded with coalesced loads into LDS (one pad word per kPR
   // items, so that each thread then reads its kPR consecutive items without
   // bank conflicts) and scanned in one round: each thread sums its items in
@@ -608,6 +612,7 @@ __global__ __launch_bounds__(256) void k_agg_lruns(const uint32_t *gkey, const f
         const float wf = (float)sum;
         ukey[ts.sb + rk] = key[r];
         uval[ts.sb + rk] = wf;
+        if (l64) l64[ts.sb + rk] = sum;
         kacc += (double)wf;
       }
     }
@@ -623,12 +628,12 @@ __global__ __launch_bounds__(256) void k_agg_lruns(const uint32_t *gkey, const f
   }
 }
 void agg_large_runs(int pass, const uint32_t *gkey, const float *gval, const RsSeg &g, int64_t *hc, double *tin,
-                    uint32_t *ukey, float *uval, double *tks, hipStream_t s) {
+                    uint32_t *ukey, float *uval, double *l64, double *tks, hipStream_t s) {
   if (g.ntiles <= 0) return;
   if (pass == 0)
-    hipLaunchKernelGGL(k_agg_lruns<0>, (int)g.ntiles, 256, 0, s, gkey, gval, g, hc, tin, ukey, uval, tks);
+    hipLaunchKernelGGL(k_agg_lruns<0>, (int)g.ntiles, 256, 0, s, gkey, gval, g, hc, tin, ukey, uval, l64, tks);
   else
-    hipLaunchKernelGGL(k_agg_lruns<1>, (int)g.ntiles, 256, 0, s, gkey, gval, g, hc, tin, ukey, uval, tks);
+    hipLaunchKernelGGL(k_agg_lruns<1>, (int)g.ntiles, 256, 0, s, gkey, gval, g, hc, tin, ukey, uval, l64, tks);
 }
 
 // rowlen and K' of the large segments (K' from the tiles' parts): a
@@ -655,7 +660,8 @@ void agg_large_rows(int64_t nl, const int32_t *lc, const int64_t *tfirst, const 
 // ---- 6: rows into place ------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_agg_csmall(const int64_t *seg, int64_t ncomm, const int32_t *rowlen,
                                                     const int64_t *out_off, const uint32_t *ukey, const float *uval,
-                                                    int32_t *out_idx, float *out_w) {
+                                                    const double *v64, int32_t *out_idx, float *out_w,
+                                                    double *out_w64) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t c0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave * kWave; c0 < ncomm; c0 += stride) {
     const int64_t c = c0 + lane();
@@ -676,6 +682,7 @@ __global__ __launch_bounds__(256) void k_agg_csmall(const int64_t *seg, int64_t 
       for (int j = lane(); j < rk; j += kWave) {
         out_idx[dst + j] = (int32_t)ukey[src + j];
         out_w[dst + j] = uval[src + j];
+        if (out_w64) out_w64[dst + j] = v64[src + j];
       }
     }
   }
@@ -687,7 +694,8 @@ __global__ __launch_bounds__(256) void k_agg_csmall(const int64_t *seg, int64_t 
 __global__ __launch_bounds__(256) void k_agg_clarge(const int32_t *lc, const int64_t *lsb, const int32_t *tseg,
                                                     const int64_t *tfirst, const int32_t *rowlen,
                                                     const int64_t *out_off, const uint32_t *ukey, const float *uval,
-                                                    int32_t *out_idx, float *out_w) {
+                                                    const double *v64, int32_t *out_idx, float *out_w,
+                                                    double *out_w64) {
   const int64_t t = blockIdx.x;
   const int l = tseg[t];
   const int c = lc[l];
@@ -697,18 +705,19 @@ __global__ __launch_bounds__(256) void k_agg_clarge(const int32_t *lc, const int
   for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
     out_idx[d0 + j] = (int32_t)ukey[s0 + j];
     out_w[d0 + j] = uval[s0 + j];
+    if (out_w64) out_w64[d0 + j] = v64[s0 + j];
   }
 }
 void agg_compact(const int64_t *seg, int64_t ncomm, const int32_t *lc, const int64_t *lsb, const int32_t *tseg,
                  const int64_t *tfirst, int64_t ntl, const int32_t *rowlen, const int64_t *out_off,
-                 const uint32_t *ukey, const float *uval, const uint32_t *lkey, const float *lval, int32_t *out_idx,
-                 float *out_w, hipStream_t s) {
+                 const uint32_t *ukey, const float *uval, const uint32_t *lkey, const float *lval,
+                 const double *v64, int32_t *out_idx, float *out_w, double *out_w64, hipStream_t s) {
   if (ncomm > 0)
     hipLaunchKernelGGL(k_agg_csmall, flat_grid(ncomm, 256, 8192), 256, 0, s, seg, ncomm, rowlen, out_off, ukey, uval,
-                       out_idx, out_w);
+                       v64, out_idx, out_w, out_w64);
   if (ntl > 0)
     hipLaunchKernelGGL(k_agg_clarge, (int)ntl, 256, 0, s, lc, lsb, tseg, tfirst, rowlen, out_off, lkey, lval,
-                       out_idx, out_w);
+                       v64, out_idx, out_w, out_w64);
 }
 
 }  // namespace lk

@@ -44,8 +44,10 @@ __global__ __launch_bounds__(256) void k_mod_edges(const int64_t *off, const int
 }
 
 // Internal weight only (acc[0] += sum of entries inside a community): used
-// when Sigma and 2m are already known.
-__global__ __launch_bounds__(256) void k_mod_intra(const int64_t *off, const int32_t *idx, const float *w,
+// when Sigma and 2m are already known.  W: float for a stored graph, double
+// for the FP64 weights of an aggregated level.
+template <class W>
+__global__ __launch_bounds__(256) void k_mod_intra(const int64_t *off, const int32_t *idx, const W *w,
                                                    const int32_t *crow, int64_t nnz, const int32_t *C,
                                                    double *acc) {
   __shared__ int rowof[kChunk];
@@ -58,13 +60,13 @@ __global__ __launch_bounds__(256) void k_mod_intra(const int64_t *off, const int
   // then both communities
   constexpr int PER = kChunk / 256;
   int j[PER], r[PER];
-  float x[PER];
+  W x[PER];
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const int t = threadIdx.x + k * 256;
     j[k] = 0;
     r[k] = 0;
-    x[k] = 0.0f;
+    x[k] = W(0);
     if (t < len) {
       j[k] = idx[q0 + t];
       x[k] = w[q0 + t];
@@ -80,7 +82,21 @@ __global__ __launch_bounds__(256) void k_mod_intra(const int64_t *off, const int
 }
 void modularity_intra(const int64_t *off, const int32_t *idx, const float *w, const int32_t *crow, int64_t nnz,
                       const int32_t *C, double *acc, hipStream_t s) {
-  if (nnz > 0) hipLaunchKernelGGL(k_mod_intra, (int)ceil_div(nnz, kChunk), 256, 0, s, off, idx, w, crow, nnz, C, acc);
+  if (nnz > 0)
+    hipLaunchKernelGGL(k_mod_intra<float>, (int)ceil_div(nnz, kChunk), 256, 0, s, off, idx, w, crow, nnz, C, acc);
+}
+void modularity_intra64(const int64_t *off, const int32_t *idx, const double *w, const int32_t *crow, int64_t nnz,
+                        const int32_t *C, double *acc, hipStream_t s) {
+  if (nnz > 0)
+    hipLaunchKernelGGL(k_mod_intra<double>, (int)ceil_div(nnz, kChunk), 256, 0, s, off, idx, w, crow, nnz, C, acc);
+}
+
+__global__ void k_scatter_labels(const int32_t *to, const int32_t *val, int64_t n, int32_t *out) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    out[to[v]] = val[v];
+}
+void scatter_labels(const int32_t *to, const int32_t *val, int64_t n, int32_t *out, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_scatter_labels, flat_grid(n), 256, 0, s, to, val, n, out);
 }
 
 void modularity_edges(const int64_t *off, const int32_t *idx, const float *w, const int32_t *crow,

@@ -295,20 +295,23 @@ void agg_vdeg(int64_t n, const int64_t *off, const int32_t *vs, int64_t *deg, in
 void agg_cdeg(int64_t n, const uint32_t *Cs, const int64_t *eoff, int64_t *hpos, int64_t *cdeg, hipStream_t s);
 void agg_group(const AggArgs &a, const int32_t *crow, const int32_t *pos, const int64_t *eoff, uint32_t *gkey,
                float *gval, hipStream_t s);
+// u64 / l64 / v64 (nullable): the rows' weights also as the FP64 run sums
+// before rounding, at the same positions.
 void agg_small(const int64_t *seg, int64_t ncomm, const uint32_t *gkey, const float *gval, uint32_t *ukey,
-               float *uval, int32_t *rowlen, double *K, hipStream_t s);
+               float *uval, double *u64, int32_t *rowlen, double *K, hipStream_t s);
 void agg_large_flags(const int64_t *seg, int64_t ncomm, int32_t *flag, hipStream_t s);
 void agg_large_list(const int64_t *seg, int64_t ncomm, int32_t *flag, const int32_t *lidx, int32_t *lc, int64_t *lsb,
                     int64_t *lse, int64_t *ltn, hipStream_t s);
 void agg_tile_seg(const int64_t *tfirst, int64_t nl, int32_t *tseg, hipStream_t s);
 void agg_large_runs(int pass, const uint32_t *gkey, const float *gval, const RsSeg &g, int64_t *hc, double *tin,
-                    uint32_t *ukey, float *uval, double *tks, hipStream_t s);
+                    uint32_t *ukey, float *uval, double *l64, double *tks, hipStream_t s);
 void agg_large_rows(int64_t nl, const int32_t *lc, const int64_t *tfirst, const int64_t *hc, const double *tks,
                     int32_t *rowlen, double *K, hipStream_t s);
 // rows of the small segments from (ukey, uval), of the large ones from (lkey, lval)
 void agg_compact(const int64_t *seg, int64_t ncomm, const int32_t *lc, const int64_t *lsb, const int32_t *tseg,
                  const int64_t *tfirst, int64_t ntl, const int32_t *rowlen, const int64_t *out_off, const uint32_t *ukey, const float *uval,
-                 const uint32_t *lkey, const float *lval, int32_t *out_idx, float *out_w, hipStream_t s);
+                 const uint32_t *lkey, const float *lval, const double *v64, int32_t *out_idx, float *out_w,
+                 double *out_w64, hipStream_t s);
 
 // ---- k_modularity.hip --------------------------------------------------------
 // acc[0] += sigma total, S[c] += K-contributions (S zeroed, ncomm = n)
@@ -318,6 +321,10 @@ void modularity_edges(const int64_t *off, const int32_t *idx, const float *w, co
 // acc[0] += weight of the entries inside a community (Sigma and 2m known elsewhere)
 void modularity_intra(const int64_t *off, const int32_t *idx, const float *w, const int32_t *crow, int64_t nnz,
                       const int32_t *C, double *acc, hipStream_t s);
+void modularity_intra64(const int64_t *off, const int32_t *idx, const double *w, const int32_t *crow, int64_t nnz,
+                        const int32_t *C, double *acc, hipStream_t s);
+// out[to[v]] = val[v] for v < n (every writer of one target writes the same value)
+void scatter_labels(const int32_t *to, const int32_t *val, int64_t n, int32_t *out, hipStream_t s);
 // acc[1] += sum_c S_c, acc[2] += sum_c (S_c)^2 scaled: computed as sum (S_c/M2)^2 after M2 known
 void modularity_comm(const double *S, int64_t n, double *acc, hipStream_t s);
 void modularity_comm_sq(const double *S, int64_t n, double M2, double *acc, hipStream_t s);
