@@ -36,7 +36,7 @@ enum Slot {
   // level graphs (ping-pong), and the first aggregated level kept for the
   // modularity of the result (with its FP64 weights and the level-0 map)
   G0_off, G0_idx, G0_w, G0_crow, G1_off, G1_idx, G1_w, G1_crow, L1_off, L1_idx, L1_w, L1_crow, L1_w64,
-  L1_map, L1_lab, A_v64,
+  L1_map, L1_lab, A_v64, L_fa, L_map2,
   // aggregation
   A_vk, A_vk2, A_vv, A_vv2, A_eoff, A_pos, A_seg, A_hpos, A_gkey, A_gval, A_ukey, A_uval, A_lflag,
   A_lidx, A_lc, A_lsb, A_lse, A_ltn, A_tseg, A_hc, A_tin, A_rowlen,
@@ -553,6 +553,30 @@ int64_t renumber_dense(Ctx &x, int32_t *C, int64_t n, int64_t bound) {
   return (int64_t)x.read(&map[bound]);
 }
 
+// renumber_dense with the labels that have a member with edges first (in
+// ascending order, *na of them), then the others: the aggregated level's
+// vertices without edges (the level-0 vertices without edges, each alone)
+// are then the last ones and can be left out of it.
+int64_t renumber_active_first(Ctx &x, int32_t *C, int64_t n, const int64_t *off, int64_t *na) {
+  int32_t *used = x.get<int32_t>(L_flags, n + 1);
+  int32_t *act = x.get<int32_t>(L_fa, n + 1);
+  int32_t *pa = x.get<int32_t>(L_map, n + 1);
+  int32_t *pi = x.get<int32_t>(L_map2, n + 1);
+  x.zero(used, n + 1);
+  x.zero(act, n + 1);
+  mark_used_active(C, off, n, used, act, x.s);
+  flags_inactive(used, act, n, x.s);
+  scan_i32(x, act, pa, n + 1);
+  scan_i32(x, used, pi, n + 1);
+  const int64_t nact = (int64_t)x.read(&pa[n]);
+  const int64_t nin = (int64_t)x.read(&pi[n]);
+  active_first_map(act, pa, pi, nact, n, used, x.s);
+  gather_map(C, used, n, x.s);
+  x.launched("renumber");
+  *na = nact;
+  return nact + nin;
+}
+
 // Alg. "leidenAggregate": level g with dense labels C (< ncomm) -> out level.
 // Entries grouped by the community of their source (vertices in community
 // order), each community's group sorted by neighbour community and summed:
@@ -687,6 +711,7 @@ struct Level1 {
   Level g{};
   const double *w64 = nullptr;
   const int32_t *map = nullptr;  // level-0 vertex -> first-level vertex
+  int64_t nlab = 0;              // first-level labels (with those left out of the level)
 };
 
 // modularity_known from the first aggregated level: the result's labels
@@ -697,7 +722,7 @@ double modularity_level1(Ctx &x, const Level1 &l1, const int32_t *C, int64_t n, 
   DevScal *sc = x.scal();
   x.zero(sc->acc, 4);
   hipEvent_t t0 = x.kp ? x.kp->begin() : nullptr;
-  int32_t *lab = x.get<int32_t>(L1_lab, l1.g.n);
+  int32_t *lab = x.get<int32_t>(L1_lab, l1.nlab);
   scatter_labels(l1.map, C, n, lab, x.s);
   modularity_intra64(l1.g.off, l1.g.idx, l1.w64, l1.g.crow, l1.g.nnz, lab, sc->acc, x.s);
   if (x.kp) x.kp->end(t0, LEIDEN_PROF_MOD_SCAN, l1.g.nnz, n);
@@ -770,11 +795,19 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
 
   Level g = g0;
   int curbuf = -1;  // -1: the level-0 graph
+  // Asynchronous mode with several wavefronts: the first level's vertices
+  // without edges (level-0 vertices without edges, alone in every pass) are
+  // left out of the aggregated levels; their labels stay above every later
+  // level's and the pass loop's rules and statistics count them as before.
+  // (One wavefront keeps the serial order and labels.)
+  const bool compact = async && NW > 1;
+  int64_t niso = 0;
   double tau = p.tau0;
   int pass = 0;
   for (pass = 0; pass < p.max_passes; ++pass) {
     tm.pass = pass;
     const int64_t nl = g.n;
+    const int64_t nfull = nl + niso;
     const Layout B = level_layout(x, g, NS, hubdeg, region, counts, scnt, soff, sfill, vbs);
     const HubHost hh = hub_plan(x, g, NS, hubdeg, B);
     const int64_t alen = B.region[NS * kNB];  // vertices with edges
@@ -807,7 +840,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     ma.anext = &sc->anext; ma.akeys = akeys; ma.avals = avals;
     ma.alist = alist; ma.alen = alen;
     ma.hubdeg = hubdeg;
-    ma.cached = async && nl >= kCachedLevel;
+    ma.cached = async && nfull >= kCachedLevel;
     ma.defer = async && NW > 1;
     int li = 0;
     int64_t moves_total = 0;
@@ -881,7 +914,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     tm.mark(CAT_MOVE);
     if (st && pass < LEIDEN_MAX_PASSES) {
       st->move_iters[pass] = li;
-      st->level_vertices[pass] = nl;
+      st->level_vertices[pass] = nfull;
       st->level_entries[pass] = g.nnz;
       if (pass == 0) {
         st->moves_pass0 = moves_total;
@@ -905,7 +938,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     ra.anext = &sc->anext; ra.akeys = akeys; ra.avals = avals;
     ra.alist = alist; ra.alen = alen;
     ra.hubdeg = hubdeg;
-    ra.cached = async && nl >= kCachedLevel;
+    ra.cached = async && nfull >= kCachedLevel;
     ra.defer = async && NW > 1;
     ra.sweep_work = x.kp && x.kp->on ? sc->sweep_work + 2 : nullptr;
     reset_iter(counts, NS * kNB, nullptr, &sc->refined, async ? &sc->anext : nullptr, x.s);
@@ -951,14 +984,17 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
         // communities of this level, for the statistics only
         int32_t *tmpC = x.get<int32_t>(L_CB, nl);
         x.copy(tmpC, C, nl);
-        st->communities[pass] = renumber_dense(x, tmpC, nl, nl);
+        st->communities[pass] = renumber_dense(x, tmpC, nl, nl) + niso;
       }
       tm.mark(CAT_OTHER);
       break;
     }
-    const int64_t ncomm = renumber_dense(x, C, nl, nl);
-    if (st && pass < LEIDEN_MAX_PASSES) st->communities[pass] = ncomm;
-    if (p.agg_tol < 1.0 && (double)ncomm / (double)nl > p.agg_tol) {
+    int64_t nact = 0;
+    const int64_t ncomm = (compact && pass == 0) ? renumber_active_first(x, C, nl, g.off, &nact)
+                                                 : renumber_dense(x, C, nl, nl);
+    if (!(compact && pass == 0)) nact = ncomm;
+    if (st && pass < LEIDEN_MAX_PASSES) st->communities[pass] = ncomm + niso;
+    if (p.agg_tol < 1.0 && (double)(ncomm + niso) / (double)nfull > p.agg_tol) {
       tm.mark(CAT_OTHER);
       break;
     }
@@ -966,11 +1002,11 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     // trades: it ends the passes as a level that converged in one iteration
     // would.  A stalled level that still merged many (slowly converging
     // levels, e.g. of road-like graphs) goes on to the next pass.
-    if (stalled && (double)ncomm > kStallKeep * (double)nl) {
+    if (stalled && (double)(ncomm + niso) > kStallKeep * (double)nfull) {
       tm.mark(CAT_OTHER);
       break;
     }
-    gather_map(Ctop, C, n, x.s);  // dendrogram lookup
+    gather_map_bounded(Ctop, C, n, nl, x.s);  // dendrogram lookup (left-out labels stay)
     x.launched("lookup");
     tm.mark(CAT_OTHER);
     if (l1 && pass == 0) {
@@ -981,25 +1017,32 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
       g = aggregate_level(x, g, C, ncomm, 2, K, &w64);
       curbuf = 2;
       l1->ok = w64 != nullptr;
-      l1->g = g;
       l1->w64 = w64;
       l1->map = map;
+      l1->nlab = ncomm;
     } else {
       const int outbuf = (curbuf == 0) ? 1 : 0;
       g = aggregate_level(x, g, C, ncomm, outbuf, K);
       curbuf = outbuf;
     }
+    if (nact < ncomm) {
+      // the trailing rows are the left-out vertices' (empty): drop them
+      g.n = nact;
+      chunk_start_rows(g.off, nact, g.nnz, const_cast<int32_t *>(g.crow), x.s);
+      niso += ncomm - nact;
+    }
+    if (l1 && pass == 0) l1->g = g;
     tm.mark(CAT_AGG);
-    x.copy(S, K, ncomm);
-    fill_u8(U, 1, ncomm, x.s);
-    iota_i32(C, ncomm, x.s);
-    fill_u8(dC, 1, ncomm, x.s);
+    x.copy(S, K, nact);
+    fill_u8(U, 1, nact, x.s);
+    iota_i32(C, nact, x.s);
+    fill_u8(dC, 1, nact, x.s);
     x.launched("pass reset");
     tau = tau / p.tol_drop;
   }
   tm.pass = -1;
   if (st && pass >= p.max_passes) st->passes = p.max_passes;
-  gather_map(Ctop, C, n, x.s);
+  gather_map_bounded(Ctop, C, n, g.n, x.s);
   renumber_dense(x, Ctop, n, n);
   x.copy(out, Ctop, n);
   x.launched("final lookup");

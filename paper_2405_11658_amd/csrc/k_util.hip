@@ -102,6 +102,43 @@ void gather_map(int32_t *C, const int32_t *map, int64_t n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_gather_map, flat_grid(n), 256, 0, s, C, map, n);
 }
 
+__global__ void k_gather_map_bounded(int32_t *C, const int32_t *map, int64_t n, int64_t bound) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int c = C[i];
+    if (c < bound) C[i] = map[c];
+  }
+}
+void gather_map_bounded(int32_t *C, const int32_t *map, int64_t n, int64_t bound, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_gather_map_bounded, flat_grid(n), 256, 0, s, C, map, n, bound);
+}
+
+__global__ void k_mark_used_active(const int32_t *C, const int64_t *off, int64_t n, int32_t *used, int32_t *act) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int c = C[i];
+    used[c] = 1;
+    if (off[i + 1] > off[i]) act[c] = 1;
+  }
+}
+void mark_used_active(const int32_t *C, const int64_t *off, int64_t n, int32_t *used, int32_t *act, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_mark_used_active, flat_grid(n), 256, 0, s, C, off, n, used, act);
+}
+__global__ void k_flags_inactive(int32_t *used, const int32_t *act, int64_t n) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x)
+    used[c] = used[c] && !act[c];
+}
+void flags_inactive(int32_t *used, const int32_t *act, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_flags_inactive, flat_grid(n), 256, 0, s, used, act, n);
+}
+__global__ void k_active_first_map(const int32_t *act, const int32_t *pa, const int32_t *pi, int64_t na, int64_t n,
+                                   int32_t *map) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x)
+    map[c] = act[c] ? pa[c] : (int32_t)(na + pi[c]);
+}
+void active_first_map(const int32_t *act, const int32_t *pa, const int32_t *pi, int64_t na, int64_t n, int32_t *map,
+                      hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_active_first_map, flat_grid(n), 256, 0, s, act, pa, pi, na, n, map);
+}
+
 __global__ void k_mark_used(const int32_t *C, int64_t n, int32_t *flags) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     flags[C[i]] = 1;

@@ -47,6 +47,15 @@ void row_sums(const int64_t *off, const float *w, int64_t nrows, int64_t nnz, co
 void scatter_add(const double *v, const int32_t *C, int64_t n, double *out, hipStream_t s);
 // C[i] = map[C[i]]
 void gather_map(int32_t *C, const int32_t *map, int64_t n, hipStream_t s);
+// C[i] = map[C[i]] where C[i] < bound; larger labels are left as they are
+void gather_map_bounded(int32_t *C, const int32_t *map, int64_t n, int64_t bound, hipStream_t s);
+// flags of the labels in use (used) and of those with a member with edges (act)
+void mark_used_active(const int32_t *C, const int64_t *off, int64_t n, int32_t *used, int32_t *act, hipStream_t s);
+// used[c] = used[c] && !act[c] (in place), for c < n
+void flags_inactive(int32_t *used, const int32_t *act, int64_t n, hipStream_t s);
+// map[c] = act[c] ? pa[c] : na + pi[c], for c < n
+void active_first_map(const int32_t *act, const int32_t *pa, const int32_t *pi, int64_t na, int64_t n, int32_t *map,
+                      hipStream_t s);
 // flags[C[i]] = 1
 void mark_used(const int32_t *C, int64_t n, int32_t *flags, hipStream_t s);
 // C[i] < bound for all i?  sets *err |= flag otherwise.
