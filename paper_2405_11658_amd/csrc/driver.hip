@@ -582,9 +582,11 @@ int64_t renumber_active_first(Ctx &x, int32_t *C, int64_t n, const int64_t *off,
 // order), each community's group sorted by neighbour community and summed:
 // rows come out sorted by id, with FP64 sums rounded to float32.  outbuf 0
 // and 1 are the ping-pong level graphs, 2 the kept first level; with w64 the
-// rows' FP64 sums are kept too (*w64, one per stored entry).
+// rows' FP64 sums are kept too (*w64, one per stored entry).  Neighbour
+// labels are below nkey (ncomm when 0; fewer when the labels of communities
+// without edges come last, since no entry points to those).
 Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, int outbuf, double *Kout,
-                      double **w64 = nullptr) {
+                      double **w64 = nullptr, int64_t nkey = 0) {
   AggArgs a;
   memset(&a, 0, sizeof(a));
   a.n = g.n;
@@ -667,7 +669,8 @@ Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, i
       rs.sbeg = lsb;
       rs.send = lse;
       // sorted segments in (skey, sval); their rows go to the other pair
-      const int r = rsort<uint32_t, float>(gkey, gval, ukey, uval, rs, cb, x.tmp(rs_tmp_bytes(ntl)), x.s);
+      const int cbe = nkey > 0 ? key_bits((unsigned long long)std::max<int64_t>(nkey - 1, 0)) : cb;
+      const int r = rsort<uint32_t, float>(gkey, gval, ukey, uval, rs, cbe, x.tmp(rs_tmp_bytes(ntl)), x.s);
       uint32_t *skey = r ? ukey : gkey;
       float *sval = r ? uval : gval;
       lkey = r ? gkey : ukey;
@@ -1014,7 +1017,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
       int32_t *map = x.get<int32_t>(L1_map, n);
       x.copy(map, C, n);
       double *w64 = nullptr;
-      g = aggregate_level(x, g, C, ncomm, 2, K, &w64);
+      g = aggregate_level(x, g, C, ncomm, 2, K, &w64, nact);
       curbuf = 2;
       l1->ok = w64 != nullptr;
       l1->w64 = w64;
@@ -1022,7 +1025,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
       l1->nlab = ncomm;
     } else {
       const int outbuf = (curbuf == 0) ? 1 : 0;
-      g = aggregate_level(x, g, C, ncomm, outbuf, K);
+      g = aggregate_level(x, g, C, ncomm, outbuf, K, nullptr, nact);
       curbuf = outbuf;
     }
     if (nact < ncomm) {

@@ -152,52 +152,38 @@ __global__ __launch_bounds__(kPT) void k_rs_hist(const K *keys, RsSeg g, int shi
 
 // Each tile ranks its items stably by digit into a local digit-sorted copy in
 // LDS, then writes it out in order: the items of one digit go to consecutive
-// places, so consecutive threads write consecutive addresses.
+// places, so consecutive threads write consecutive addresses.  Each
+// wavefront ranks its own contiguous quarter of the tile (16 rounds of 64
+// items, in order) against digit counters that only it uses, so the rounds
+// need no workgroup barrier; one prefix over the digits and the four
+// wavefronts' counts then gives every item its place.  Items are ordered by
+// (wavefront, round, lane), which is their order in the tile: stable.
 template <class K, class V>
 __global__ __launch_bounds__(kPT) void k_rs_scatter(const K *ki, const V *vi, K *ko, V *vo, RsSeg g, int shift,
                                                     int bits, const int64_t *hs, const int32_t *tcnt) {
+  (void)tcnt;
   constexpr int W = kPT / kWave;
+  constexpr int QW = kPTile / W;  // items per wavefront
   __shared__ K sk[kPTile];
   __shared__ V sv[kPTile];
   __shared__ int64_t gbase[kDig];
-  __shared__ int loff[kDig];
-  __shared__ int run[kDig];
-  __shared__ int wcnt[W][kDig];
+  __shared__ int cnt[W][kDig];
   __shared__ int sw[W];
   const int64_t t = blockIdx.x;
   const TileSpan ts = tile_span(g, t);
   const int64_t seg0 = hs[kDig * ts.f0];
-  {
-    // tile-local digit offsets: each thread owns kDPT consecutive digits
-    int c[kDPT], sum = 0;
-#pragma unroll
-    for (int k = 0; k < kDPT; ++k) {
-      c[k] = tcnt[t * kDig + threadIdx.x * kDPT + k];
-      sum += c[k];
-    }
-    int tot;
-    int pre = blk_excl<int>(sum, &tot, sw);
-#pragma unroll
-    for (int k = 0; k < kDPT; ++k) {
-      const int d = threadIdx.x * kDPT + k;
-      loff[d] = pre;
-      gbase[d] = ts.sb + (hs[kDig * ts.f0 + (int64_t)d * ts.nt + (t - ts.f0)] - seg0) - pre;
-      run[d] = 0;
-      pre += c[k];
-#pragma unroll
-      for (int w = 0; w < W; ++w) wcnt[w][d] = 0;
-    }
-  }
-  __syncthreads();
-  const K mask = (K)((1u << bits) - 1u);
   const int wid = (int)threadIdx.x / kWave;
-  const unsigned long long below = lane() == 0 ? 0ull : (~0ull >> (64 - lane()));
-  // the tile's items in registers first (all loads in flight together)
+  for (int d = threadIdx.x; d < kDig; d += kPT) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) cnt[w][d] = 0;
+  }
+  // the wavefront's items in registers first (all loads in flight together)
+  const int64_t q0 = ts.lo + (int64_t)wid * QW;
   K kr[kPR];
   V vr[kPR];
 #pragma unroll
   for (int r = 0; r < kPR; ++r) {
-    const int64_t p = ts.lo + r * kPT + threadIdx.x;
+    const int64_t p = q0 + r * kWave + lane();
     kr[r] = (K)0;
     vr[r] = V();
     if (p < ts.hi) {
@@ -205,41 +191,68 @@ __global__ __launch_bounds__(kPT) void k_rs_scatter(const K *ki, const V *vi, K 
       vr[r] = vi[p];
     }
   }
+  __syncthreads();  // counters cleared
+  const K mask = (K)((1u << bits) - 1u);
+  const unsigned long long below = lane() == 0 ? 0ull : (~0ull >> (64 - lane()));
+  int rk[kPR];
 #pragma unroll
   for (int r = 0; r < kPR; ++r) {
-    const int64_t p = ts.lo + r * kPT + threadIdx.x;
-    if (ts.lo + r * kPT >= ts.hi) break;  // uniform
+    const int64_t p = q0 + r * kWave + lane();
     const bool act = p < ts.hi;
-    const K key = kr[r];
-    const V val = vr[r];
-    const int dg = act ? (int)((key >> shift) & mask) : 0;
+    const int dg = act ? (int)((kr[r] >> shift) & mask) : 0;
     unsigned long long same = __ballot(act);
     for (int bit = 0; bit < bits; ++bit) {
       const unsigned long long on = __ballot(act && ((dg >> bit) & 1));
       same &= ((dg >> bit) & 1) ? on : ~on;
     }
     const int rank_w = __popcll(same & below);
-    if (act && rank_w == 0) wcnt[wid][dg] = __popcll(same);
-    __syncthreads();
-    if (act) {
-      int before = 0;
-      for (int w = 0; w < wid; ++w) before += wcnt[w][dg];
-      const int q = loff[dg] + run[dg] + before + rank_w;
-      sk[q] = key;
-      sv[q] = val;
-    }
-    __syncthreads();
-    for (int d = threadIdx.x; d < kDig; d += kPT) {
-      int sum = 0;
+    // every lane reads the count before the group's first lane adds to it
+    // (one wavefront's LDS operations execute in order)
+    const int old = act ? cnt[wid][dg] : 0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (act && rank_w == 0) cnt[wid][dg] = old + __popcll(same);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    rk[r] = old + rank_w;
+  }
+  __syncthreads();
+  {
+    // digit d's items start at the total of the smaller digits; wavefront w's
+    // after those of the wavefronts before it.  Each thread owns kDPT digits.
+    int c[kDPT][W], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kDPT; ++k) {
+      const int d = threadIdx.x * kDPT + k;
 #pragma unroll
       for (int w = 0; w < W; ++w) {
-        sum += wcnt[w][d];
-        wcnt[w][d] = 0;
+        c[k][w] = cnt[w][d];
+        sum += c[k][w];
       }
-      run[d] += sum;
     }
-    __syncthreads();
+    int tot;
+    int pre = blk_excl<int>(sum, &tot, sw);  // barriers: every count read above
+#pragma unroll
+    for (int k = 0; k < kDPT; ++k) {
+      const int d = threadIdx.x * kDPT + k;
+      gbase[d] = ts.sb + (hs[kDig * ts.f0 + (int64_t)d * ts.nt + (t - ts.f0)] - seg0) - pre;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        cnt[w][d] = pre;
+        pre += c[k][w];
+      }
+    }
   }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kPR; ++r) {
+    const int64_t p = q0 + r * kWave + lane();
+    if (p < ts.hi) {
+      const int dg = (int)((kr[r] >> shift) & mask);
+      const int q = cnt[wid][dg] + rk[r];
+      sk[q] = kr[r];
+      sv[q] = vr[r];
+    }
+  }
+  __syncthreads();
   const int m = (int)(ts.hi - ts.lo);
   for (int j = threadIdx.x; j < m; j += kPT) {
     const K key = sk[j];
