@@ -123,10 +123,9 @@ constexpr int kRadixBits = 9;            // digits of at most 9 bits
 constexpr int kDig = 1 << kRadixBits;    // 512 digit values
 constexpr int kDPT = kDig / kPT;         // digits per thread
 
-// hist: scan layout (segment, digit, tile); tcnt: the tile's own digit counts.
+// hist: scan layout (segment, digit, tile) over the pass's 2^bits digits.
 template <class K>
-__global__ __launch_bounds__(kPT) void k_rs_hist(const K *keys, RsSeg g, int shift, int bits, int64_t *hist,
-                                                 int32_t *tcnt) {
+__global__ __launch_bounds__(kPT) void k_rs_hist(const K *keys, RsSeg g, int shift, int bits, int64_t *hist) {
   __shared__ int h[kDig];
   const int64_t t = blockIdx.x;
   const TileSpan ts = tile_span(g, t);
@@ -144,10 +143,8 @@ __global__ __launch_bounds__(kPT) void k_rs_hist(const K *keys, RsSeg g, int shi
   for (int r = 0; r < kPR; ++r)
     if (ts.lo + r * kPT + threadIdx.x < ts.hi) atomicAdd(&h[(int)((kr[r] >> shift) & mask)], 1);
   __syncthreads();
-  for (int d = threadIdx.x; d < kDig; d += kPT) {
-    hist[kDig * ts.f0 + (int64_t)d * ts.nt + (t - ts.f0)] = h[d];
-    tcnt[t * kDig + d] = h[d];
-  }
+  const int nd = 1 << bits;
+  for (int d = threadIdx.x; d < nd; d += kPT) hist[nd * ts.f0 + (int64_t)d * ts.nt + (t - ts.f0)] = h[d];
 }
 
 // Each tile ranks its items stably by digit into a local digit-sorted copy in
@@ -160,8 +157,7 @@ __global__ __launch_bounds__(kPT) void k_rs_hist(const K *keys, RsSeg g, int shi
 // (wavefront, round, lane), which is their order in the tile: stable.
 template <class K, class V>
 __global__ __launch_bounds__(kPT) void k_rs_scatter(const K *ki, const V *vi, K *ko, V *vo, RsSeg g, int shift,
-                                                    int bits, const int64_t *hs, const int32_t *tcnt) {
-  (void)tcnt;
+                                                    int bits, const int64_t *hs) {
   constexpr int W = kPT / kWave;
   constexpr int QW = kPTile / W;  // items per wavefront
   __shared__ K sk[kPTile];
@@ -171,7 +167,8 @@ __global__ __launch_bounds__(kPT) void k_rs_scatter(const K *ki, const V *vi, K 
   __shared__ int sw[W];
   const int64_t t = blockIdx.x;
   const TileSpan ts = tile_span(g, t);
-  const int64_t seg0 = hs[kDig * ts.f0];
+  const int nd = 1 << bits;
+  const int64_t seg0 = hs[nd * ts.f0];
   const int wid = (int)threadIdx.x / kWave;
   for (int d = threadIdx.x; d < kDig; d += kPT) {
 #pragma unroll
@@ -233,7 +230,7 @@ __global__ __launch_bounds__(kPT) void k_rs_scatter(const K *ki, const V *vi, K 
 #pragma unroll
     for (int k = 0; k < kDPT; ++k) {
       const int d = threadIdx.x * kDPT + k;
-      gbase[d] = ts.sb + (hs[kDig * ts.f0 + (int64_t)d * ts.nt + (t - ts.f0)] - seg0) - pre;
+      if (d < nd) gbase[d] = ts.sb + (hs[nd * ts.f0 + (int64_t)d * ts.nt + (t - ts.f0)] - seg0) - pre;
 #pragma unroll
       for (int w = 0; w < W; ++w) {
         cnt[w][d] = pre;
@@ -267,7 +264,7 @@ int rs_passes(int bits) { return bits <= 0 ? 0 : (bits + kRadixBits - 1) / kRadi
 
 size_t rs_tmp_bytes(int64_t ntiles) {
   const int64_t nh = (int64_t)kDig * std::max<int64_t>(ntiles, 1);
-  return (size_t)nh * (sizeof(int64_t) + sizeof(int32_t)) + scan_bytes(nh, sizeof(int64_t));
+  return (size_t)nh * sizeof(int64_t) + scan_bytes(nh, sizeof(int64_t));
 }
 
 template <class K, class V>
@@ -275,19 +272,19 @@ int rsort(K *k0, V *v0, K *k1, V *v1, const RsSeg &g, int bits, void *tmp, hipSt
   const int np = rs_passes(bits);
   if (np == 0 || g.ntiles <= 0) return 0;
   const int wd = (bits + np - 1) / np;
-  const int64_t nh = (int64_t)kDig * g.ntiles;
+  const int64_t nhmax = (int64_t)kDig * g.ntiles;
   int64_t *hist = (int64_t *)tmp;
-  int32_t *tcnt = (int32_t *)(hist + nh);
-  int64_t *stmp = (int64_t *)(tcnt + nh);
+  int64_t *stmp = hist + nhmax;
   K *ks = k0, *kd = k1;
   V *vs = v0, *vd = v1;
   int shift = 0;
   for (int p = 0; p < np; ++p) {
     const int b = std::min(wd, bits - shift);
-    hipLaunchKernelGGL((k_rs_hist<K>), (int)g.ntiles, kPT, 0, s, (const K *)ks, g, shift, b, hist, tcnt);
+    const int64_t nh = ((int64_t)1 << b) * g.ntiles;
+    hipLaunchKernelGGL((k_rs_hist<K>), (int)g.ntiles, kPT, 0, s, (const K *)ks, g, shift, b, hist);
     scan_rec<int64_t, int64_t>(hist, hist, nh, stmp, s);
     hipLaunchKernelGGL((k_rs_scatter<K, V>), (int)g.ntiles, kPT, 0, s, (const K *)ks, (const V *)vs, kd, vd, g,
-                       shift, b, (const int64_t *)hist, (const int32_t *)tcnt);
+                       shift, b, (const int64_t *)hist);
     std::swap(ks, kd);
     std::swap(vs, vd);
     shift += b;
