@@ -67,7 +67,7 @@ BYTES_PER_UNIT = {  # (per entry, per vertex)
     "refine_sweep": (16.0, 45.0),
 }
 PROF_KERNEL_NAMES = {  # symbol of each timed kernel, as rocprofv3 lists it
-    "hub_gather": "lk::k_hub_gather(lk::MoveArgs)",
+    "hub_gather": "hub slices region (k_hub_*)",
     "agg_merge": "aggregation region (k_agg_*, k_rs_*, k_scan_*)",
     "mod_scan": "lk::k_mod_intra",
     "batch_merge": "lk::k_batch_apply_old(lk::BatchArgs)",
@@ -353,7 +353,9 @@ def main() -> int:
     del off, idx, w
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats()
     r = run_stream(L, torch, h, batches, args.warmup, args.steps, args.mode, args.static_reps, "main")
+    peak_gb = torch.cuda.max_memory_allocated() / 1e9  # the library allocates through torch's allocator
     del h, batches
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
@@ -362,9 +364,9 @@ def main() -> int:
     entries = float(np.mean(r["ents"]))
     value = entries / (ms_per_step / 1e3)
     prof = r["prof"]
-    # the aggregation is timed as one region of several kernels, so the
-    # roofline names the dominant single kernel among the others
-    dom = max((k for k in prof if k != "agg_merge"), key=lambda k: prof[k]["ms"])
+    # the aggregation and the hub slices are timed as regions of several
+    # kernels, so the roofline names the dominant single kernel among the others
+    dom = max((k for k in prof if k not in ("agg_merge", "hub_gather")), key=lambda k: prof[k]["ms"])
     pd = prof[dom]
     roofline = None
     if pd["launches"] > 0 and pd["ms"] > 0:
@@ -467,6 +469,7 @@ def main() -> int:
         "static_ms": {"p50": round(pct(r["static_ms"], 50), 3), "reps": len(r["static_ms"])},
         "speedup_vs_static": ratio(pct(r["static_ms"], 50), pct(lat, 50)),
         "passes": r["passes"],
+        "peak_device_memory_gb": round(peak_gb, 1),
         "modularity": {"update_last": r["qs"][-1], "update_last5_mean": r["q_tail"],
                        "static_final_graph": r["q_static_final"], "static_final_mean": r["q_static_mean"],
                        "dq_update_vs_static": r["q_tail"] - r["q_static_mean"], "static_initial": r["q_static0"]},

@@ -110,9 +110,11 @@ typedef struct {
 #define LEIDEN_MAX_PASSES 64
 
 /* Kernels timed when leiden_params.profile = 1 (index into leiden_stats.prof_*):
- *   HUB_GATHER  - local-moving edge scan of the hubs (degree > hub_degree; one
- *                 launch per slice and iteration with hubs in the frontier);
- *                 entries = edges scanned;
+ *   HUB_GATHER  - local moving of the hubs (degree > hub_degree): asynchronous
+ *                 mode, every slice of an iteration (gather, score and apply
+ *                 kernels) timed as one region; synchronous mode, the gather
+ *                 launch of each slice with hubs; entries = edges scanned by
+ *                 the gathers;
  *   AGG_MERGE   - the aggregation of a level up to its row lengths (several
  *                 kernels, timed as one region per aggregated level);
  *                 entries = level CSR entries, vertices = level vertices;

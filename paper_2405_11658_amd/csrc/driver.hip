@@ -854,6 +854,8 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
     for (int it = 0; it < p.max_iter; ++it) {
       reset_iter(counts, NS * kNB, &sc->gain, &sc->moves, async ? &sc->anext : nullptr, x.s);
       if (gi) x.zero(gi, nl);
+      // asynchronous mode: the hub slices of the iteration timed as one region
+      hipEvent_t th = (x.kp && async && hh.nhub > 0) ? x.kp->begin() : nullptr;
       for (int sl = 0; sl < NS; ++sl) {
         ma.s = sl;
         ma.vbeg = B.soff[sl];
@@ -864,9 +866,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
         if (async) {
           // hubs: synchronous among the hubs of the slice; the rest below
           if (ma.hend == ma.hbeg) continue;
-          hipEvent_t t0 = x.kp ? x.kp->begin() : nullptr;
           move_hub_gather(ma, x.s);
-          if (x.kp) x.kp->end(t0, LEIDEN_PROF_HUB_GATHER, 0, 0);
           move_hub_score(ma, x.s);
           move_apply_bucket(ma, B.region.data(), kNB - 1, x.s);
           continue;
@@ -881,6 +881,7 @@ void run_core(Ctx &x, const leiden_params &p, const Level &g0, double M2, bool t
         }
         move_apply(ma, B.region.data(), x.s);
       }
+      if (th) x.kp->end(th, LEIDEN_PROF_HUB_GATHER, 0, 0);
       if (async) {
         // after the hubs: the other vertices then see the hubs' new communities
         hipEvent_t t0 = x.kp ? x.kp->begin() : nullptr;
