@@ -97,26 +97,48 @@ __global__ __launch_bounds__(256) void k_batch_apply_old(BatchArgs a) {
   const int64_t q0 = (int64_t)blockIdx.x * kChunk;
   const int len = (int)min((int64_t)kChunk, a.nnz - q0);
   chunk_rows<kChunk>(a.off, q0, len, a.crow[blockIdx.x], a.crow[blockIdx.x + 1], rowof, sh);
-  for (int t = threadIdx.x; t < len; t += blockDim.x) {
-    const int r = rowof[t];
+  // the thread's entries in two rounds of loads, each round's loads issued
+  // together: ids, weights and the rows' batch counts and offsets; then the
+  // places (a binary search in the row's sorted batch entries where it has
+  // any) and the stores
+  constexpr int PER = kChunk / 256;
+  int x[PER], bc[PER], r[PER];
+  float wv[PER];
+  int64_t base[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int t = threadIdx.x + k * 256;
+    x[k] = 0;
+    bc[k] = 0;
+    r[k] = 0;
+    wv[k] = 0.0f;
+    base[k] = 0;
+    if (t < len) {
+      r[k] = rowof[t];
+      x[k] = a.idx[q0 + t];
+      wv[k] = a.w[q0 + t];
+      bc[k] = a.bcnt[r[k]];
+      base[k] = a.newoff[r[k]] - a.off[r[k]];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int t = threadIdx.x + k * 256;
+    if (t >= len) continue;
     const int64_t q = q0 + t;
-    const int x = a.idx[q];
-    int64_t pos;
-    const int bc = a.bcnt[r];
-    if (bc == 0) {
-      pos = a.newoff[r] + (q - a.off[r]);
-    } else {
-      const int64_t s0 = a.bstart[r];
-      const int64_t s1 = s0 + bc;
-      const unsigned long long key = ((unsigned long long)(uint32_t)r << 32) | (uint32_t)x;
+    int64_t pos = base[k] + q;
+    if (bc[k] != 0) {
+      const int64_t s0 = a.bstart[r[k]];
+      const int64_t s1 = s0 + bc[k];
+      const unsigned long long key = ((unsigned long long)(uint32_t)r[k] << 32) | (uint32_t)x[k];
       const int64_t p = lower_bound_u64(a.skeys, s0, s1, key);
       if (p < s1 && a.skeys[p] == key) continue;  // deleted
       const int64_t dl = a.delpre[p] - a.delpre[s0];
       const int64_t il = (p - s0) - dl;
-      pos = a.newoff[r] + (q - a.off[r]) - dl + il;
+      pos += il - dl;
     }
-    a.nidx[pos] = x;
-    a.nw[pos] = a.w[q];
+    a.nidx[pos] = x[k];
+    a.nw[pos] = wv[k];
   }
 }
 
