@@ -157,3 +157,42 @@ def test_async_one_wavefront_is_the_serial_oracle(name, g):
         assert st["move_iters"] == ost["move_iters"] and st["moves_pass0"] == ost["moves_pass0"]
         assert st["affected"] == ost["affected"] and st["changed"] == ost["changed"]
         say(name, mode, "one-wavefront update equals the serial oracle")
+
+
+def test_async_edgeless_vertices_stay_alone():
+    """As many vertices without edges as with (ids interleaved): the
+    asynchronous mode leaves the edgeless ones out of the aggregated levels,
+    so each ends alone under a label of its own, the statistics still count
+    them on every level, and the modularity, K, Sigma and 2m match the
+    oracle's for the returned membership (the first-level modularity path
+    included).  A DF update that connects some of them then treats them like
+    any vertex, and the others stay alone."""
+    base = gen.planted_partition(2048, 32, 0.1, 0.002, seed=7, permute=True)
+    n = 2 * base.n
+    src = np.repeat(np.arange(base.n, dtype=np.int64), np.diff(base.off))
+    g = gen.from_edges(n, 2 * src, 2 * base.idx.astype(np.int64), base.w)
+    iso = np.arange(1, n, 2)
+    assert np.all(np.diff(g.off)[iso] == 0)
+    h = L.leiden_create(g.off, g.idx, g.w)
+    say("async static, planted 2048 + 2048 edgeless")
+    C, q, st = L.leiden_static(h)
+    _check_state(h, g, C, q)
+    C = to_np(C)
+    assert len(np.unique(C[iso])) == len(iso)
+    assert not np.isin(C[iso], C[0::2]).any()
+    assert st["level_vertices"][0] == n
+    assert st["passes"] > 1 and st["level_vertices"][1] >= len(iso) + 1
+    ost, _ = oracle.static(og(g))
+    qa = oracle.modularity(og(g), ost.C)
+    say("edgeless: Q", q, "oracle", qa, "levels", st["level_vertices"][:st["passes"]])
+    assert q - qa >= -5e-3
+    rng = np.random.default_rng(3)
+    a = rng.choice(iso, 64, replace=False).astype(np.int32)
+    b = rng.choice(np.arange(0, n, 2), 64, replace=False).astype(np.int32)
+    batch = gen.UBatch(np.zeros(0, np.int32), np.zeros(0, np.int32), a, b, np.ones(64, np.float32))
+    C2, q2, st2, _ = L.leiden_update(h, dev_batch(batch), "df")
+    _check_state(h, _graph_of(h), C2, q2)
+    C2 = to_np(C2)
+    rest = np.setdiff1d(iso, a)
+    assert len(np.unique(C2[rest])) == len(rest)
+    assert not np.isin(C2[rest], np.delete(C2, rest)).any()
