@@ -660,7 +660,7 @@ Level aggregate_level(Ctx &x, const Level &g, const int32_t *C, int64_t ncomm, i
       scan_i64(x, ltn, ltn, nl + 1);
       ntl = x.read(&ltn[nl]);
       tseg = x.get<int32_t>(A_tseg, ntl);
-      agg_tile_seg(ltn, nl, tseg, x.s);
+      agg_tile_seg(ltn, nl, ntl, tseg, x.s);
       RsSeg rs;
       rs.ntiles = ntl;
       rs.n = 0;

@@ -472,9 +472,19 @@ __global__ void k_agg_llist(const int64_t *seg, int64_t ncomm, const int32_t *fl
     ltn[l] = ceil_div(seg[c + 1] - seg[c], kPTile);
   }
 }
-__global__ void k_agg_tseg(const int64_t *tfirst, int64_t nl, int32_t *tseg) {
-  for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < nl; l += (int64_t)gridDim.x * blockDim.x)
-    for (int64_t t = tfirst[l]; t < tfirst[l + 1]; ++t) tseg[t] = (int32_t)l;
+// tseg[t] = the large segment of tile t: one thread per tile, a binary search
+// in the segments' first tiles (strictly increasing; a thread per segment
+// left the giant segment's hundreds of thousands of tiles to one thread).
+__global__ void k_agg_tseg(const int64_t *tfirst, int64_t nl, int64_t ntl, int32_t *tseg) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < ntl; t += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = nl;  // tfirst[lo] <= t < tfirst[hi]
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (tfirst[mid] <= t) lo = mid;
+      else hi = mid;
+    }
+    tseg[t] = (int32_t)lo;
+  }
 }
 void agg_large_list(const int64_t *seg, int64_t ncomm, int32_t *flag, const int32_t *lidx, int32_t *lc, int64_t *lsb,
                     int64_t *lse, int64_t *ltn, hipStream_t s) {
@@ -484,8 +494,8 @@ void agg_large_list(const int64_t *seg, int64_t ncomm, int32_t *flag, const int3
 void agg_large_flags(const int64_t *seg, int64_t ncomm, int32_t *flag, hipStream_t s) {
   hipLaunchKernelGGL(k_agg_lflag, flat_grid(ncomm + 1), 256, 0, s, seg, ncomm, flag);
 }
-void agg_tile_seg(const int64_t *tfirst, int64_t nl, int32_t *tseg, hipStream_t s) {
-  if (nl > 0) hipLaunchKernelGGL(k_agg_tseg, flat_grid(nl), 256, 0, s, tfirst, nl, tseg);
+void agg_tile_seg(const int64_t *tfirst, int64_t nl, int64_t ntl, int32_t *tseg, hipStream_t s) {
+  if (nl > 0 && ntl > 0) hipLaunchKernelGGL(k_agg_tseg, flat_grid(ntl), 256, 0, s, tfirst, nl, ntl, tseg);
 }
 
 // Runs of equal neighbours in the sorted large segments.  A segmented

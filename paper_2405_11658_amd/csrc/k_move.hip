@@ -371,17 +371,40 @@ __global__ __launch_bounds__(256) void k_hub_final(MoveArgs a) {
 }
 
 // ---- hub plan -------------------------------------------------------------------
-__global__ void k_hub_find(const int64_t *off, int64_t n, int S, int64_t hubdeg, const int32_t *hub_soff,
-                           int32_t *hub_fill, int32_t *hubv) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+// Each workgroup takes a contiguous range of vertices, counts its hubs per
+// slice in LDS, reserves each slice's places with one global atomic and then
+// writes them: one atomic per workgroup and slice instead of one per hub (a
+// level has up to millions of hubs but only S counters, and device-scope
+// atomics on one address are performed one after another).  S <= 256.
+constexpr int kHubFindBlocks = 1024;
+__global__ __launch_bounds__(256) void k_hub_find(const int64_t *off, int64_t n, int S, int64_t hubdeg,
+                                                  const int32_t *hub_soff, int32_t *hub_fill, int32_t *hubv) {
+  __shared__ int cnt[256];
+  __shared__ int base[256];
+  const int64_t per = ceil_div(n, (int64_t)gridDim.x);
+  const int64_t v0 = (int64_t)blockIdx.x * per;
+  const int64_t v1 = min(v0 + per, n);
+  for (int k = threadIdx.x; k < S; k += blockDim.x) cnt[k] = 0;
+  __syncthreads();
+  for (int64_t i = v0 + threadIdx.x; i < v1; i += blockDim.x)
+    if (off[i + 1] - off[i] > hubdeg) atomicAdd(&cnt[slice_of(i, S)], 1);
+  __syncthreads();
+  for (int k = threadIdx.x; k < S; k += blockDim.x) {
+    base[k] = cnt[k] ? atomicAdd(&hub_fill[k], cnt[k]) : 0;
+    cnt[k] = 0;
+  }
+  __syncthreads();
+  for (int64_t i = v0 + threadIdx.x; i < v1; i += blockDim.x) {
     if (off[i + 1] - off[i] <= hubdeg) continue;
     const int sl = slice_of(i, S);
-    hubv[hub_soff[sl] + atomicAdd(&hub_fill[sl], 1)] = (int32_t)i;
+    hubv[hub_soff[sl] + base[sl] + atomicAdd(&cnt[sl], 1)] = (int32_t)i;
   }
 }
 void hub_find(const int64_t *off, int64_t n, int S, int64_t hubdeg, const int32_t *hub_soff, int32_t *hub_fill,
               int32_t *hubv, hipStream_t s) {
-  if (n > 0) hipLaunchKernelGGL(k_hub_find, flat_grid(n), 256, 0, s, off, n, S, hubdeg, hub_soff, hub_fill, hubv);
+  if (n > 0)
+    hipLaunchKernelGGL(k_hub_find, (int)std::min<int64_t>(kHubFindBlocks, ceil_div(n, (int64_t)256)), 256, 0, s,
+                       off, n, S, hubdeg, hub_soff, hub_fill, hubv);
 }
 
 __global__ void k_hub_sizes(const int64_t *off, const int32_t *hubv, int64_t nhub, int64_t *nch, int64_t *ncap,

@@ -311,7 +311,7 @@ void agg_small(const int64_t *seg, int64_t ncomm, const uint32_t *gkey, const fl
 void agg_large_flags(const int64_t *seg, int64_t ncomm, int32_t *flag, hipStream_t s);
 void agg_large_list(const int64_t *seg, int64_t ncomm, int32_t *flag, const int32_t *lidx, int32_t *lc, int64_t *lsb,
                     int64_t *lse, int64_t *ltn, hipStream_t s);
-void agg_tile_seg(const int64_t *tfirst, int64_t nl, int32_t *tseg, hipStream_t s);
+void agg_tile_seg(const int64_t *tfirst, int64_t nl, int64_t ntl, int32_t *tseg, hipStream_t s);
 void agg_large_runs(int pass, const uint32_t *gkey, const float *gval, const RsSeg &g, int64_t *hc, double *tin,
                     uint32_t *ukey, float *uval, double *l64, double *tks, hipStream_t s);
 void agg_large_rows(int64_t nl, const int32_t *lc, const int64_t *tfirst, const int64_t *hc, const double *tks,
